@@ -1,0 +1,187 @@
+/*
+ * hmps.h -- C ABI of the MI355X (gfx950) library for the hot path of the
+ * hybrid purification/sampling method for thermal quantum systems
+ * (J. Chen and E.M. Stoudenmire, arXiv:1910.09142).
+ *
+ * The library evolves a batch of independent hybrid METTS-ancilla Markov
+ * chains.  Each chain is a matrix product state (MPS) whose cluster sites
+ * are physical-ancilla Bell pairs and whose environment sites are a sampled
+ * product state (Hybrid METTS-Ancilla subsection, steps 1-4 of the Markov
+ * Chain Sampling Algorithm).  All numerical work runs in hand-written HIP
+ * kernels on the device selected at create time.
+ *
+ * Conventions used by every call
+ *   - Spin-1 sites, physical dimension d = 3, local basis ordered
+ *     m = +1, 0, -1 (S^z eigenbasis).  Product-state outcome labels 0,1,2
+ *     denote the eigenvalues +1, 0, -1 of S^z (basis 0) or S^x (basis 1).
+ *   - MPS layout: physical sites in the order mps_order; every cluster
+ *     physical site is immediately followed by its ancilla partner (Ancilla
+ *     Method subsection; Fig. "initial").  "Environment positions" are the
+ *     MPS positions of non-cluster physical sites, ascending.
+ *   - Ownership: the caller owns every host array (read during the call or
+ *     written before it returns) and the device workspace it passes to
+ *     hmps_create; the library never allocates device memory.
+ *   - Streams: work is enqueued on the stream given at create time.  Calls
+ *     returning host data synchronise that stream before returning.
+ *   - Errors: no exception crosses the ABI.  HMPS_E_INVALID leaves the
+ *     context unchanged.  HMPS_E_DEVICE and HMPS_E_NUMERIC poison the
+ *     context: only hmps_last_error, hmps_stats and hmps_destroy are
+ *     accepted afterwards.  hmps_last_error explains the last failure.
+ *   - Thread compatibility: one context must not be used by two threads at
+ *     once; distinct contexts are independent.
+ */
+#ifndef HMPS_H
+#define HMPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hmps_ctx hmps_ctx;
+typedef int32_t hmps_status;
+
+#define HMPS_OK 0
+#define HMPS_E_INVALID 1 /* bad argument; context unchanged             */
+#define HMPS_E_NOMEM 2   /* workspace too small for the request         */
+#define HMPS_E_DEVICE 3  /* a HIP call failed                           */
+#define HMPS_E_STATE 4   /* call out of order (e.g. evolve before init) */
+#define HMPS_E_NUMERIC 5 /* SVD did not converge, NaN/Inf, zero norm    */
+
+/* Precision of the theta contraction (the SVD, truncation, norms and all
+ * accumulations are always FP64). */
+#define HMPS_PREC_FP64 0
+#define HMPS_PREC_MIXED_FP32 1
+
+typedef struct {
+  int32_t device;          /* HIP device ordinal                          */
+  void *stream;            /* hipStream_t; NULL = the null stream         */
+  void *workspace;         /* device buffer owned by the caller           */
+  size_t workspace_bytes;  /* its size; see hmps_workspace_bytes          */
+  int32_t max_chains;      /* largest n_chains accepted by init           */
+  int32_t max_sites;       /* largest MPS length (physical + ancilla)     */
+  int32_t chi_cap;         /* largest chi_max accepted by evolve          */
+  int32_t max_bonds;       /* largest number of Hamiltonian bonds         */
+  int32_t precision;       /* HMPS_PREC_*                                 */
+  int32_t max_sweeps;      /* Jacobi sweep cap, 0 = default (30)          */
+  double jacobi_tol;       /* relative orthogonality tolerance, 0 = auto  */
+} hmps_options;
+
+/* Hamiltonian H = sum_b J_b S_{i_b} . S_{j_b} on n_phys spin-1 sites
+ * (Results section: the S=1 Heisenberg ladder is one instance), the
+ * order of the physical sites along the MPS, and the cluster mask (sites
+ * purified by an ancilla; the rest is sampled).  Host arrays, read only
+ * during hmps_init_cluster_env. */
+typedef struct {
+  int32_t n_phys;
+  int32_t n_bonds;
+  const int32_t *bond_i;     /* n_bonds physical ids                       */
+  const int32_t *bond_j;     /* n_bonds physical ids, != bond_i            */
+  const double *bond_J;      /* n_bonds couplings (finite)                 */
+  const int32_t *mps_order;  /* n_phys: a permutation of 0..n_phys-1       */
+  const uint8_t *in_cluster; /* n_phys: 1 = cluster (purified) site        */
+} hmps_lattice;
+
+typedef struct {
+  int64_t updates;          /* two-site updates applied (all chains)     */
+  int64_t gate_updates;     /* of which Hamiltonian gates                */
+  int64_t move_updates;     /* of which orthogonality-centre moves       */
+  int64_t jacobi_sweeps;    /* Jacobi sweeps launched                    */
+  int32_t max_chi;          /* largest bond dimension reached            */
+  int32_t n_chains;
+  int32_t n_sites;
+  int32_t n_env;
+  int64_t sample;           /* index of the current sample               */
+  double discarded_weight;  /* sum of relative discarded weights         */
+  double evolve_seconds;    /* wall time spent in hmps_evolve            */
+} hmps_stats_t;
+
+/* Bytes of device workspace needed for the given capacities. */
+size_t hmps_workspace_bytes(int32_t max_chains, int32_t max_sites,
+                            int32_t chi_cap, int32_t max_bonds);
+
+/* Create a context on opt->device using the caller's workspace.
+ * E_INVALID for bad capacities or a workspace smaller than
+ * hmps_workspace_bytes(...); E_DEVICE if the device is unusable. */
+hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt);
+
+/* Step 1 of the Markov chain (Hybrid METTS-Ancilla subsection; Bell pair
+ * |B_j> = d^{-1/2} sum_s |s>_P |s>_A): build n_chains initial states.
+ * env_state: n_chains x n_env outcome labels (row-major, chain-major) in
+ * `basis`, or NULL to draw each environment site's S^z label uniformly
+ * with Philox4x64-10 (key = (seed, 0), counter = (chain, 0, MPS position,
+ * 0), label = floor(3 u), u = top 53 bits / 2^53).  Resets the sample
+ * counter to 0 and every log-weight to 0.  E_INVALID for a malformed
+ * lattice, a label > 2, or capacities exceeded. */
+hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
+                                  int32_t n_chains, uint64_t seed,
+                                  const uint8_t *env_state, int32_t basis);
+
+/* Step 2: apply (e^{-tau H})^M, M = beta/(2 tau) (Ancilla Method
+ * subsection; M must be an integer to 1e-9, else E_INVALID), as a second-
+ * order Trotter product of two-site gates exp(-(tau/2) J S_i.S_j) applied
+ * with nearest-neighbour swaps, each followed by an SVD truncated to at
+ * most chi_max values with relative discarded weight <= cutoff (Results
+ * section).  The state is renormalised after every gate and ln of its
+ * squared norm is added to the chain's log-weight.  On return the
+ * orthogonality centre is site 0.  E_INVALID: chi_max < 1 or > chi_cap,
+ * cutoff < 0, tau <= 0 with beta > 0.  E_NUMERIC: the Jacobi SVD did not
+ * converge in max_sweeps or produced a non-finite value. */
+hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
+                        int32_t chi_max, double cutoff);
+
+/* Step 3: per-chain Monte Carlo estimators <psi|A|psi> (Markov Chain
+ * Sampling Algorithm, step 3).  Outputs (host, any may be NULL):
+ *   energy  [n_chains]           sum_b J_b <S_i.S_j>
+ *   bond_ss [n_chains * n_bonds] <S_i.S_j> per bond, in lattice order
+ *   logw    [n_chains]           accumulated ln of squared gate norms
+ *   qn      [n_chains]           <sum_phys S^z - sum_ancilla S^z>
+ * Synchronises the stream. */
+hmps_status hmps_measure(hmps_ctx *ctx, double *energy, double *bond_ss,
+                         double *logw, double *qn);
+
+/* Step 4: collapse every environment site in MPS order by a projective
+ * measurement in `basis` (0 = S^z, 1 = S^x), tracing the cluster sites;
+ * outcome of a site = smallest label s with u < cumulative conditional
+ * probability, u from Philox4x64-10 with counter (chain, sample, MPS
+ * position, 1).  Then re-initialise every chain to the new product state
+ * (in `basis`) with fresh Bell pairs and advance the sample counter.
+ * env_out (host, may be NULL): n_chains x n_env labels.  Synchronises. */
+hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
+                                   uint8_t *env_out);
+
+/* Counters since init. */
+hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out);
+
+/* Bond dimensions chi[c][b], b = 0..n_sites, of every chain (host array
+ * of n_chains * (n_sites + 1) int32).  Synchronises. */
+hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi);
+
+/* Destroy a context (NULL is accepted).  Does not free the workspace. */
+void hmps_destroy(hmps_ctx *ctx);
+
+/* Text of the last error on this context ("" if none); static storage
+ * owned by the context. */
+const char *hmps_last_error(const hmps_ctx *ctx);
+
+/* ---- host-only helpers (no device work) -------------------------------
+ * The 9x9 gate exp(-x J S_1.S_2), index (s1,s2) -> 3 s1 + s2, row-major,
+ * written into out[81] (spectral form with the three total-spin
+ * projectors; Results section Hamiltonian, d = 3). */
+hmps_status hmps_gate(double J, double x, double *out);
+
+/* The update list of one Trotter step for `lat`: entries (k, op), k the
+ * left MPS site, op >= 0 an index into the distinct couplings (in order
+ * of first appearance in the bond list) or -1 for a swap.  Writes
+ * *n_sites, *n_updates and, when the arrays are not NULL and cap >=
+ * *n_updates, the entries. */
+hmps_status hmps_schedule(const hmps_lattice *lat, int32_t *n_sites,
+                          int32_t *n_updates, int32_t *k, int32_t *op,
+                          int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMPS_H */

@@ -1,0 +1,826 @@
+// Host side of the hmps C ABI: validation, the hybrid MPS layout and the
+// Trotter update list, the closed-form gates, the workspace layout, and
+// the orchestration of the gfx950 kernels (kernels.hip).
+//
+// Method: Chen & Stoudenmire, arXiv:1910.09142 -- Hybrid METTS-Ancilla
+// subsection (steps 1-4 of the Markov chain), Ancilla Method subsection
+// (Trotter evolution of physical sites, ancilla interleaving), Results
+// section (S=1 Heisenberg Hamiltonian, second-order Trotter, truncation by
+// relative discarded weight).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hmps.h"
+#include "hmps_internal.h"
+
+using namespace hmps;
+
+namespace {
+
+constexpr int OP_SWAP = -1;
+constexpr int OP_IDENT = -2;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// ---------------------------------------------------------------------
+// two-site gate exp(-x J S_1.S_2): S.S has eigenvalues -2, -1, +1 on total
+// spin 0, 1, 2; the projectors are polynomials of h = S.S.
+// ---------------------------------------------------------------------
+void heisenberg9(double h[81]) {
+  const double r2 = std::sqrt(2.0);
+  double sz[3] = {1.0, 0.0, -1.0};
+  double sp[3][3] = {{0, r2, 0}, {0, 0, r2}, {0, 0, 0}};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) {
+          // <a b| Sz Sz + (S+ S- + S- S+)/2 |c d>
+          double v = (a == c && b == d) ? sz[a] * sz[b] : 0.0;
+          v += 0.5 * (sp[a][c] * sp[d][b] + sp[c][a] * sp[b][d]);
+          h[(a * 3 + b) * 9 + (c * 3 + d)] = v;
+        }
+}
+
+void matmul9(const double *A, const double *B, double *C) {
+  for (int i = 0; i < 9; ++i)
+    for (int j = 0; j < 9; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < 9; ++k) v += A[i * 9 + k] * B[k * 9 + j];
+      C[i * 9 + j] = v;
+    }
+}
+
+void gate9(double J, double x, double *out) {
+  double h[81], h2[81], hp2[81], hm1[81], hp1[81], t[81];
+  heisenberg9(h);
+  for (int i = 0; i < 81; ++i) {
+    const double id = (i % 10 == 0) ? 1.0 : 0.0;
+    hp2[i] = h[i] + 2.0 * id;
+    hm1[i] = h[i] - id;
+    hp1[i] = h[i] + id;
+  }
+  matmul9(h, h, h2);
+  double p0[81], p1[81], p2[81];
+  for (int i = 0; i < 81; ++i) p0[i] = (h2[i] - ((i % 10 == 0) ? 1.0 : 0.0)) / 3.0;
+  matmul9(hp2, hm1, t);
+  for (int i = 0; i < 81; ++i) p1[i] = -0.5 * t[i];
+  matmul9(hp2, hp1, t);
+  for (int i = 0; i < 81; ++i) p2[i] = t[i] / 6.0;
+  const double e0 = std::exp(2.0 * x * J), e1 = std::exp(x * J),
+               e2 = std::exp(-x * J);
+  for (int i = 0; i < 81; ++i) out[i] = e0 * p0[i] + e1 * p1[i] + e2 * p2[i];
+}
+
+void swap9(double *out) {
+  for (int i = 0; i < 81; ++i) out[i] = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) out[(b * 3 + a) * 9 + (a * 3 + b)] = 1.0;
+}
+
+// ---------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11), first output word.
+// ---------------------------------------------------------------------
+uint64_t philox0(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                 uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+    const unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+    const uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    const uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return c0;
+}
+
+// ---------------------------------------------------------------------
+// layout + update list
+// ---------------------------------------------------------------------
+struct Plan {
+  int n_phys = 0, len = 0, n_env = 0, n_bonds = 0;
+  std::vector<int> phys_of_pos, pos_of_phys, is_cluster, is_ancilla,
+      env_index, env_pos;
+  std::vector<double> couplings;       // distinct J, first-appearance order
+  std::vector<int> bond_p, bond_q;     // per lattice bond, p < q
+  std::vector<double> bond_J;
+  std::vector<int> step_k, step_op;    // one Trotter step
+};
+
+std::string validate_and_plan(const hmps_lattice *lat, Plan &P) {
+  if (!lat) return "lattice is NULL";
+  if (lat->n_phys < 1) return "n_phys must be >= 1";
+  if (lat->n_bonds < 0) return "n_bonds must be >= 0";
+  if (lat->n_bonds > 0 && (!lat->bond_i || !lat->bond_j || !lat->bond_J))
+    return "bond arrays are NULL";
+  if (!lat->mps_order || !lat->in_cluster) return "order/cluster arrays NULL";
+  const int n = lat->n_phys;
+  std::vector<int> seen(n, 0);
+  for (int t = 0; t < n; ++t) {
+    const int i = lat->mps_order[t];
+    if (i < 0 || i >= n || seen[i]) return "mps_order is not a permutation";
+    seen[i] = 1;
+  }
+  for (int b = 0; b < lat->n_bonds; ++b) {
+    const int i = lat->bond_i[b], j = lat->bond_j[b];
+    if (i < 0 || i >= n || j < 0 || j >= n || i == j)
+      return "bond endpoints out of range";
+    if (!std::isfinite(lat->bond_J[b])) return "bond coupling is not finite";
+  }
+  P = Plan();
+  P.n_phys = n;
+  P.pos_of_phys.assign(n, -1);
+  for (int t = 0; t < n; ++t) {
+    const int i = lat->mps_order[t];
+    P.pos_of_phys[i] = (int)P.phys_of_pos.size();
+    P.phys_of_pos.push_back(i);
+    P.is_ancilla.push_back(0);
+    P.is_cluster.push_back(lat->in_cluster[i] ? 1 : 0);
+    if (lat->in_cluster[i]) {
+      P.phys_of_pos.push_back(-1);
+      P.is_ancilla.push_back(1);
+      P.is_cluster.push_back(1);
+    }
+  }
+  P.len = (int)P.phys_of_pos.size();
+  P.env_index.assign(P.len, -1);
+  for (int p = 0; p < P.len; ++p)
+    if (!P.is_cluster[p]) {
+      P.env_index[p] = (int)P.env_pos.size();
+      P.env_pos.push_back(p);
+    }
+  P.n_env = (int)P.env_pos.size();
+  P.n_bonds = lat->n_bonds;
+  struct B3 {
+    int p, q, jx;
+  };
+  std::vector<B3> mb;
+  for (int b = 0; b < lat->n_bonds; ++b) {
+    const double J = lat->bond_J[b];
+    int jx = -1;
+    for (size_t t = 0; t < P.couplings.size(); ++t)
+      if (P.couplings[t] == J) jx = (int)t;
+    if (jx < 0) {
+      jx = (int)P.couplings.size();
+      P.couplings.push_back(J);
+    }
+    int p = P.pos_of_phys[lat->bond_i[b]], q = P.pos_of_phys[lat->bond_j[b]];
+    if (p > q) std::swap(p, q);
+    P.bond_p.push_back(p);
+    P.bond_q.push_back(q);
+    P.bond_J.push_back(J);
+    mb.push_back({p, q, jx});
+  }
+  std::stable_sort(mb.begin(), mb.end(), [](const B3 &a, const B3 &b) {
+    return a.p != b.p ? a.p < b.p : a.q < b.q;
+  });
+  // forward half-sweep: bring p next to q by swaps, gate, swap back
+  std::vector<int> hk, hop;
+  for (const B3 &e : mb) {
+    for (int k = e.p; k < e.q - 1; ++k) {
+      hk.push_back(k);
+      hop.push_back(OP_SWAP);
+    }
+    hk.push_back(e.q - 1);
+    hop.push_back(e.jx);
+    for (int k = e.q - 2; k >= e.p; --k) {
+      hk.push_back(k);
+      hop.push_back(OP_SWAP);
+    }
+  }
+  P.step_k = hk;
+  P.step_op = hop;
+  for (int t = (int)hk.size() - 1; t >= 0; --t) {
+    P.step_k.push_back(hk[t]);
+    P.step_op.push_back(hop[t]);
+  }
+  return "";
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------
+struct hmps_ctx {
+  hmps_options opt{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool poisoned = false;
+  bool ready = false;
+  Plan plan;
+  int B = 0;
+  uint64_t seed = 0;
+  int64_t sample = 0;
+  int center = 0;
+  std::vector<int> h_chi;  // [B][len+1]
+  hmps_stats_t stats{};
+  // device buffers (carved from the workspace)
+  size_t site_cap = 0, chi2 = 0, th_stride = 0;
+  int n_cap = 0, slots = 0;
+  double *d_sites = nullptr, *d_TH = nullptr, *d_X = nullptr,
+         *d_sig2 = nullptr, *d_sig = nullptr, *d_fac = nullptr,
+         *d_logw = nullptr, *d_disc = nullptr, *d_gates = nullptr,
+         *d_envs = nullptr, *d_wsz = nullptr, *d_bscr = nullptr,
+         *d_norm = nullptr, *d_bond_ss = nullptr, *d_energy = nullptr,
+         *d_qn = nullptr, *d_bond_J = nullptr;
+  int32_t *d_chi = nullptr, *d_perm = nullptr, *d_knew = nullptr,
+          *d_rot = nullptr, *d_done = nullptr, *d_err = nullptr,
+          *d_sweeps = nullptr, *d_near = nullptr, *d_bond_p = nullptr,
+          *d_bond_q = nullptr, *d_is_cluster = nullptr,
+          *d_is_ancilla = nullptr, *d_env_index = nullptr;
+  uint8_t *d_labels = nullptr, *d_outcomes = nullptr;
+  // pinned host staging
+  int32_t *h_stage = nullptr;  // 4 * max_chains
+};
+
+namespace {
+
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t count) {
+    T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+    off += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+// Lays out every device buffer; with base == nullptr it only measures.
+size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
+             int chi_cap, int max_bonds) {
+  Carver cv{base};
+  const size_t B = max_chains;
+  const size_t chi2 = (size_t)chi_cap * chi_cap;
+  const size_t site_cap = 3 * chi2;
+  const int mc = 3 * chi_cap;
+  const int n_cap = (mc + 2 * JB - 1) / (2 * JB) * (2 * JB);
+  const size_t th_stride = (size_t)mc * n_cap;
+  const int slots = std::max(2, std::min(std::max(max_bonds, 1), 8));
+  hmps_ctx tmp;
+  hmps_ctx *t = c ? c : &tmp;
+  t->site_cap = site_cap;
+  t->chi2 = chi2;
+  t->th_stride = th_stride;
+  t->n_cap = n_cap;
+  t->slots = slots;
+  t->d_sites = cv.take<double>(B * max_sites * site_cap);
+  t->d_chi = cv.take<int32_t>(B * (max_sites + 1));
+  t->d_TH = cv.take<double>(B * th_stride);
+  t->d_X = cv.take<double>(B * th_stride);
+  t->d_sig2 = cv.take<double>(B * n_cap);
+  t->d_sig = cv.take<double>(B * n_cap);
+  t->d_perm = cv.take<int32_t>(B * n_cap);
+  t->d_knew = cv.take<int32_t>(B);
+  t->d_err = cv.take<int32_t>(B);
+  t->d_rot = cv.take<int32_t>(B);
+  t->d_done = cv.take<int32_t>(B);
+  t->d_sweeps = cv.take<int32_t>(B);
+  t->d_near = cv.take<int32_t>(B);
+  t->d_fac = cv.take<double>(B);
+  t->d_logw = cv.take<double>(B);
+  t->d_disc = cv.take<double>(B);
+  t->d_norm = cv.take<double>(B);
+  t->d_energy = cv.take<double>(B);
+  t->d_qn = cv.take<double>(B);
+  t->d_gates = cv.take<double>((size_t)(max_bonds + 2) * 81);
+  t->d_envs = cv.take<double>(B * (max_sites + 1) * chi2);
+  t->d_wsz = cv.take<double>(B * max_sites);
+  t->d_bscr = cv.take<double>(B * slots * 4 * chi2);
+  t->d_bond_ss = cv.take<double>(B * std::max(max_bonds, 1));
+  t->d_bond_J = cv.take<double>(std::max(max_bonds, 1));
+  t->d_bond_p = cv.take<int32_t>(std::max(max_bonds, 1));
+  t->d_bond_q = cv.take<int32_t>(std::max(max_bonds, 1));
+  t->d_is_cluster = cv.take<int32_t>(max_sites);
+  t->d_is_ancilla = cv.take<int32_t>(max_sites);
+  t->d_env_index = cv.take<int32_t>(max_sites);
+  t->d_labels = cv.take<uint8_t>(B * max_sites);
+  t->d_outcomes = cv.take<uint8_t>(B * max_sites);
+  return cv.off;
+}
+
+hmps_status fail(hmps_ctx *c, hmps_status st, const std::string &msg) {
+  if (c) {
+    c->err = msg;
+    if (st == HMPS_E_DEVICE || st == HMPS_E_NUMERIC) c->poisoned = true;
+  }
+  return st;
+}
+
+#define HIPCHK(call)                                                       \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail(ctx, HMPS_E_DEVICE,                                      \
+                  std::string(#call) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+Batch batch_of(hmps_ctx *ctx) {
+  Batch b;
+  b.sites = ctx->d_sites;
+  b.chi = ctx->d_chi;
+  b.nsites = ctx->plan.len;
+  b.site_cap = ctx->site_cap;
+  b.B = ctx->B;
+  return b;
+}
+
+UpdScratch scratch_of(hmps_ctx *ctx) {
+  UpdScratch s;
+  s.TH = ctx->d_TH;
+  s.X = ctx->d_X;
+  s.th_stride = ctx->th_stride;
+  s.sig2 = ctx->d_sig2;
+  s.perm = ctx->d_perm;
+  s.sig = ctx->d_sig;
+  s.n_cap = ctx->n_cap;
+  s.knew = ctx->d_knew;
+  s.fac = ctx->d_fac;
+  s.logw = ctx->d_logw;
+  s.discarded = ctx->d_disc;
+  s.rot_cur = ctx->d_rot;
+  s.done = ctx->d_done;
+  s.err = ctx->d_err;
+  s.sweeps = ctx->d_sweeps;
+  return s;
+}
+
+// Host copy of the bond dimensions right after an initialisation.
+void init_host_chi(hmps_ctx *ctx) {
+  const int L = ctx->plan.len;
+  ctx->h_chi.assign((size_t)ctx->B * (L + 1), 1);
+  for (int c = 0; c < ctx->B; ++c)
+    for (int p = 0; p < L; ++p)
+      ctx->h_chi[(size_t)c * (L + 1) + p + 1] =
+          (ctx->plan.is_cluster[p] && !ctx->plan.is_ancilla[p]) ? 3 : 1;
+}
+
+hmps_status check_usable(hmps_ctx *ctx, bool need_init) {
+  if (!ctx) return HMPS_E_INVALID;
+  if (ctx->poisoned)
+    return HMPS_E_STATE;
+  if (need_init && !ctx->ready)
+    return fail(ctx, HMPS_E_STATE, "hmps_init_cluster_env has not been called");
+  return HMPS_OK;
+}
+
+// One two-site update on (k, k+1) for every chain.
+hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
+                      double cutoff) {
+  const int L = ctx->plan.len;
+  int max_chiL = 1, max_chiR = 1;
+  size_t max_mn = 0;
+  int max_nb = 2;
+  for (int c = 0; c < ctx->B; ++c) {
+    const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
+    max_chiL = std::max(max_chiL, row[k]);
+    max_chiR = std::max(max_chiR, row[k + 2]);
+    max_mn = std::max(max_mn, (size_t)(3 * row[k]) * (3 * row[k + 2]));
+    const int n = 3 * row[k + 2];
+    int nb = (n + JB - 1) / JB;
+    nb += nb & 1;
+    max_nb = std::max(max_nb, nb);
+  }
+  const bool is_move = (op == OP_IDENT);
+  UpdParams u;
+  u.k = k;
+  const int ncoup = (int)ctx->plan.couplings.size();
+  u.gate = ctx->d_gates +
+           81 * (op >= 0 ? op : (op == OP_SWAP ? ncoup : ncoup + 1));
+  u.is_gate = op >= 0;
+  u.right = right ? 1 : 0;
+  u.chi_max = is_move ? ctx->opt.chi_cap : chi_max;
+  u.cutoff = is_move ? 0.0 : cutoff;
+  u.tol = ctx->opt.jacobi_tol;
+  u.max_sweeps = ctx->opt.max_sweeps;
+  u.mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32;
+  Batch b = batch_of(ctx);
+  UpdScratch s = scratch_of(ctx);
+  hipStream_t st = ctx->stream;
+  launch_theta(b, s, u, max_chiL, max_chiR, st);
+  if (max_mn <= (size_t)SMALL_LDS) {
+    launch_jacobi_small(b, s, u, st);
+  } else {
+    bool converged = false;
+    for (int sweep = 0; sweep <= ctx->opt.max_sweeps; ++sweep) {
+      launch_jacobi_sweep_begin(s, ctx->B, sweep, st);
+      if (sweep == ctx->opt.max_sweeps) break;
+      for (int r = 0; r < max_nb - 1; ++r)
+        launch_jacobi_round(b, s, u, r, max_nb / 2, st);
+      ctx->stats.jacobi_sweeps += 1;
+      HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_rot,
+                            sizeof(int32_t) * ctx->B, hipMemcpyDeviceToHost,
+                            st));
+      HIPCHK(hipStreamSynchronize(st));
+      bool any = false;
+      for (int c = 0; c < ctx->B; ++c) any |= ctx->h_stage[c] != 0;
+      if (!any) {
+        converged = true;
+        break;
+      }
+    }
+    if (!converged)
+      return fail(ctx, HMPS_E_NUMERIC,
+                  "Jacobi SVD did not converge within max_sweeps");
+  }
+  launch_truncate(b, s, u, st);
+  const int mmax = 3 * max_chiL, nmax = 3 * max_chiR;
+  const int kmax = std::max(1, std::min(u.chi_max, std::min(mmax, nmax)));
+  launch_writeback(b, s, u, mmax, nmax, kmax, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_knew, sizeof(int32_t) * ctx->B,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ctx->h_stage + ctx->opt.max_chains, ctx->d_err,
+                        sizeof(int32_t) * ctx->B, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int c = 0; c < ctx->B; ++c) {
+    if (ctx->h_stage[ctx->opt.max_chains + c])
+      return fail(ctx, HMPS_E_NUMERIC,
+                  "numerical failure in the SVD/truncation of chain " +
+                      std::to_string(c));
+    const int kn = ctx->h_stage[c];
+    ctx->h_chi[(size_t)c * (L + 1) + k + 1] = kn;
+    ctx->stats.max_chi = std::max(ctx->stats.max_chi, kn);
+  }
+  ctx->stats.updates += ctx->B;
+  if (op >= 0) ctx->stats.gate_updates += ctx->B;
+  if (is_move) ctx->stats.move_updates += ctx->B;
+  return HMPS_OK;
+}
+
+hmps_status move_center(hmps_ctx *ctx, int target) {
+  while (ctx->center < target) {
+    hmps_status st = do_update(ctx, ctx->center, OP_IDENT, true, 0, 0.0);
+    if (st) return st;
+    ctx->center += 1;
+  }
+  while (ctx->center > target) {
+    hmps_status st = do_update(ctx, ctx->center - 1, OP_IDENT, false, 0, 0.0);
+    if (st) return st;
+    ctx->center -= 1;
+  }
+  return HMPS_OK;
+}
+
+}  // namespace
+
+// =====================================================================
+// ABI
+// =====================================================================
+extern "C" {
+
+size_t hmps_workspace_bytes(int32_t max_chains, int32_t max_sites,
+                            int32_t chi_cap, int32_t max_bonds) {
+  if (max_chains < 1 || max_sites < 1 || chi_cap < 1 || max_bonds < 0)
+    return 0;
+  return carve(nullptr, nullptr, max_chains, max_sites, chi_cap, max_bonds);
+}
+
+hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
+  if (!out || !opt) return HMPS_E_INVALID;
+  *out = nullptr;
+  // chi_cap >= 3: a Bell pair carries a bond of dimension 3; chi_cap <= 640:
+  // the truncation sorts at most 2048 singular values (3 chi_cap <= 1920)
+  if (opt->max_chains < 1 || opt->max_sites < 1 || opt->chi_cap < 3 ||
+      opt->max_bonds < 0 || opt->chi_cap > 640 ||
+      (opt->precision != HMPS_PREC_FP64 &&
+       opt->precision != HMPS_PREC_MIXED_FP32))
+    return HMPS_E_INVALID;
+  const size_t need = hmps_workspace_bytes(opt->max_chains, opt->max_sites,
+                                           opt->chi_cap, opt->max_bonds);
+  if (!opt->workspace || opt->workspace_bytes < need) return HMPS_E_NOMEM;
+  if (((uintptr_t)opt->workspace) % ALIGN) return HMPS_E_INVALID;
+  hmps_ctx *ctx = new hmps_ctx();
+  ctx->opt = *opt;
+  if (ctx->opt.max_sweeps <= 0) ctx->opt.max_sweeps = 30;
+  if (!(ctx->opt.jacobi_tol > 0.0)) {
+    // relative orthogonality reachable with rounded inner products of
+    // length 3 chi_cap: a few sqrt(m) eps
+    ctx->opt.jacobi_tol = 8.0 * std::sqrt(3.0 * opt->chi_cap) * 2.220446e-16;
+  }
+  ctx->stream = reinterpret_cast<hipStream_t>(opt->stream);
+  hipError_t e = hipSetDevice(opt->device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return HMPS_E_DEVICE;
+  }
+  e = hipHostMalloc((void **)&ctx->h_stage,
+                    sizeof(int32_t) * 4 * opt->max_chains);
+  if (e != hipSuccess) {
+    delete ctx;
+    return HMPS_E_DEVICE;
+  }
+  carve(ctx, reinterpret_cast<char *>(opt->workspace), opt->max_chains,
+        opt->max_sites, opt->chi_cap, opt->max_bonds);
+  *out = ctx;
+  return HMPS_OK;
+}
+
+void hmps_destroy(hmps_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  delete ctx;
+}
+
+const char *hmps_last_error(const hmps_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
+                                  int32_t n_chains, uint64_t seed,
+                                  const uint8_t *env_state, int32_t basis) {
+  hmps_status st = check_usable(ctx, false);
+  if (st) return st;
+  Plan P;
+  std::string why = validate_and_plan(lat, P);
+  if (!why.empty()) return fail(ctx, HMPS_E_INVALID, why);
+  if (n_chains < 1 || n_chains > ctx->opt.max_chains)
+    return fail(ctx, HMPS_E_INVALID, "n_chains outside [1, max_chains]");
+  if (P.len > ctx->opt.max_sites)
+    return fail(ctx, HMPS_E_INVALID, "MPS length exceeds max_sites");
+  if (P.n_bonds > ctx->opt.max_bonds)
+    return fail(ctx, HMPS_E_INVALID, "n_bonds exceeds max_bonds");
+  if (basis != 0 && basis != 1)
+    return fail(ctx, HMPS_E_INVALID, "basis must be 0 or 1");
+  std::vector<uint8_t> labels((size_t)n_chains * std::max(P.n_env, 1), 0);
+  if (env_state) {
+    for (size_t i = 0; i < (size_t)n_chains * P.n_env; ++i) {
+      if (env_state[i] > 2)
+        return fail(ctx, HMPS_E_INVALID, "environment label > 2");
+      labels[i] = env_state[i];
+    }
+  } else {
+    basis = 0;
+    for (int c = 0; c < n_chains; ++c)
+      for (int e = 0; e < P.n_env; ++e) {
+        const uint64_t x = philox0((uint64_t)c, 0, (uint64_t)P.env_pos[e], 0,
+                                   seed, 0);
+        const double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
+        labels[(size_t)c * P.n_env + e] =
+            (uint8_t)std::min(2, (int)std::floor(3.0 * u));
+      }
+  }
+  ctx->plan = P;
+  ctx->B = n_chains;
+  ctx->seed = seed;
+  ctx->sample = 0;
+  ctx->center = 0;
+  ctx->ready = false;
+  std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+  hipStream_t s = ctx->stream;
+  std::vector<int32_t> bp(P.bond_p), bq(P.bond_q);
+  if (P.n_bonds > 0) {
+    HIPCHK(hipMemcpyAsync(ctx->d_bond_p, bp.data(), sizeof(int32_t) * P.n_bonds,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->d_bond_q, bq.data(), sizeof(int32_t) * P.n_bonds,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->d_bond_J, P.bond_J.data(),
+                          sizeof(double) * P.n_bonds, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipMemcpyAsync(ctx->d_is_cluster, P.is_cluster.data(),
+                        sizeof(int32_t) * P.len, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_is_ancilla, P.is_ancilla.data(),
+                        sizeof(int32_t) * P.len, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_env_index, P.env_index.data(),
+                        sizeof(int32_t) * P.len, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_labels, labels.data(), labels.size(),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(ctx->d_disc, 0, sizeof(double) * n_chains, s));
+  HIPCHK(hipMemsetAsync(ctx->d_err, 0, sizeof(int32_t) * n_chains, s));
+  HIPCHK(hipMemsetAsync(ctx->d_sweeps, 0, sizeof(int32_t) * n_chains, s));
+  Batch b = batch_of(ctx);
+  InitArgs ia;
+  ia.is_cluster = ctx->d_is_cluster;
+  ia.is_ancilla = ctx->d_is_ancilla;
+  ia.env_index = ctx->d_env_index;
+  ia.labels = ctx->d_labels;
+  ia.n_env = P.n_env;
+  ia.basis = basis;
+  launch_init(b, ia, ctx->d_logw, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  init_host_chi(ctx);
+  ctx->stats.n_chains = n_chains;
+  ctx->stats.n_sites = P.len;
+  ctx->stats.n_env = P.n_env;
+  ctx->ready = true;
+  return HMPS_OK;
+}
+
+hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
+                        int32_t chi_max, double cutoff) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  if (!(std::isfinite(beta) && beta >= 0.0))
+    return fail(ctx, HMPS_E_INVALID, "beta must be finite and >= 0");
+  if (chi_max < 1 || chi_max > ctx->opt.chi_cap)
+    return fail(ctx, HMPS_E_INVALID, "chi_max outside [1, chi_cap]");
+  if (!(cutoff >= 0.0) || !std::isfinite(cutoff))
+    return fail(ctx, HMPS_E_INVALID, "cutoff must be finite and >= 0");
+  int M = 0;
+  if (beta > 0.0) {
+    if (!(tau > 0.0) || !std::isfinite(tau))
+      return fail(ctx, HMPS_E_INVALID, "tau must be > 0");
+    const double m = beta / (2.0 * tau);
+    M = (int)std::llround(m);
+    if (std::fabs(m - M) > 1e-9 * std::max(1.0, m) || M < 1)
+      return fail(ctx, HMPS_E_INVALID, "beta/(2 tau) must be an integer");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  const Plan &P = ctx->plan;
+  const int ncoup = (int)P.couplings.size();
+  std::vector<double> g((size_t)(ncoup + 2) * 81);
+  for (int j = 0; j < ncoup; ++j) gate9(P.couplings[j], tau / 2.0, &g[81 * j]);
+  swap9(&g[81 * ncoup]);
+  for (int i = 0; i < 81; ++i) g[81 * (ncoup + 1) + i] = (i % 10 == 0) ? 1.0 : 0.0;
+  HIPCHK(hipMemcpyAsync(ctx->d_gates, g.data(), sizeof(double) * g.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  const int steplen = (int)P.step_k.size();
+  const long total = (long)M * steplen;
+  for (long t = 0; t < total; ++t) {
+    const int k = P.step_k[t % steplen], op = P.step_op[t % steplen];
+    const int kn = (t + 1 < total) ? P.step_k[(t + 1) % steplen] : 0;
+    if (ctx->center < k) {
+      st = move_center(ctx, k);
+    } else if (ctx->center > k + 1) {
+      st = move_center(ctx, k + 1);
+    }
+    if (st) return st;
+    const bool right = kn >= k;
+    st = do_update(ctx, k, op, right, chi_max, cutoff);
+    if (st) return st;
+    ctx->center = right ? k + 1 : k;
+  }
+  st = move_center(ctx, 0);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->stats.evolve_seconds +=
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0)
+          .count();
+  return HMPS_OK;
+}
+
+hmps_status hmps_measure(hmps_ctx *ctx, double *energy, double *bond_ss,
+                         double *logw, double *qn) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  if (ctx->center != 0) {
+    st = move_center(ctx, 0);
+    if (st) return st;
+  }
+  const Plan &P = ctx->plan;
+  Batch b = batch_of(ctx);
+  MeasureArgs ma;
+  ma.bond_p = ctx->d_bond_p;
+  ma.bond_q = ctx->d_bond_q;
+  ma.bond_J = ctx->d_bond_J;
+  ma.n_bonds = P.n_bonds;
+  ma.is_ancilla = ctx->d_is_ancilla;
+  ma.envs = ctx->d_envs;
+  ma.wsz = ctx->d_wsz;
+  ma.bond_scratch = ctx->d_bscr;
+  ma.slots = ctx->slots;
+  ma.chi2 = ctx->chi2;
+  ma.norm = ctx->d_norm;
+  ma.bond_ss = ctx->d_bond_ss;
+  hipStream_t s = ctx->stream;
+  launch_measure_envs(b, ma, s);
+  for (int b0 = 0; b0 < P.n_bonds; b0 += ctx->slots)
+    launch_measure_bonds(b, ma, b0, std::min(ctx->slots, P.n_bonds - b0), s);
+  launch_measure_finish(b, ma, ctx->d_energy, ctx->d_qn, s);
+  HIPCHK(hipGetLastError());
+  const size_t B = ctx->B;
+  if (energy)
+    HIPCHK(hipMemcpyAsync(energy, ctx->d_energy, sizeof(double) * B,
+                          hipMemcpyDeviceToHost, s));
+  if (bond_ss && P.n_bonds > 0)
+    HIPCHK(hipMemcpyAsync(bond_ss, ctx->d_bond_ss,
+                          sizeof(double) * B * P.n_bonds,
+                          hipMemcpyDeviceToHost, s));
+  if (logw)
+    HIPCHK(hipMemcpyAsync(logw, ctx->d_logw, sizeof(double) * B,
+                          hipMemcpyDeviceToHost, s));
+  if (qn)
+    HIPCHK(hipMemcpyAsync(qn, ctx->d_qn, sizeof(double) * B,
+                          hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return HMPS_OK;
+}
+
+hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
+                                   uint8_t *env_out) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  if (basis != 0 && basis != 1)
+    return fail(ctx, HMPS_E_INVALID, "basis must be 0 or 1");
+  if (ctx->center != 0) {
+    st = move_center(ctx, 0);
+    if (st) return st;
+  }
+  const Plan &P = ctx->plan;
+  Batch b = batch_of(ctx);
+  hipStream_t s = ctx->stream;
+  CollapseArgs ca;
+  ca.is_cluster = ctx->d_is_cluster;
+  ca.env_index = ctx->d_env_index;
+  ca.n_env = P.n_env;
+  ca.scratch = ctx->d_bscr;
+  ca.chi2 = ctx->chi2;
+  ca.outcomes = ctx->d_outcomes;
+  ca.near = ctx->d_near;
+  ca.basis = basis;
+  ca.seed = ctx->seed;
+  ca.sample = ctx->sample;
+  launch_collapse(b, ca, s);
+  HIPCHK(hipGetLastError());
+  if (env_out && P.n_env > 0)
+    HIPCHK(hipMemcpyAsync(env_out, ctx->d_outcomes,
+                          (size_t)ctx->B * P.n_env, hipMemcpyDeviceToHost, s));
+  InitArgs ia;
+  ia.is_cluster = ctx->d_is_cluster;
+  ia.is_ancilla = ctx->d_is_ancilla;
+  ia.env_index = ctx->d_env_index;
+  ia.labels = ctx->d_outcomes;
+  ia.n_env = P.n_env;
+  ia.basis = basis;
+  launch_init(b, ia, ctx->d_logw, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  init_host_chi(ctx);
+  ctx->center = 0;
+  ctx->sample += 1;
+  ctx->stats.sample = ctx->sample;
+  return HMPS_OK;
+}
+
+hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out) {
+  if (!ctx || !out) return HMPS_E_INVALID;
+  hmps_stats_t s = ctx->stats;
+  if (ctx->ready && !ctx->poisoned) {
+    std::vector<double> disc(ctx->B);
+    std::vector<int32_t> sw(ctx->B);
+    if (hipMemcpy(disc.data(), ctx->d_disc, sizeof(double) * ctx->B,
+                  hipMemcpyDeviceToHost) == hipSuccess &&
+        hipMemcpy(sw.data(), ctx->d_sweeps, sizeof(int32_t) * ctx->B,
+                  hipMemcpyDeviceToHost) == hipSuccess) {
+      s.discarded_weight = 0.0;
+      for (double d : disc) s.discarded_weight += d;
+      for (int32_t v : sw) s.jacobi_sweeps += v;
+    }
+  }
+  *out = s;
+  return HMPS_OK;
+}
+
+hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  if (!chi) return fail(ctx, HMPS_E_INVALID, "chi is NULL");
+  HIPCHK(hipMemcpyAsync(chi, ctx->d_chi,
+                        sizeof(int32_t) * ctx->B * (ctx->plan.len + 1),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HMPS_OK;
+}
+
+hmps_status hmps_gate(double J, double x, double *out) {
+  if (!out || !std::isfinite(J) || !std::isfinite(x)) return HMPS_E_INVALID;
+  gate9(J, x, out);
+  return HMPS_OK;
+}
+
+hmps_status hmps_schedule(const hmps_lattice *lat, int32_t *n_sites,
+                          int32_t *n_updates, int32_t *k, int32_t *op,
+                          int32_t cap) {
+  Plan P;
+  if (!validate_and_plan(lat, P).empty()) return HMPS_E_INVALID;
+  if (n_sites) *n_sites = P.len;
+  if (n_updates) *n_updates = (int32_t)P.step_k.size();
+  if (k && op && cap >= (int32_t)P.step_k.size()) {
+    for (size_t t = 0; t < P.step_k.size(); ++t) {
+      k[t] = P.step_k[t];
+      op[t] = P.step_op[t];
+    }
+  }
+  return HMPS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Internal interface between the host orchestration (hmps.cpp) and the
+// gfx950 kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hmps {
+
+// Jacobi column-block width of the large-matrix SVD path; a block pair is
+// 2*JB columns.
+constexpr int JB = 16;
+// Largest m * n_even (doubles) handled by the single-workgroup SVD whose
+// matrix lives entirely in LDS.
+constexpr int SMALL_LDS = 18432;
+// Relative floor below which a singular value is numerically zero (it is
+// always discarded: its singular vectors are noise).
+constexpr double SIGMA_FLOOR = 1e-13;
+// Relative gap below which neighbouring singular values tie.
+constexpr double TIE_TOL = 1e-8;
+
+// Device view of one batch of chains.  Site p of chain c is the row-major
+// tensor T[s][l][r] (s < 3, l < chi[c][p], r < chi[c][p+1]) stored at
+// sites + (c * nsites + p) * site_cap.
+struct Batch {
+  double *sites;
+  int32_t *chi;       // [B][nsites + 1]
+  int nsites;
+  size_t site_cap;    // doubles per site slot
+  int B;
+};
+
+// Per-chain scratch of one two-site update.  theta' (m x n) is stored
+// column-major twice: TH keeps it, X is rotated by the Jacobi sweeps
+// (n_pad >= n columns, the padding columns are zero).
+struct UpdScratch {
+  double *TH;         // [B][th_stride]
+  double *X;          // [B][th_stride]
+  size_t th_stride;
+  double *sig2;       // [B][n_cap] squared column norms after convergence
+  int32_t *perm;      // [B][n_cap] kept columns, largest singular value first
+  double *sig;        // [B][n_cap] kept singular values (sorted)
+  int n_cap;
+  int32_t *knew;      // [B]
+  double *fac;        // [B] 1/||kept||
+  double *logw;       // [B]
+  double *discarded;  // [B] accumulated relative discarded weight
+  int32_t *rot_cur;   // [B] rotations in the current sweep
+  int32_t *done;      // [B] Jacobi converged
+  int32_t *err;       // [B] nonzero: numerical failure
+  int32_t *sweeps;    // [B] Jacobi sweeps done by the in-LDS path
+};
+
+struct UpdParams {
+  int k;              // left site of the update
+  const double *gate; // 81 doubles on the device (row-major (s1 s2),(t1 t2))
+  int is_gate;        // accumulate ln ||theta'||^2 into logw
+  int right;          // absorb singular values to the right
+  int chi_max;
+  double cutoff;
+  double tol;         // Jacobi relative orthogonality tolerance
+  int max_sweeps;
+  int mixed;          // FP32 contraction
+};
+
+// ---- launchers (kernels.hip) -----------------------------------------
+void launch_theta(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                  int max_chiL, int max_chiR, hipStream_t st);
+void launch_jacobi_small(const Batch &b, const UpdScratch &s,
+                         const UpdParams &u, hipStream_t st);
+void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
+                               hipStream_t st);
+void launch_jacobi_round(const Batch &b, const UpdScratch &s,
+                         const UpdParams &u, int round, int max_pairs,
+                         hipStream_t st);
+void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                     hipStream_t st);
+void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                      int max_m, int max_n, int max_k, hipStream_t st);
+
+struct MeasureArgs {
+  const int32_t *bond_p, *bond_q;  // [n_bonds] MPS positions, p < q
+  const double *bond_J;
+  int n_bonds;
+  const int32_t *is_ancilla;       // [nsites]
+  double *envs;                    // [B][nsites+1][chi_cap^2] left envs
+  double *wsz;                     // [B][nsites] <S^z> per site
+  double *bond_scratch;            // [B][slots][4 chi_cap^2]
+  int slots;
+  size_t chi2;                     // chi_cap^2
+  double *norm;                    // [B]
+  double *bond_ss;                 // [B][n_bonds]
+};
+void launch_measure_envs(const Batch &b, const MeasureArgs &m,
+                         hipStream_t st);
+void launch_measure_bonds(const Batch &b, const MeasureArgs &m, int b0,
+                          int nb, hipStream_t st);
+void launch_measure_finish(const Batch &b, const MeasureArgs &m,
+                           double *energy, double *qn, hipStream_t st);
+
+struct CollapseArgs {
+  const int32_t *is_cluster;  // [nsites]
+  const int32_t *env_index;   // [nsites] index among env sites or -1
+  int n_env;
+  double *scratch;            // [B][8 chi_cap^2]
+  size_t chi2;
+  uint8_t *outcomes;          // [B][n_env]
+  int32_t *near;              // [B] draws within 1e-12 of a threshold
+  int basis;
+  uint64_t seed;
+  int64_t sample;
+};
+void launch_collapse(const Batch &b, const CollapseArgs &a, hipStream_t st);
+
+struct InitArgs {
+  const int32_t *is_cluster;   // [nsites]
+  const int32_t *is_ancilla;   // [nsites]
+  const int32_t *env_index;    // [nsites]
+  const uint8_t *labels;       // [B][n_env]
+  int n_env;
+  int basis;
+};
+void launch_init(const Batch &b, const InitArgs &a, double *logw,
+                 hipStream_t st);
+
+}  // namespace hmps

@@ -1,0 +1,260 @@
+"""Thin ctypes binding of libhmps.so (the C ABI declared in include/hmps.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch supplies the device workspace (one uint8 tensor) and the
+stream; nothing here computes physics.  The binding fails loudly when the
+library is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmps.so")
+
+HMPS_OK = 0
+HMPS_E_INVALID = 1
+HMPS_E_NOMEM = 2
+HMPS_E_DEVICE = 3
+HMPS_E_STATE = 4
+HMPS_E_NUMERIC = 5
+PREC_FP64 = 0
+PREC_MIXED_FP32 = 1
+
+EXPORTS = [
+    "hmps_workspace_bytes", "hmps_create", "hmps_init_cluster_env",
+    "hmps_evolve", "hmps_measure", "hmps_collapse_resample", "hmps_stats",
+    "hmps_bond_dims", "hmps_destroy", "hmps_last_error", "hmps_gate",
+    "hmps_schedule",
+]
+
+
+class hmps_options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("max_chains", C.c_int32), ("max_sites", C.c_int32),
+                ("chi_cap", C.c_int32), ("max_bonds", C.c_int32),
+                ("precision", C.c_int32), ("max_sweeps", C.c_int32),
+                ("jacobi_tol", C.c_double)]
+
+
+class hmps_lattice(C.Structure):
+    _fields_ = [("n_phys", C.c_int32), ("n_bonds", C.c_int32),
+                ("bond_i", C.POINTER(C.c_int32)),
+                ("bond_j", C.POINTER(C.c_int32)),
+                ("bond_J", C.POINTER(C.c_double)),
+                ("mps_order", C.POINTER(C.c_int32)),
+                ("in_cluster", C.POINTER(C.c_uint8))]
+
+
+class hmps_stats_t(C.Structure):
+    _fields_ = [("updates", C.c_int64), ("gate_updates", C.c_int64),
+                ("move_updates", C.c_int64), ("jacobi_sweeps", C.c_int64),
+                ("max_chi", C.c_int32), ("n_chains", C.c_int32),
+                ("n_sites", C.c_int32), ("n_env", C.c_int32),
+                ("sample", C.c_int64), ("discarded_weight", C.c_double),
+                ("evolve_seconds", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libhmps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with "
+            "`python -m paper_1910_09142_amd.build` (no fallback exists)")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    lib.hmps_workspace_bytes.restype = C.c_size_t
+    lib.hmps_workspace_bytes.argtypes = [C.c_int32] * 4
+    lib.hmps_create.argtypes = [P(C.c_void_p), P(hmps_options)]
+    lib.hmps_init_cluster_env.argtypes = [C.c_void_p, P(hmps_lattice),
+                                          C.c_int32, C.c_uint64,
+                                          P(C.c_uint8), C.c_int32]
+    lib.hmps_evolve.argtypes = [C.c_void_p, C.c_double, C.c_double,
+                                C.c_int32, C.c_double]
+    lib.hmps_measure.argtypes = [C.c_void_p] + [P(C.c_double)] * 4
+    lib.hmps_collapse_resample.argtypes = [C.c_void_p, C.c_int32,
+                                           P(C.c_uint8)]
+    lib.hmps_stats.argtypes = [C.c_void_p, P(hmps_stats_t)]
+    lib.hmps_bond_dims.argtypes = [C.c_void_p, P(C.c_int32)]
+    lib.hmps_destroy.argtypes = [C.c_void_p]
+    lib.hmps_destroy.restype = None
+    lib.hmps_last_error.argtypes = [C.c_void_p]
+    lib.hmps_last_error.restype = C.c_char_p
+    lib.hmps_gate.argtypes = [C.c_double, C.c_double, P(C.c_double)]
+    lib.hmps_schedule.argtypes = [P(hmps_lattice), P(C.c_int32),
+                                  P(C.c_int32), P(C.c_int32), P(C.c_int32),
+                                  C.c_int32]
+    for name in ("hmps_create", "hmps_init_cluster_env", "hmps_evolve",
+                 "hmps_measure", "hmps_collapse_resample", "hmps_stats",
+                 "hmps_bond_dims", "hmps_gate", "hmps_schedule"):
+        getattr(lib, name).restype = C.c_int32
+    _lib = lib
+    return lib
+
+
+class HmpsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hmps status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+class Lattice:
+    """Host arrays of an hmps_lattice kept alive with the struct."""
+
+    def __init__(self, n_phys, bonds, order, in_cluster):
+        self.n_phys = int(n_phys)
+        self.bi = np.ascontiguousarray([b[0] for b in bonds], dtype=np.int32)
+        self.bj = np.ascontiguousarray([b[1] for b in bonds], dtype=np.int32)
+        self.bJ = np.ascontiguousarray([b[2] for b in bonds],
+                                       dtype=np.float64)
+        self.order = np.ascontiguousarray(order, dtype=np.int32)
+        self.in_cluster = np.ascontiguousarray(in_cluster, dtype=np.uint8)
+        self.n_bonds = len(bonds)
+        self.c = hmps_lattice(self.n_phys, self.n_bonds,
+                              _ptr(self.bi, C.c_int32),
+                              _ptr(self.bj, C.c_int32),
+                              _ptr(self.bJ, C.c_double),
+                              _ptr(self.order, C.c_int32),
+                              _ptr(self.in_cluster, C.c_uint8))
+
+
+def hmps_workspace_bytes(max_chains, max_sites, chi_cap, max_bonds) -> int:
+    return int(load().hmps_workspace_bytes(max_chains, max_sites, chi_cap,
+                                           max_bonds))
+
+
+def hmps_gate(J: float, x: float) -> np.ndarray:
+    out = np.zeros(81)
+    st = load().hmps_gate(J, x, _ptr(out, C.c_double))
+    if st:
+        raise HmpsError(st, "hmps_gate")
+    return out.reshape(9, 9)
+
+
+def hmps_schedule(lat: Lattice):
+    """(n_sites, [(k, op)] of one Trotter step)."""
+    lib = load()
+    ns, nu = C.c_int32(), C.c_int32()
+    st = lib.hmps_schedule(C.byref(lat.c), C.byref(ns), C.byref(nu), None,
+                           None, 0)
+    if st:
+        raise HmpsError(st, "hmps_schedule")
+    k = np.zeros(nu.value, np.int32)
+    op = np.zeros(nu.value, np.int32)
+    st = lib.hmps_schedule(C.byref(lat.c), C.byref(ns), C.byref(nu),
+                           _ptr(k, C.c_int32), _ptr(op, C.c_int32), nu.value)
+    if st:
+        raise HmpsError(st, "hmps_schedule")
+    return ns.value, list(zip(k.tolist(), op.tolist()))
+
+
+class Context:
+    """One hmps context with a torch-owned device workspace."""
+
+    def __init__(self, max_chains, max_sites, chi_cap, max_bonds,
+                 precision=PREC_FP64, device=0, stream=None, max_sweeps=0,
+                 jacobi_tol=0.0):
+        import torch
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("hmps needs a ROCm GPU (torch.cuda)")
+        self.lib = lib
+        self.device = device
+        nbytes = hmps_workspace_bytes(max_chains, max_sites, chi_cap,
+                                      max_bonds)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
+                                     device=f"cuda:{device}")
+        base = self.workspace.data_ptr()
+        base = (base + 255) // 256 * 256
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        self.opt = hmps_options(device, C.c_void_p(stream.cuda_stream),
+                                C.c_void_p(base), nbytes, max_chains,
+                                max_sites, chi_cap, max_bonds, precision,
+                                max_sweeps, jacobi_tol)
+        h = C.c_void_p()
+        st = lib.hmps_create(C.byref(h), C.byref(self.opt))
+        if st:
+            raise HmpsError(st, "hmps_create")
+        self.h = h
+        self.n_chains = 0
+        self.n_env = 0
+        self.n_bonds = 0
+        self.n_sites = 0
+
+    def _check(self, st, what):
+        if st:
+            msg = self.lib.hmps_last_error(self.h).decode()
+            raise HmpsError(st, f"{what}: {msg}")
+
+    def hmps_init_cluster_env(self, lat: Lattice, n_chains: int, seed: int,
+                              env_state=None, basis: int = 0):
+        self._lat = lat
+        es = None
+        if env_state is not None:
+            env_state = np.ascontiguousarray(env_state, dtype=np.uint8)
+            es = _ptr(env_state, C.c_uint8)
+        self._check(self.lib.hmps_init_cluster_env(
+            self.h, C.byref(lat.c), n_chains, C.c_uint64(seed), es, basis),
+            "hmps_init_cluster_env")
+        self.n_chains = n_chains
+        self.n_bonds = lat.n_bonds
+        s = self.hmps_stats()
+        self.n_env = s.n_env
+        self.n_sites = s.n_sites
+
+    def hmps_evolve(self, beta, tau, chi_max, cutoff):
+        self._check(self.lib.hmps_evolve(self.h, beta, tau, chi_max, cutoff),
+                    "hmps_evolve")
+
+    def hmps_measure(self):
+        B, nb = self.n_chains, self.n_bonds
+        e, lw, qn = np.zeros(B), np.zeros(B), np.zeros(B)
+        ss = np.zeros((B, max(nb, 1)))
+        self._check(self.lib.hmps_measure(
+            self.h, _ptr(e, C.c_double), _ptr(ss, C.c_double),
+            _ptr(lw, C.c_double), _ptr(qn, C.c_double)), "hmps_measure")
+        return {"energy": e, "bond_ss": ss[:, :nb], "logw": lw, "qn": qn}
+
+    def hmps_collapse_resample(self, basis: int):
+        out = np.zeros((self.n_chains, max(self.n_env, 1)), np.uint8)
+        self._check(self.lib.hmps_collapse_resample(
+            self.h, basis, _ptr(out, C.c_uint8)), "hmps_collapse_resample")
+        return out[:, : self.n_env]
+
+    def hmps_stats(self):
+        s = hmps_stats_t()
+        self._check(self.lib.hmps_stats(self.h, C.byref(s)), "hmps_stats")
+        return s
+
+    def hmps_bond_dims(self):
+        out = np.zeros((self.n_chains, self.n_sites + 1), np.int32)
+        self._check(self.lib.hmps_bond_dims(self.h, _ptr(out, C.c_int32)),
+                    "hmps_bond_dims")
+        return out
+
+    def hmps_destroy(self):
+        if getattr(self, "h", None):
+            self.lib.hmps_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.hmps_destroy()
+        except Exception:
+            pass

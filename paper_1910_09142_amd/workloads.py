@@ -1,0 +1,68 @@
+"""Seeded synthetic inputs: the S=1 two-leg ladder workloads and their run
+parameters.  Holds no arithmetic of the method (the lattice is the input
+Hamiltonian of the C ABI; random product states are drawn inside the
+library by Philox).  Shared by tests, smoke() and bench.py.
+
+Ladder (Results section): sites (column c, leg l) with id 2c+l, rungs
+(c,0)-(c,1) with J_rung, legs (c,l)-(c+1,l) with J_leg, open boundaries.
+Bond order: rungs by column, then leg 0, then leg 1.  MPS order "snake":
+column c lists leg 0 then leg 1 for even c, leg 1 then leg 0 for odd c.
+Cluster: W central columns starting at (L-W)//2.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    L: int
+    W: int
+    J_leg: float
+    J_rung: float
+    beta: float
+    tau: float
+    chi_max: int
+    cutoff: float
+    n_chains: int
+    n_samples: int
+    seed: int = 0
+
+
+# The five ladder workloads (sizes as stated for each one).
+C1 = Workload("ladder2x3_W1_beta1_chi32", 3, 1, 1.0, 1.0, 1.0, 0.1, 32,
+              1e-12, 1, 20)
+C2 = Workload("ladder2x8_W2_beta5_chi128", 8, 2, 1.0, 1.0, 5.0, 0.05, 128,
+              1e-12, 1, 100)
+C3 = Workload("ladder2x16_W2_Jr0.5_beta5_chi256", 16, 2, 1.0, 0.5, 5.0,
+              0.05, 256, 1e-10, 1, 2)
+C4 = Workload("ladder2x16_W2_Jr0.5_beta5_chi256_batch256", 16, 2, 1.0, 0.5,
+              5.0, 0.05, 256, 1e-10, 256, 1)
+C5 = Workload("ladder2x32_W4_beta10_chi512_batch64", 32, 4, 1.0, 1.0, 10.0,
+              0.05, 512, 1e-10, 64, 1)
+ALL = {w.name: w for w in (C1, C2, C3, C4, C5)}
+
+
+def ladder_arrays(L: int, J_leg: float, J_rung: float, W: int,
+                  ordering: str = "snake"):
+    """(n_phys, bonds [(i, j, J)], mps order, cluster mask)."""
+    bonds = [(2 * c, 2 * c + 1, float(J_rung)) for c in range(L)]
+    for leg in range(2):
+        bonds += [(2 * c + leg, 2 * (c + 1) + leg, float(J_leg))
+                  for c in range(L - 1)]
+    order = []
+    for c in range(L):
+        if ordering == "snake" and c % 2 == 1:
+            order += [2 * c + 1, 2 * c]
+        else:
+            order += [2 * c, 2 * c + 1]
+    c0 = (L - W) // 2
+    mask = [0] * (2 * L)
+    for c in range(c0, c0 + W):
+        mask[2 * c] = mask[2 * c + 1] = 1
+    return 2 * L, bonds, order, mask
+
+
+def mps_length(L: int, W: int) -> int:
+    return 2 * L + 2 * W

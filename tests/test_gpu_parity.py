@@ -1,0 +1,190 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 path, gauge-invariant outputs -- energy 1e-10 relative,
+<S_i.S_j> 1e-10 absolute, log-weight 1e-9 absolute (a sum of up to a few
+thousand logarithms), <Q> 1e-10.  Collapse outcomes are bit-exact except
+where the oracle flags a draw within 1e-12 of a threshold.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import exact, hybrid, model, mps
+from paper_1910_09142_amd import hmps, workloads
+
+pytestmark = pytest.mark.gpu
+
+E_REL = 1e-10
+SS_ABS = 1e-10
+LOGW_ABS = 1e-9
+
+
+def gpu_ctx(L, W, chi_cap, n_chains, precision=hmps.PREC_FP64, J_leg=1.0,
+            J_rung=1.0):
+    n, bonds, order, mask = workloads.ladder_arrays(L, J_leg, J_rung, W)
+    lat = hmps.Lattice(n, bonds, order, mask)
+    ctx = hmps.Context(n_chains, workloads.mps_length(L, W), chi_cap,
+                       len(bonds), precision=precision)
+    return ctx, lat
+
+
+def run_gpu_chain(L, W, beta, tau, chi, cut, n_samples, seed, J_rung=1.0,
+                  n_chains=1):
+    ctx, lat = gpu_ctx(L, W, chi, n_chains, J_rung=J_rung)
+    ctx.hmps_init_cluster_env(lat, n_chains, seed)
+    out = []
+    for n in range(n_samples):
+        ctx.hmps_evolve(beta, tau, chi, cut)
+        m = ctx.hmps_measure()
+        env = ctx.hmps_collapse_resample(n % 2)
+        m["outcomes"] = env
+        out.append(m)
+    ctx.hmps_destroy()
+    return out
+
+
+def compare_sample(g, r, c=0):
+    e = r["energy"]
+    print(f"  E gpu={g['energy'][c]:.15f} oracle={e:.15f}", flush=True)
+    assert abs(g["energy"][c] - e) <= E_REL * abs(e)
+    assert np.abs(g["bond_ss"][c] - np.array(r["bond_ss"])).max() <= SS_ABS
+    assert abs(g["logw"][c] - r["logw"]) <= LOGW_ABS
+    assert abs(g["qn"][c] - r["qn"]) <= 1e-10
+
+
+def test_c1_chain_parity():
+    # 2x3 ladder, W=1, beta=1, tau=0.1, chi_max=32, cutoff 1e-12, seed 0
+    L, W, beta, tau, chi, cut, N = 3, 1, 1.0, 0.1, 32, 1e-12, 20
+    print("case: C1 chain, 20 samples", flush=True)
+    gpu = run_gpu_chain(L, W, beta, tau, chi, cut, N, 0)
+    ref = hybrid.run_chain(model.ladder(L, 1.0, 1.0, W=W), beta, tau, chi,
+                           cut, N, seed=0)
+    lay = model.layout(model.ladder(L, 1.0, 1.0, W=W))
+    for n in range(N):
+        compare_sample(gpu[n], ref[n])
+        want = [ref[n]["outcomes"][p] for p in lay.env_positions]
+        got = list(gpu[n]["outcomes"][0])
+        if got != want:
+            assert ref[n]["near"] > 0, f"sample {n}: {got} != {want}"
+            break
+
+
+def test_exhaustive_batch_equals_trotter():
+    # all 81 environment product states of the 2x3 W=1 ladder as one batch,
+    # untruncated: the P-weighted mean is the Trotter thermal average
+    L, W, beta, tau = 3, 1, 1.0, 0.1
+    olat = model.ladder(L, 1.0, 1.0, W=W)
+    lay = model.layout(olat)
+    states = np.array(list(itertools.product(range(3), repeat=4)), np.uint8)
+    ref_e = exact.trotter_energy(olat, beta, tau)
+    for basis in (0, 1):
+        print(f"case: exhaustive batch basis={basis}", flush=True)
+        ctx, lat = gpu_ctx(L, W, 81, len(states))
+        ctx.hmps_init_cluster_env(lat, len(states), 0, env_state=states,
+                                  basis=basis)
+        ctx.hmps_evolve(beta, tau, 81, 0.0)
+        g = ctx.hmps_measure()
+        ctx.hmps_destroy()
+        w = np.exp(g["logw"] - g["logw"].max())
+        avg = float((w * g["energy"]).sum() / w.sum())
+        assert abs(avg - ref_e) < 1e-11
+        for c in (0, 17, 40, 80):
+            env = dict(zip(lay.env_positions, states[c].tolist()))
+            psi = mps.init_state(lay, env, basis)
+            mps.evolve(psi, model.schedule(olat, lay), 5, tau, 81, 0.0)
+            r = mps.measure(psi, olat, lay)
+            assert abs(g["energy"][c] - r["energy"]) <= E_REL * abs(r["energy"])
+            assert abs(g["logw"][c] - psi.logw) <= LOGW_ABS
+
+
+def test_batch_is_bit_identical_to_single_chains():
+    L, W, beta, tau, chi, cut = 3, 1, 1.0, 0.1, 32, 1e-12
+    states = np.array([[0, 1, 2, 0], [2, 2, 1, 0], [1, 0, 0, 2]], np.uint8)
+    print("case: batch vs single", flush=True)
+    ctx, lat = gpu_ctx(L, W, chi, 3)
+    ctx.hmps_init_cluster_env(lat, 3, 5, env_state=states)
+    ctx.hmps_evolve(beta, tau, chi, cut)
+    gb = ctx.hmps_measure()
+    ctx.hmps_destroy()
+    for c in range(3):
+        ctx, lat = gpu_ctx(L, W, chi, 1)
+        ctx.hmps_init_cluster_env(lat, 1, 5, env_state=states[c:c + 1])
+        ctx.hmps_evolve(beta, tau, chi, cut)
+        g1 = ctx.hmps_measure()
+        ctx.hmps_destroy()
+        assert g1["energy"][0] == gb["energy"][c]
+        assert np.array_equal(g1["bond_ss"][0], gb["bond_ss"][c])
+        assert g1["logw"][0] == gb["logw"][c]
+
+
+@pytest.mark.parametrize("beta,n_samples", [(0.5, 2), (1.0, 1)])
+def test_c2_ladder_parity(beta, n_samples):
+    # 2x8 ladder, W=2, tau=0.05, chi_max=128, cutoff 1e-12 (large-matrix
+    # Jacobi path: theta reaches 384 x 384)
+    L, W, tau, chi, cut = 8, 2, 0.05, 128, 1e-12
+    print(f"case: C2 beta={beta}", flush=True)
+    gpu = run_gpu_chain(L, W, beta, tau, chi, cut, n_samples, 0)
+    ref = hybrid.run_chain(model.ladder(L, 1.0, 1.0, W=W), beta, tau, chi,
+                           cut, n_samples, seed=0)
+    lay = model.layout(model.ladder(L, 1.0, 1.0, W=W))
+    for n in range(n_samples):
+        assert ref[n]["stats"].min_margin > 1e-8
+        compare_sample(gpu[n], ref[n])
+        want = [ref[n]["outcomes"][p] for p in lay.env_positions]
+        assert list(gpu[n]["outcomes"][0]) == want or ref[n]["near"] > 0
+
+
+@pytest.mark.parametrize("L,W,J_rung", [(3, 0, 1.0), (2, 2, 0.5),
+                                        (1, 1, 1.0), (4, 2, 0.5)])
+def test_cluster_limits(L, W, J_rung):
+    # W=0 is METTS, W=L the ancilla method (a single deterministic sample)
+    beta, tau, chi, cut = 1.0, 0.1, 64, 1e-12
+    print(f"case: limits L={L} W={W}", flush=True)
+    gpu = run_gpu_chain(L, W, beta, tau, chi, cut, 2, 3, J_rung=J_rung)
+    olat = model.ladder(L, 1.0, J_rung, W=W)
+    ref = hybrid.run_chain(olat, beta, tau, chi, cut, 2, seed=3)
+    for n in range(2):
+        compare_sample(gpu[n], ref[n])
+    if W == L:
+        e = exact.trotter_energy(olat, beta, tau)
+        assert abs(gpu[0]["energy"][0] - e) < 1e-9
+
+
+def test_beta_zero_and_chi_one():
+    L, W = 3, 1
+    print("case: beta=0, chi_max=1", flush=True)
+    ctx, lat = gpu_ctx(L, W, 32, 1)
+    st = np.array([[2, 0, 1, 2]], np.uint8)
+    ctx.hmps_init_cluster_env(lat, 1, 0, env_state=st)
+    ctx.hmps_evolve(0.0, 0.1, 32, 1e-12)
+    g = ctx.hmps_measure()
+    assert g["logw"][0] == 0.0
+    out = ctx.hmps_collapse_resample(0)
+    assert np.array_equal(out, st)
+    ctx.hmps_evolve(1.0, 0.1, 1, 0.0)
+    chi = ctx.hmps_bond_dims()
+    assert chi.max() == 1
+    ctx.hmps_destroy()
+
+
+def test_invalid_arguments_on_device():
+    ctx, lat = gpu_ctx(3, 1, 32, 2)
+    with pytest.raises(hmps.HmpsError):
+        ctx.hmps_evolve(1.0, 0.1, 32, 1e-12)          # before init
+    ctx.hmps_init_cluster_env(lat, 2, 0)
+    for args in [(1.0, 0.3, 32, 1e-12), (1.0, 0.1, 33, 1e-12),
+                 (1.0, 0.1, 0, 1e-12), (1.0, 0.1, 32, -1.0)]:
+        with pytest.raises(hmps.HmpsError) as e:
+            ctx.hmps_evolve(*args)
+        assert e.value.status == hmps.HMPS_E_INVALID
+    with pytest.raises(hmps.HmpsError):
+        ctx.hmps_init_cluster_env(lat, 3, 0)          # above max_chains
+    with pytest.raises(hmps.HmpsError):
+        ctx.hmps_init_cluster_env(lat, 1, 0, env_state=np.full((1, 4), 3, np.uint8))
+    # still usable after rejected calls
+    ctx.hmps_evolve(1.0, 0.1, 32, 1e-12)
+    g = ctx.hmps_measure()
+    assert np.all(np.isfinite(g["energy"]))
+    ctx.hmps_destroy()
