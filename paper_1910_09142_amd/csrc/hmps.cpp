@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -231,6 +232,7 @@ struct hmps_ctx {
   int center = 0;
   std::vector<int> h_chi;  // [B][len+1]
   hmps_stats_t stats{};
+  bool sync_debug = false;  // HMPS_SYNC_DEBUG=1: check every launch
   // device buffers (carved from the workspace)
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
   int n_cap = 0, slots = 0;
@@ -324,6 +326,14 @@ hmps_status fail(hmps_ctx *c, hmps_status st, const std::string &msg) {
   return st;
 }
 
+#define LAUNCHCHK(ctx)                                                     \
+  do {                                                                     \
+    if ((ctx)->sync_debug) {                                               \
+      HIPCHK(hipStreamSynchronize((ctx)->stream));                         \
+      HIPCHK(hipGetLastError());                                           \
+    }                                                                      \
+  } while (0)
+
 #define HIPCHK(call)                                                       \
   do {                                                                     \
     hipError_t e_ = (call);                                                \
@@ -387,14 +397,17 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   const int L = ctx->plan.len;
   int max_chiL = 1, max_chiR = 1;
   size_t max_mn = 0;
-  int max_nb = 2;
+  int max_nb = 2, max_vlen = 1, max_nvec = 1;
   for (int c = 0; c < ctx->B; ++c) {
     const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
     max_chiL = std::max(max_chiL, row[k]);
     max_chiR = std::max(max_chiR, row[k + 2]);
     max_mn = std::max(max_mn, (size_t)(3 * row[k]) * (3 * row[k + 2]));
-    const int n = 3 * row[k + 2];
-    int nb = (n + JB - 1) / JB;
+    // the Jacobi SVD orthogonalises min(m, n) vectors of length max(m, n)
+    const int nvec = 3 * std::min(row[k], row[k + 2]);
+    max_vlen = std::max(max_vlen, 3 * std::max(row[k], row[k + 2]));
+    max_nvec = std::max(max_nvec, nvec);
+    int nb = (nvec + JB - 1) / JB;
     nb += nb & 1;
     max_nb = std::max(max_nb, nb);
   }
@@ -415,9 +428,12 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   UpdScratch s = scratch_of(ctx);
   hipStream_t st = ctx->stream;
   launch_theta(b, s, u, max_chiL, max_chiR, st);
+  LAUNCHCHK(ctx);
   if (max_mn <= (size_t)SMALL_LDS) {
     launch_jacobi_small(b, s, u, st);
+    LAUNCHCHK(ctx);
   } else {
+    launch_pad(b, s, u, st);
     bool converged = false;
     for (int sweep = 0; sweep <= ctx->opt.max_sweeps; ++sweep) {
       launch_jacobi_sweep_begin(s, ctx->B, sweep, st);
@@ -441,9 +457,9 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
                   "Jacobi SVD did not converge within max_sweeps");
   }
   launch_truncate(b, s, u, st);
-  const int mmax = 3 * max_chiL, nmax = 3 * max_chiR;
-  const int kmax = std::max(1, std::min(u.chi_max, std::min(mmax, nmax)));
-  launch_writeback(b, s, u, mmax, nmax, kmax, st);
+  LAUNCHCHK(ctx);
+  const int kmax = std::max(1, std::min(u.chi_max, max_nvec));
+  launch_writeback(b, s, u, max_vlen, max_nvec, kmax, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_knew, sizeof(int32_t) * ctx->B,
                         hipMemcpyDeviceToHost, st));
@@ -451,10 +467,25 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
                         sizeof(int32_t) * ctx->B, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (int c = 0; c < ctx->B; ++c) {
-    if (ctx->h_stage[ctx->opt.max_chains + c])
-      return fail(ctx, HMPS_E_NUMERIC,
-                  "numerical failure in the SVD/truncation of chain " +
-                      std::to_string(c));
+    const int code = ctx->h_stage[ctx->opt.max_chains + c];
+    if (code) {
+      const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
+      const int m = 3 * row[k], n = 3 * row[k + 2];
+      double sg[6] = {0, 0, 0, 0, 0, 0};
+      (void)hipMemcpy(sg, ctx->d_sig2 + (size_t)c * ctx->n_cap,
+                      sizeof(double) * std::min(n, 6), hipMemcpyDeviceToHost);
+      char buf[512];
+      std::snprintf(buf, sizeof buf,
+                    "numerical failure (code %d: %s) in chain %d, update on "
+                    "sites (%d,%d) op %d, theta %d x %d, update #%lld; "
+                    "sigma^2[0..5] = %.3e %.3e %.3e %.3e %.3e %.3e",
+                    code,
+                    code == 1 ? "in-LDS Jacobi did not converge"
+                              : "zero or non-finite singular values",
+                    c, k, k + 1, op, m, n, (long long)ctx->stats.updates,
+                    sg[0], sg[1], sg[2], sg[3], sg[4], sg[5]);
+      return fail(ctx, HMPS_E_NUMERIC, buf);
+    }
     const int kn = ctx->h_stage[c];
     ctx->h_chi[(size_t)c * (L + 1) + k + 1] = kn;
     ctx->stats.max_chi = std::max(ctx->stats.max_chi, kn);
@@ -516,6 +547,7 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
     ctx->opt.jacobi_tol = 8.0 * std::sqrt(3.0 * opt->chi_cap) * 2.220446e-16;
   }
   ctx->stream = reinterpret_cast<hipStream_t>(opt->stream);
+  if (const char *e = std::getenv("HMPS_SYNC_DEBUG")) ctx->sync_debug = e[0] == '1';
   hipError_t e = hipSetDevice(opt->device);
   if (e != hipSuccess) {
     delete ctx;

@@ -66,6 +66,8 @@ struct UpdParams {
 // ---- launchers (kernels.hip) -----------------------------------------
 void launch_theta(const Batch &b, const UpdScratch &s, const UpdParams &u,
                   int max_chiL, int max_chiR, hipStream_t st);
+void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                hipStream_t st);
 void launch_jacobi_small(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, hipStream_t st);
 void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
@@ -76,7 +78,7 @@ void launch_jacobi_round(const Batch &b, const UpdScratch &s,
 void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
                      hipStream_t st);
 void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                      int max_m, int max_n, int max_k, hipStream_t st);
+                      int max_L, int max_N, int max_k, hipStream_t st);
 
 struct MeasureArgs {
   const int32_t *bond_p, *bond_q;  // [n_bonds] MPS positions, p < q

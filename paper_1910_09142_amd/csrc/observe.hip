@@ -1,0 +1,273 @@
+// gfx950 kernels of steps 1, 3 and 4 of the hybrid Markov chain
+// (Chen & Stoudenmire, arXiv:1910.09142, Hybrid METTS-Ancilla subsection):
+// initial states, measurement by transfer matrices, sequential projective
+// collapse of the environment with Philox4x64-10 draws.
+#include "device_common.h"
+
+namespace hmps {
+namespace {
+using namespace dev;
+
+// Product-basis vectors: row t is the state of outcome t (eigenvalue
+// +1, 0, -1) written in the S^z basis; basis 0 = S^z, 1 = S^x.
+__constant__ double c_basis[2][3][3] = {
+    {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}},
+    {{0.5, 0.70710678118654752440, 0.5},
+     {0.70710678118654752440, 0.0, -0.70710678118654752440},
+     {0.5, -0.70710678118654752440, 0.5}}};
+
+// =====================================================================
+// Measurement.  The centre is site 0 and sites 1.. are right-orthonormal,
+// so the right environment of every site is the identity.  L_p is the
+// left environment of <psi|psi> (sites < p).
+// =====================================================================
+__global__ void __launch_bounds__(NT)
+    k_measure_envs(Batch b, MeasureArgs ma) {
+  const int c = blockIdx.x;
+  const int32_t *chi = chi_row(b, c);
+  double *env = ma.envs + (size_t)c * (b.nsites + 1) * ma.chi2;
+  double *Y = ma.bond_scratch + (size_t)c * ma.slots * 4 * ma.chi2;
+  __shared__ double red[NT / 64];
+  if (threadIdx.x == 0) env[0] = 1.0;
+  __syncthreads();
+  for (int p = 0; p < b.nsites; ++p) {
+    const int chiL = chi[p], chiR = chi[p + 1];
+    const double *T = site_ptr(b, c, p);
+    double *Lp = env + (size_t)p * ma.chi2;
+    double *Lq = env + (size_t)(p + 1) * ma.chi2;
+    double sz = 0.0;
+    for (int t = 0; t < 3; ++t) {
+      const double *Ts = T + (size_t)t * chiL * chiR;
+      wg_gemm(chiL, chiR, chiL, 1.0, Lp, chiL, 0, Ts, chiR, 0, 0.0, Y, chiR);
+      const double w = wg_dot(chiL, chiR, Ts, Y, chiR, red);
+      sz += (1 - t) * w;
+      wg_gemm(chiR, chiR, chiL, 1.0, Ts, chiR, 1, Y, chiR, 0, t ? 1.0 : 0.0,
+              Lq, chiR);
+    }
+    if (threadIdx.x == 0)
+      ma.wsz[(size_t)c * b.nsites + p] = ma.is_ancilla[p] ? -sz : sz;
+  }
+  if (threadIdx.x == 0) ma.norm[c] = env[(size_t)b.nsites * ma.chi2];
+}
+
+__global__ void __launch_bounds__(NT)
+    k_measure_bonds(Batch b, MeasureArgs ma, int b0) {
+  const int c = blockIdx.y, slot = blockIdx.x, bond = b0 + blockIdx.x;
+  if (bond >= ma.n_bonds) return;
+  const int32_t *chi = chi_row(b, c);
+  const int p = ma.bond_p[bond], q = ma.bond_q[bond];
+  const double *env = ma.envs + (size_t)c * (b.nsites + 1) * ma.chi2;
+  double *scr = ma.bond_scratch + ((size_t)c * ma.slots + slot) * 4 * ma.chi2;
+  double *E = scr, *E2 = scr + ma.chi2, *Y = scr + 2 * ma.chi2;
+  __shared__ double red[NT / 64];
+  const double r2 = 1.4142135623730950488;
+  double total = 0.0;
+  for (int str = 0; str < 2; ++str) {
+    // at p: E = sum_{s,t} O[s,t] T_p[s]^T L_p T_p[t]  (O = S^z or S^+)
+    {
+      const int chiL = chi[p], chiR = chi[p + 1];
+      const double *T = site_ptr(b, c, p);
+      const double *Lp = env + (size_t)p * ma.chi2;
+      bool first = true;
+      for (int sb = 0; sb < 3; ++sb) {
+        int tk;
+        double coef;
+        if (str == 0) {
+          tk = sb;
+          coef = 1.0 - sb;
+        } else {
+          tk = sb + 1;
+          coef = r2;
+          if (sb == 2) coef = 0.0;
+        }
+        if (coef == 0.0) continue;
+        wg_gemm(chiL, chiR, chiL, 1.0, Lp, chiL, 0,
+                T + (size_t)tk * chiL * chiR, chiR, 0, 0.0, Y, chiR);
+        wg_gemm(chiR, chiR, chiL, coef, T + (size_t)sb * chiL * chiR, chiR, 1,
+                Y, chiR, 0, first ? 0.0 : 1.0, E, chiR);
+        first = false;
+      }
+    }
+    for (int mid = p + 1; mid < q; ++mid) {
+      const int chiL = chi[mid], chiR = chi[mid + 1];
+      const double *T = site_ptr(b, c, mid);
+      for (int sb = 0; sb < 3; ++sb) {
+        const double *Ts = T + (size_t)sb * chiL * chiR;
+        wg_gemm(chiL, chiR, chiL, 1.0, E, chiL, 0, Ts, chiR, 0, 0.0, Y, chiR);
+        wg_gemm(chiR, chiR, chiL, 1.0, Ts, chiR, 1, Y, chiR, 0,
+                sb ? 1.0 : 0.0, E2, chiR);
+      }
+      double *t = E;
+      E = E2;
+      E2 = t;
+    }
+    // at q: sum_{s,t} O'[s,t] <T_q[s], E T_q[t]>  (O' = S^z or S^-)
+    {
+      const int chiL = chi[q], chiR = chi[q + 1];
+      const double *T = site_ptr(b, c, q);
+      for (int sb = 0; sb < 3; ++sb) {
+        int tk;
+        double coef;
+        if (str == 0) {
+          tk = sb;
+          coef = 1.0 - sb;
+        } else {
+          tk = sb - 1;
+          coef = (sb == 0) ? 0.0 : r2;
+        }
+        if (coef == 0.0) continue;
+        wg_gemm(chiL, chiR, chiL, 1.0, E, chiL, 0,
+                T + (size_t)tk * chiL * chiR, chiR, 0, 0.0, Y, chiR);
+        total += coef *
+                 wg_dot(chiL, chiR, T + (size_t)sb * chiL * chiR, Y, chiR, red);
+      }
+    }
+  }
+  if (threadIdx.x == 0) ma.bond_ss[(size_t)c * ma.n_bonds + bond] = total;
+}
+
+__global__ void k_measure_finish(Batch b, MeasureArgs ma, double *energy,
+                                 double *qn) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b.B) return;
+  const double nrm = ma.norm[c];
+  double e = 0.0;
+  for (int i = 0; i < ma.n_bonds; ++i) {
+    const double v = ma.bond_ss[(size_t)c * ma.n_bonds + i] / nrm;
+    ma.bond_ss[(size_t)c * ma.n_bonds + i] = v;
+    e += ma.bond_J[i] * v;
+  }
+  energy[c] = e;
+  double z = 0.0;
+  for (int p = 0; p < b.nsites; ++p) z += ma.wsz[(size_t)c * b.nsites + p];
+  qn[c] = z / nrm;
+}
+
+// =====================================================================
+// Collapse: E is the left density matrix of the measured/traced past.
+// =====================================================================
+__global__ void __launch_bounds__(NT) k_collapse(Batch b, CollapseArgs a) {
+  const int c = blockIdx.x;
+  const int32_t *chi = chi_row(b, c);
+  double *scr = a.scratch + (size_t)c * 8 * a.chi2;
+  double *E = scr, *E2 = scr + a.chi2, *Z = scr + 2 * a.chi2;
+  double *Yt = scr + 3 * a.chi2;  // 3 buffers
+  __shared__ double red[NT / 64];
+  __shared__ int pick;
+  if (threadIdx.x == 0) {
+    E[0] = 1.0;
+    a.near[c] = 0;
+  }
+  __syncthreads();
+  for (int k = 0; k < b.nsites; ++k) {
+    const int chiL = chi[k], chiR = chi[k + 1];
+    const double *T = site_ptr(b, c, k);
+    if (a.is_cluster[k]) {
+      for (int sb = 0; sb < 3; ++sb) {
+        const double *Ts = T + (size_t)sb * chiL * chiR;
+        wg_gemm(chiL, chiR, chiL, 1.0, E, chiL, 0, Ts, chiR, 0, 0.0, Z, chiR);
+        wg_gemm(chiR, chiR, chiL, 1.0, Ts, chiR, 1, Z, chiR, 0,
+                sb ? 1.0 : 0.0, E2, chiR);
+      }
+    } else {
+      const int sz = chiL * chiR;
+      for (int idx = threadIdx.x; idx < sz; idx += NT) {
+        const double v0 = T[idx], v1 = T[sz + idx], v2 = T[2 * sz + idx];
+        for (int t = 0; t < 3; ++t)
+          Yt[(size_t)t * a.chi2 + idx] = c_basis[a.basis][t][0] * v0 +
+                                         c_basis[a.basis][t][1] * v1 +
+                                         c_basis[a.basis][t][2] * v2;
+      }
+      __syncthreads();
+      double pr[3];
+      for (int t = 0; t < 3; ++t) {
+        wg_gemm(chiL, chiR, chiL, 1.0, E, chiL, 0, Yt + (size_t)t * a.chi2,
+                chiR, 0, 0.0, Z, chiR);
+        pr[t] = fmax(wg_dot(chiL, chiR, Yt + (size_t)t * a.chi2, Z, chiR, red),
+                     0.0);
+      }
+      if (threadIdx.x == 0) {
+        const double P = pr[0] + pr[1] + pr[2];
+        const double cum0 = pr[0] / P, cum1 = (pr[0] + pr[1]) / P;
+        const uint64_t x = philox_word0((uint64_t)c, (uint64_t)a.sample,
+                                        (uint64_t)k, 1ull, a.seed, 0ull);
+        const double uu = (double)(x >> 11) * (1.0 / 9007199254740992.0);
+        int sel = 2;
+        if (uu < cum0)
+          sel = 0;
+        else if (uu < cum1)
+          sel = 1;
+        double dmin = fmin(fabs(uu - cum0), fabs(uu - cum1));
+        dmin = fmin(dmin, fabs(uu - 1.0));
+        if (dmin < 1e-12) a.near[c] += 1;
+        pick = sel;
+        a.outcomes[(size_t)c * a.n_env + a.env_index[k]] = (uint8_t)sel;
+      }
+      __syncthreads();
+      const int sel = pick;
+      const double *Ys = Yt + (size_t)sel * a.chi2;
+      wg_gemm(chiL, chiR, chiL, 1.0, E, chiL, 0, Ys, chiR, 0, 0.0, Z, chiR);
+      wg_gemm(chiR, chiR, chiL, 1.0 / pr[sel], Ys, chiR, 1, Z, chiR, 0, 0.0,
+              E2, chiR);
+    }
+    double *t = E;
+    E = E2;
+    E2 = t;
+  }
+}
+
+// =====================================================================
+// Initial states.
+// =====================================================================
+__global__ void k_init(Batch b, InitArgs a, double *logw) {
+  const int p = blockIdx.x, c = blockIdx.y;
+  int32_t *chi = b.chi + (size_t)c * (b.nsites + 1);
+  double *T = site_ptr(b, c, p);
+  const int t = threadIdx.x;
+  if (a.is_cluster[p] && !a.is_ancilla[p]) {
+    if (t < 9) T[t] = ((t / 3) == (t % 3)) ? 0.57735026918962576451 : 0.0;
+    if (t == 0) chi[p + 1] = 3;
+  } else if (a.is_ancilla[p]) {
+    if (t < 9) T[t] = ((t / 3) == (t % 3)) ? 1.0 : 0.0;
+    if (t == 0) chi[p + 1] = 1;
+  } else {
+    const int lab = a.labels[(size_t)c * a.n_env + a.env_index[p]];
+    if (t < 3) T[t] = c_basis[a.basis][lab][t];
+    if (t == 0) chi[p + 1] = 1;
+  }
+  if (p == 0 && t == 0) {
+    chi[0] = 1;
+    logw[c] = 0.0;
+  }
+}
+
+}  // namespace
+
+void launch_measure_envs(const Batch &b, const MeasureArgs &m,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_measure_envs, dim3(b.B), dim3(NT), 0, st, b, m);
+}
+
+void launch_measure_bonds(const Batch &b, const MeasureArgs &m, int b0,
+                          int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_measure_bonds, dim3(nb, b.B), dim3(NT), 0, st, b, m,
+                     b0);
+}
+
+void launch_measure_finish(const Batch &b, const MeasureArgs &m,
+                           double *energy, double *qn, hipStream_t st) {
+  hipLaunchKernelGGL(k_measure_finish, dim3((b.B + 255) / 256), dim3(256), 0,
+                     st, b, m, energy, qn);
+}
+
+void launch_collapse(const Batch &b, const CollapseArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_collapse, dim3(b.B), dim3(NT), 0, st, b, a);
+}
+
+void launch_init(const Batch &b, const InitArgs &a, double *logw,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3(b.nsites, b.B), dim3(64), 0, st, b, a,
+                     logw);
+}
+
+}  // namespace hmps

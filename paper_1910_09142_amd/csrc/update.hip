@@ -1,0 +1,579 @@
+// gfx950 kernels of one two-site Trotter update on every chain of a batch
+// (Chen & Stoudenmire, arXiv:1910.09142: gate on a bond, then a truncated
+// SVD restores the MPS form -- Ancilla Method subsection and Results
+// section, sources of error).
+//
+//   k_theta         theta' = G (T_k T_{k+1}), written as a matrix whose
+//                   columns are the vectors the Jacobi SVD orthogonalises
+//   k_pad           zero padding vectors of the blocked Jacobi path
+//   k_jacobi_small  one-sided Jacobi SVD with the whole matrix in LDS
+//   k_jacobi_round  one round of the blocked one-sided Jacobi SVD
+//   k_truncate      sort singular values, choose how many to keep
+//   k_writeback_*   new site tensors from the kept singular triplets
+//
+// Vector layout.  theta' is m x n with m = 3 chi_L (rows (s1,a)) and
+// n = 3 chi_R (columns (s2,c)).  The Jacobi SVD orthogonalises the N =
+// min(m, n) vectors of length L = max(m, n): the columns of theta' when
+// n <= m, its rows when n > m ("transposed").  More vectors than their
+// length could never all become orthogonal.  X and TH hold the L x N
+// vector matrix column-major (vector j at offset j*L).
+#include "device_common.h"
+
+namespace hmps {
+namespace {
+using namespace dev;
+
+struct Dims {
+  int chiL, chiM, chiR, m, n, L, N, trans;
+};
+
+__device__ __forceinline__ Dims dims_of(const Batch &b, int c, int k) {
+  const int32_t *chi = chi_row(b, c);
+  Dims d;
+  d.chiL = chi[k];
+  d.chiM = chi[k + 1];
+  d.chiR = chi[k + 2];
+  d.m = 3 * d.chiL;
+  d.n = 3 * d.chiR;
+  d.trans = d.n > d.m;
+  d.L = d.trans ? d.n : d.m;
+  d.N = d.trans ? d.m : d.n;
+  return d;
+}
+
+// =====================================================================
+// theta'[(s1,a),(s2,c)] = sum_{t1,t2} G[(s1 s2),(t1 t2)]
+//                          sum_b T_k[t1][a][b] T_{k+1}[t2][b][c]
+// One workgroup per 16 x 16 tile of (a, c); all nine (t1, t2) blocks of
+// the tile are accumulated so the 9 x 9 gate is applied in registers.
+// =====================================================================
+__global__ void __launch_bounds__(NT)
+    k_theta(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.z;
+  const Dims d = dims_of(b, c, u.k);
+  const int a0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+  if (a0 >= d.chiL || c0 >= d.chiR) return;
+  const int chiL = d.chiL, chiM = d.chiM, chiR = d.chiR;
+  const double *A = site_ptr(b, c, u.k);
+  const double *Bt = site_ptr(b, c, u.k + 1);
+  double *TH = s.TH + (size_t)c * s.th_stride;
+  double *X = s.X + (size_t)c * s.th_stride;
+  __shared__ double As[3][16][17];
+  __shared__ double Bs[3][16][17];
+  __shared__ double G[81];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  if (threadIdx.x < 81) G[threadIdx.x] = u.gate[threadIdx.x];
+  double acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = 0.0;
+  for (int b0 = 0; b0 < chiM; b0 += 16) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      As[t][ty][tx] = (a0 + ty < chiL && b0 + tx < chiM)
+                          ? A[(size_t)t * chiL * chiM +
+                              (size_t)(a0 + ty) * chiM + b0 + tx]
+                          : 0.0;
+      Bs[t][ty][tx] = (b0 + ty < chiM && c0 + tx < chiR)
+                          ? Bt[(size_t)t * chiM * chiR +
+                               (size_t)(b0 + ty) * chiR + c0 + tx]
+                          : 0.0;
+    }
+    __syncthreads();
+    // normal layout: thread (tx, ty) = (a, c); transposed: (c, a), so
+    // that consecutive threads write consecutive elements of a vector
+    const int ia = d.trans ? ty : tx, ic = d.trans ? tx : ty;
+#pragma unroll 4
+    for (int bb = 0; bb < 16; ++bb) {
+      const double a_0 = As[0][ia][bb], a_1 = As[1][ia][bb],
+                   a_2 = As[2][ia][bb];
+      const double b_0 = Bs[0][bb][ic], b_1 = Bs[1][bb][ic],
+                   b_2 = Bs[2][bb][ic];
+      acc[0] += a_0 * b_0;
+      acc[1] += a_0 * b_1;
+      acc[2] += a_0 * b_2;
+      acc[3] += a_1 * b_0;
+      acc[4] += a_1 * b_1;
+      acc[5] += a_1 * b_2;
+      acc[6] += a_2 * b_0;
+      acc[7] += a_2 * b_1;
+      acc[8] += a_2 * b_2;
+    }
+    __syncthreads();
+  }
+  const int a = a0 + (d.trans ? ty : tx), cc = c0 + (d.trans ? tx : ty);
+  if (a < chiL && cc < chiR) {
+#pragma unroll
+    for (int s1 = 0; s1 < 3; ++s1) {
+#pragma unroll
+      for (int s2 = 0; s2 < 3; ++s2) {
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) v += G[(s1 * 3 + s2) * 9 + t] * acc[t];
+        const size_t row = (size_t)s1 * chiL + a, col = (size_t)s2 * chiR + cc;
+        const size_t off = d.trans ? row * d.n + col : col * d.m + row;
+        TH[off] = v;
+        X[off] = v;
+      }
+    }
+  }
+}
+
+// Zero the padding vectors N..npad-1 of the blocked Jacobi path.
+__global__ void __launch_bounds__(NT) k_pad(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.y;
+  const Dims d = dims_of(b, c, u.k);
+  const int npad = n_blocks_even(d.N) * JB;
+  const size_t cnt = (size_t)(npad - d.N) * d.L;
+  double *X = s.X + (size_t)c * s.th_stride + (size_t)d.N * d.L;
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < cnt;
+       i += (size_t)gridDim.x * NT)
+    X[i] = 0.0;
+}
+
+// =====================================================================
+// One-sided Jacobi SVD, whole matrix in LDS (one workgroup per chain).
+// The N vectors are rotated in round-robin pair order until every pair is
+// orthogonal to relative tolerance tol; then X = U Sigma (vector side) and
+// the squared vector norms are written to sig2.
+// =====================================================================
+__global__ void __launch_bounds__(NT)
+    k_jacobi_small(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.x;
+  const Dims d = dims_of(b, c, u.k);
+  const int L = d.L, N = d.N;
+  double *X = s.X + (size_t)c * s.th_stride;
+  __shared__ double xs[SMALL_LDS];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < L * N; idx += NT) xs[idx] = X[idx];
+  const int n_even = N + (N & 1);
+  const int npairs = n_even / 2;
+  int g = 64;
+  while (g > 1 && g * npairs > NT) g >>= 1;
+  const int lane = tid & (g - 1);
+  const int per_pass = NT / g;
+  bool converged = false;
+  int sweep = 0;
+  for (; sweep < u.max_sweeps; ++sweep) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int r = 0; r < n_even - 1; ++r) {
+      for (int pi = tid / g; pi < npairs; pi += per_pass) {
+        int p, q;
+        rr_pair(r, pi, n_even, p, q);
+        if (q < N) {
+          double aa = 0.0, bb = 0.0, gg = 0.0;
+          for (int i = lane; i < L; i += g) {
+            const double x = xs[p * L + i], y = xs[q * L + i];
+            aa += x * x;
+            bb += y * y;
+            gg += x * y;
+          }
+          for (int off = g >> 1; off > 0; off >>= 1) {
+            aa += __shfl_xor(aa, off);
+            bb += __shfl_xor(bb, off);
+            gg += __shfl_xor(gg, off);
+          }
+          double cr, sr;
+          if (jacobi_rotation(aa, bb, gg, u.tol, cr, sr)) {
+            for (int i = lane; i < L; i += g) {
+              const double x = xs[p * L + i], y = xs[q * L + i];
+              xs[p * L + i] = cr * x - sr * y;
+              xs[q * L + i] = sr * x + cr * y;
+            }
+            if (lane == 0) flag = 1;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const int f = flag;
+    __syncthreads();
+    if (f == 0) {
+      converged = true;
+      break;
+    }
+  }
+  for (int idx = tid; idx < L * N; idx += NT) X[idx] = xs[idx];
+  double *sig2 = s.sig2 + (size_t)c * s.n_cap;
+  for (int j = tid; j < N; j += NT) {
+    double v = 0.0;
+    for (int i = 0; i < L; ++i) v += xs[j * L + i] * xs[j * L + i];
+    sig2[j] = v;
+  }
+  if (tid == 0) {
+    if (!converged) s.err[c] = 1;
+    s.sweeps[c] += converged ? sweep + 1 : sweep;
+  }
+}
+
+__global__ void k_jacobi_sweep_begin(UpdScratch s, int B, int sweep) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= B) return;
+  if (sweep == 0)
+    s.done[c] = 0;
+  else if (s.rot_cur[c] == 0)
+    s.done[c] = 1;
+  s.rot_cur[c] = 0;
+}
+
+// =====================================================================
+// One round of the blocked one-sided Jacobi SVD: one workgroup per pair
+// of JB-vector blocks per chain.  Gram matrix of the 2 JB vectors, its
+// eigenvectors Q by cyclic Jacobi in LDS, then X[:, pair] <- X[:, pair] Q.
+// A pair already orthogonal to tolerance records its squared norms in
+// sig2 instead (in the last sweep every pair does).
+// =====================================================================
+__global__ void __launch_bounds__(NT)
+    k_jacobi_round(Batch b, UpdScratch s, UpdParams u, int r) {
+  const int c = blockIdx.y, pi = blockIdx.x;
+  if (s.done[c]) return;
+  const Dims d = dims_of(b, c, u.k);
+  const int L = d.L, N = d.N;
+  const int NB = n_blocks_even(N);
+  if (r >= NB - 1 || pi >= NB / 2) return;
+  int bi, bj;
+  rr_pair(r, pi, NB, bi, bj);
+  double *X = s.X + (size_t)c * s.th_stride;
+  __shared__ double xs[64][33];
+  __shared__ double G[32][33];
+  __shared__ double Q[32][33];
+  __shared__ double cs[16], sn[16];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  const int gi = tid >> 3, gj0 = (tid & 7) * 4;
+  auto colidx = [&](int t) { return t < JB ? bi * JB + t : bj * JB + t - JB; };
+
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e0 = 0; e0 < L; e0 += 64) {
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const int idx = tid + NT * h;
+      const int col = idx >> 6, row = idx & 63;
+      xs[row][col] = (e0 + row < L)
+                         ? X[(size_t)colidx(col) * L + e0 + row]
+                         : 0.0;
+    }
+    __syncthreads();
+    for (int row = 0; row < 64; ++row) {
+      const double xi = xs[row][gi];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) acc[jj] += xi * xs[row][gj0 + jj];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) G[gi][gj0 + jj] = acc[jj];
+  if (tid == 0) flag = 0;
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    const int j = gj0 + jj;
+    if (j != gi && pair_needs_rotation(G[gi][gi], G[j][j], G[gi][j], u.tol))
+      flag = 1;
+  }
+  __syncthreads();
+  if (!flag) {
+    if (tid < 2 * JB) {
+      const int col = colidx(tid);
+      if (col < N) s.sig2[(size_t)c * s.n_cap + col] = G[tid][tid];
+    }
+    return;
+  }
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) Q[gi][gj0 + jj] = (gi == gj0 + jj) ? 1.0 : 0.0;
+  __syncthreads();
+
+  // eigenvectors of G by cyclic Jacobi: G <- J^T G J, Q <- Q J
+  const double tol_in = fmax(0.125 * u.tol, 4e-16);
+  for (int isw = 0; isw < 20; ++isw) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int rr = 0; rr < 2 * JB - 1; ++rr) {
+      if (tid < JB) {
+        int p, q;
+        rr_pair(rr, tid, 2 * JB, p, q);
+        double cr = 1.0, sr = 0.0;
+        if (jacobi_rotation(G[p][p], G[q][q], G[p][q], tol_in, cr, sr))
+          flag = 1;
+        cs[tid] = cr;
+        sn[tid] = sr;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int idx = tid + NT * h;
+        const int pp = idx >> 5, col = idx & 31;
+        int p, q;
+        rr_pair(rr, pp, 2 * JB, p, q);
+        const double cr = cs[pp], sr = sn[pp];
+        const double x = G[p][col], y = G[q][col];
+        G[p][col] = cr * x - sr * y;
+        G[q][col] = sr * x + cr * y;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int idx = tid + NT * h;
+        const int pp = idx >> 5, row = idx & 31;
+        int p, q;
+        rr_pair(rr, pp, 2 * JB, p, q);
+        const double cr = cs[pp], sr = sn[pp];
+        double x = G[row][p], y = G[row][q];
+        G[row][p] = cr * x - sr * y;
+        G[row][q] = sr * x + cr * y;
+        x = Q[row][p];
+        y = Q[row][q];
+        Q[row][p] = cr * x - sr * y;
+        Q[row][q] = sr * x + cr * y;
+      }
+      __syncthreads();
+    }
+    const int f = flag;
+    __syncthreads();
+    if (!f) break;
+  }
+
+  for (int e = tid; e < L; e += NT) {
+    double xin[2 * JB];
+#pragma unroll
+    for (int t = 0; t < 2 * JB; ++t) xin[t] = X[(size_t)colidx(t) * L + e];
+#pragma unroll 4
+    for (int j = 0; j < 2 * JB; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2 * JB; ++t) v += xin[t] * Q[t][j];
+      X[(size_t)colidx(j) * L + e] = v;
+    }
+  }
+  if (tid == 0) atomicAdd(&s.rot_cur[c], 1);
+}
+
+// =====================================================================
+// Truncation: sort the singular values (bitonic, LDS), then keep
+//   k = min(k_eps, chi_max), k_eps the smallest k >= 1 whose discarded
+//   tail sum_{j>=k} sigma_j^2 is <= cutoff * sum_j sigma_j^2 (relative
+//   discarded weight, Results section); values at or below SIGMA_FLOOR
+//   sigma_0 are numerically zero and always dropped; a cut inside a run
+//   of ties (relative gaps <= TIE_TOL) drops the whole run unless it
+//   starts at sigma_0.  ln sum sigma^2 = ln ||theta'||^2 goes into logw
+//   for a gate (the sampling weight is the product of these norms).
+// =====================================================================
+__global__ void __launch_bounds__(NT)
+    k_truncate(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.x;
+  const Dims d = dims_of(b, c, u.k);
+  const int N = d.N;
+  __shared__ double key[2048];
+  __shared__ int idx[2048];
+  __shared__ int kk_s;
+  const int tid = threadIdx.x;
+  int N2 = 1;
+  while (N2 < N) N2 <<= 1;
+  const double *sig2 = s.sig2 + (size_t)c * s.n_cap;
+  for (int j = tid; j < N2; j += NT) {
+    key[j] = (j < N) ? sqrt(fmax(sig2[j], 0.0)) : -1.0;
+    idx[j] = j;
+  }
+  __syncthreads();
+  for (int size = 2; size <= N2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < N2 / 2; t += NT) {
+        const int i = 2 * stride * (t / stride) + (t % stride);
+        const int j = i + stride;
+        const bool desc = (i & size) == 0;
+        const double ki = key[i], kj = key[j];
+        const int ii = idx[i], ij = idx[j];
+        const bool j_first = (kj > ki) || (kj == ki && ij < ii);
+        const bool i_first = (ki > kj) || (ki == kj && ii < ij);
+        if (desc ? j_first : i_first) {
+          key[i] = kj;
+          key[j] = ki;
+          idx[i] = ij;
+          idx[j] = ii;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    double total = 0.0;
+    for (int j = N - 1; j >= 0; --j) total += key[j] * key[j];
+    int kfloor = 0;
+    while (kfloor < N && key[kfloor] > SIGMA_FLOOR * key[0]) ++kfloor;
+    const double thr = u.cutoff * total;
+    int k_eps = N;
+    double tail = 0.0;
+    for (int k = N; k >= 1; --k) {
+      if (k < N) tail += key[k] * key[k];
+      if (tail <= thr)
+        k_eps = k;
+      else
+        break;
+    }
+    int k = k_eps < u.chi_max ? k_eps : u.chi_max;
+    if (k > kfloor) k = kfloor;
+    if (k < 1) k = 1;
+    if (k < N && key[k - 1] - key[k] <= TIE_TOL * key[k - 1]) {
+      int i = k - 1;
+      while (i > 0 && key[i - 1] - key[i] <= TIE_TOL * key[i - 1]) --i;
+      if (i > 0) k = i;
+    }
+    double kept = 0.0;
+    for (int j = k - 1; j >= 0; --j) kept += key[j] * key[j];
+    if (!(total > 0.0) || !isfinite(total) || !(kept > 0.0)) s.err[c] = 2;
+    s.fac[c] = 1.0 / sqrt(kept);
+    if (u.is_gate) s.logw[c] += log(total);
+    s.discarded[c] += (total - kept) / total;
+    s.knew[c] = k;
+    kk_s = k;
+  }
+  __syncthreads();
+  const int k = kk_s;
+  for (int j = tid; j < k; j += NT) {
+    s.perm[(size_t)c * s.n_cap + j] = idx[j];
+    s.sig[(size_t)c * s.n_cap + j] = key[j];
+  }
+  // the new bond dimension is published last: the write-back kernels read
+  // the old chi of bonds k and k+2 only
+  if (tid == 0) b.chi[(size_t)c * (b.nsites + 1) + u.k + 1] = k;
+}
+
+// =====================================================================
+// Write-back.  X = U_v Sigma with U_v the singular vectors on the vector
+// side (U for the normal layout, V for the transposed one).  The vector-
+// side site takes X_j scaled by fac (if the orthogonality centre moves
+// there) or by 1/sigma_j (isometry); the other site takes the projection
+// X_j^T TH scaled by 1/sigma_j^2 (isometry) or fac/sigma_j (centre).
+// Normal layout: vector side is site k (rows (s1,a)); transposed: site k+1
+// (columns (s2,c)).  With fac = 1/||kept||, right = 1 gives T_k = U,
+// T_{k+1} = fac Sigma V^T; right = 0 gives T_k = fac U Sigma, T_{k+1} = V^T.
+// =====================================================================
+__device__ __forceinline__ void store_vector_side(const Batch &b, int c,
+                                                  int k, const Dims &d,
+                                                  int knew, int l, int j,
+                                                  double v) {
+  if (!d.trans) {
+    const int s1 = l / d.chiL, a = l - s1 * d.chiL;
+    site_ptr(b, c, k)[(size_t)s1 * d.chiL * knew + (size_t)a * knew + j] = v;
+  } else {
+    const int s2 = l / d.chiR, cc = l - s2 * d.chiR;
+    site_ptr(b, c, k + 1)[(size_t)s2 * knew * d.chiR + (size_t)j * d.chiR +
+                          cc] = v;
+  }
+}
+
+__device__ __forceinline__ void store_other_side(const Batch &b, int c,
+                                                 int k, const Dims &d,
+                                                 int knew, int q, int j,
+                                                 double v) {
+  if (!d.trans) {
+    const int s2 = q / d.chiR, cc = q - s2 * d.chiR;
+    site_ptr(b, c, k + 1)[(size_t)s2 * knew * d.chiR + (size_t)j * d.chiR +
+                          cc] = v;
+  } else {
+    const int s1 = q / d.chiL, a = q - s1 * d.chiL;
+    site_ptr(b, c, k)[(size_t)s1 * d.chiL * knew + (size_t)a * knew + j] = v;
+  }
+}
+
+// Dims as they were before the truncation: chi[k+1] now holds knew, but
+// nothing here depends on the old middle dimension.
+__global__ void __launch_bounds__(NT)
+    k_writeback_direct(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.y;
+  const Dims d = dims_of(b, c, u.k);
+  const int k = s.knew[c];
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= d.L * k) return;
+  const int l = t % d.L, j = t / d.L;
+  const int col = s.perm[(size_t)c * s.n_cap + j];
+  const bool vec_center = (d.trans != 0) == (u.right != 0);
+  const double f =
+      vec_center ? s.fac[c] : 1.0 / s.sig[(size_t)c * s.n_cap + j];
+  const double v = s.X[(size_t)c * s.th_stride + (size_t)col * d.L + l] * f;
+  store_vector_side(b, c, u.k, d, k, l, j, v);
+}
+
+__global__ void __launch_bounds__(NT)
+    k_writeback_gemm(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.z;
+  const Dims d = dims_of(b, c, u.k);
+  const int k = s.knew[c];
+  const int q0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  if (q0 >= d.N || j0 >= k) return;
+  const int L = d.L;
+  const double *X = s.X + (size_t)c * s.th_stride;
+  const double *TH = s.TH + (size_t)c * s.th_stride;
+  const int32_t *perm = s.perm + (size_t)c * s.n_cap;
+  __shared__ double As[16][17];
+  __shared__ double Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int pj = (j0 + ty < k) ? perm[j0 + ty] : -1;
+  double acc = 0.0;
+  for (int i0 = 0; i0 < L; i0 += 16) {
+    As[ty][tx] = (pj >= 0 && i0 + tx < L) ? X[(size_t)pj * L + i0 + tx] : 0.0;
+    Bs[tx][ty] = (q0 + ty < d.N && i0 + tx < L)
+                     ? TH[(size_t)(q0 + ty) * L + i0 + tx]
+                     : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) acc += As[ty][ii] * Bs[ii][tx];
+    __syncthreads();
+  }
+  const int j = j0 + ty, q = q0 + tx;
+  if (j < k && q < d.N) {
+    const double sg = s.sig[(size_t)c * s.n_cap + j];
+    const bool vec_center = (d.trans != 0) == (u.right != 0);
+    const double f = vec_center ? 1.0 / (sg * sg) : s.fac[c] / sg;
+    store_other_side(b, c, u.k, d, k, q, j, f * acc);
+  }
+}
+
+}  // namespace
+
+// ---- launchers ---------------------------------------------------------
+void launch_theta(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                  int max_chiL, int max_chiR, hipStream_t st) {
+  dim3 grid((max_chiL + 15) / 16, (max_chiR + 15) / 16, b.B);
+  hipLaunchKernelGGL(k_theta, grid, dim3(NT), 0, st, b, s, u);
+}
+
+void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_pad, dim3(16, b.B), dim3(NT), 0, st, b, s, u);
+}
+
+void launch_jacobi_small(const Batch &b, const UpdScratch &s,
+                         const UpdParams &u, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_small, dim3(b.B), dim3(NT), 0, st, b, s, u);
+}
+
+void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_sweep_begin, dim3((B + 255) / 256), dim3(256),
+                     0, st, s, B, sweep);
+}
+
+void launch_jacobi_round(const Batch &b, const UpdScratch &s,
+                         const UpdParams &u, int round, int max_pairs,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_round, dim3(max_pairs, b.B), dim3(NT), 0, st, b,
+                     s, u, round);
+}
+
+void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_truncate, dim3(b.B), dim3(NT), 0, st, b, s, u);
+}
+
+void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                      int max_L, int max_N, int max_k, hipStream_t st) {
+  const int nd = (max_L * max_k + NT - 1) / NT;
+  hipLaunchKernelGGL(k_writeback_direct, dim3(nd, b.B), dim3(NT), 0, st, b, s,
+                     u);
+  dim3 g2((max_N + 15) / 16, (max_k + 15) / 16, b.B);
+  hipLaunchKernelGGL(k_writeback_gemm, g2, dim3(NT), 0, st, b, s, u);
+}
+
+}  // namespace hmps
