@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark of the hybrid METTS-ancilla hot path on one MI355X.
+
+One step = one full sample of every chain of the batch: imaginary-time
+evolution to beta/2 (every Trotter gate and swap with its truncated SVD),
+measurement of every bond, projective collapse of the environment and
+re-initialisation (Markov chain steps 2-4 of Chen & Stoudenmire,
+arXiv:1910.09142).  The default workload is the 2x16 S=1 ladder with
+J_rung = 0.5, W = 2, beta = 5, tau = 0.05, chi_max = 256, cutoff 1e-10 in
+FP64 (one chain); inputs are synthetic (Philox product states).
+
+Prints one JSON line.  `value` counts the two-site Trotter updates (gates
+and swaps; orthogonality-centre moves excluded) per second of the timed
+region, all chains together.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("two-site gate apps/sec at χ=256 (FP64 vs mixed, batched); "
+          "METTS samples/sec")
+UNIT = "two-site gate applications/s"
+FP64_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--workload", default="c3",
+                    choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--chains", type=int, default=None,
+                    help="override the number of chains of the workload")
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="budget of the oracle baseline (0 disables it)")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, seconds):
+    """The FP64 oracle on the same workload: chain 0, seed 0, sample 0,
+    Trotter updates in order until the time budget is spent."""
+    from oracle import model, mps
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()]
+                      or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    lat = model.ladder(wl.L, wl.J_leg, wl.J_rung, W=wl.W)
+    lay = model.layout(lat)
+    sch = model.schedule(lat, lay)
+    M = model.trotter_steps(wl.beta, wl.tau)
+    gates = [model.gate(J, wl.tau / 2.0) for J in sch.couplings]
+    swap = model.swap_gate()
+    psi = mps.init_state(lay, mps.initial_outcomes(lay, wl.seed, 0), 0)
+    st = mps.Stats()
+    t0 = time.perf_counter()
+    n = 0
+    for u in model.evolve_updates(sch, M):
+        if u.op == model.OP_SWAP:
+            mps.apply_update(psi, u.k, swap, False, u.right, wl.chi_max,
+                             wl.cutoff, st)
+        else:
+            mps.apply_update(psi, u.k, gates[u.op], True, u.right,
+                             wl.chi_max, wl.cutoff, st)
+        n += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    total = M * len(sch.step)
+    return {"value": n / dt, "unit": UNIT, "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"first {n} of the {total} Trotter updates of sample 0 "
+                       f"(chain 0, seed {wl.seed}); chi reached "
+                       f"{st.max_chi} of {wl.chi_max}; the rest of the "
+                       "sample runs at larger chi, so this rate is an upper "
+                       "bound for the oracle")}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this path shards independent "
+              "Markov chains over GPUs with no communication, and no run on "
+              "more than one GPU is part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1910_09142_amd import hmps, workloads
+
+    wl = getattr(workloads, args.workload.upper())
+    B = args.chains or wl.n_chains
+    n, bonds, order, mask = workloads.ladder_arrays(wl.L, wl.J_leg,
+                                                    wl.J_rung, wl.W)
+    lat = hmps.Lattice(n, bonds, order, mask)
+    t_start = time.perf_counter()
+
+    def progress(done, total):
+        # one line per Trotter step: evolutions at chi = 256 take minutes
+        print(f"trotter step {done}/{total} "
+              f"({time.perf_counter() - t_start:.1f} s)", file=sys.stderr,
+              flush=True)
+
+    ctx = hmps.Context(B, workloads.mps_length(wl.L, wl.W), wl.chi_max,
+                       len(bonds), progress=progress)
+    ctx.hmps_init_cluster_env(lat, B, wl.seed)
+
+    def one_sample(idx):
+        ctx.hmps_evolve(wl.beta, wl.tau, wl.chi_max, wl.cutoff)
+        m = ctx.hmps_measure()
+        ctx.hmps_collapse_resample(idx % 2)
+        return m
+
+    sample = 0
+    for _ in range(args.warmup):
+        one_sample(sample)
+        sample += 1
+        print(f"warmup sample done", file=sys.stderr, flush=True)
+    s0 = ctx.hmps_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    energies = []
+    for _ in range(args.steps):
+        m = one_sample(sample)
+        energies += m["energy"].tolist()
+        sample += 1
+        print(f"timed sample done ({time.perf_counter() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s1 = ctx.hmps_stats()
+    trotter_updates = ((s1.updates - s0.updates)
+                       - (s1.move_updates - s0.move_updates))
+    gates = s1.gate_updates - s0.gate_updates
+    value = trotter_updates / elapsed
+    launches = s1.round_launches - s0.round_launches
+    svd_s = s1.svd_seconds - s0.svd_seconds
+    svd_f = s1.svd_flops - s0.svd_flops
+    achieved = (svd_f / svd_s / 1e12) if svd_s > 0 else 0.0
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (Philox-seeded product states, ladder Hamiltonian)",
+        "config": {"workload": wl.name, "n_chains": B, "L": wl.L, "W": wl.W,
+                   "J_leg": wl.J_leg, "J_rung": wl.J_rung, "beta": wl.beta,
+                   "tau": wl.tau, "chi_max": wl.chi_max, "cutoff": wl.cutoff,
+                   "samples_per_step": 1, "precision": args.precision},
+        "samples_per_s": B * args.steps / elapsed,
+        "hamiltonian_gates_per_s": gates / elapsed,
+        "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12,
+        "max_chi": s1.max_chi,
+        "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
+        "energy_mean": sum(energies) / len(energies),
+        "roofline": {
+            "bound": "mfma", "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "kernel": "k_jacobi_round",
+            "launches": launches,
+            "avg_launch_us": 1e6 * svd_s / launches if launches else None,
+            "flops_per_launch": svd_f / launches if launches else None,
+        },
+    }
+    ctx.hmps_destroy()
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

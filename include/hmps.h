@@ -67,6 +67,11 @@ typedef struct {
   int32_t precision;       /* HMPS_PREC_*                                 */
   int32_t max_sweeps;      /* Jacobi sweep cap, 0 = default (30)          */
   double jacobi_tol;       /* relative orthogonality tolerance, 0 = auto  */
+  /* Optional: called on the calling thread after every Trotter step of
+   * hmps_evolve with (progress_user, steps done, steps in this call).  It
+   * must not call back into the library with the same context. */
+  void (*progress)(void *user, int64_t done, int64_t total);
+  void *progress_user;
 } hmps_options;
 
 /* Hamiltonian H = sum_b J_b S_{i_b} . S_{j_b} on n_phys spin-1 sites
@@ -96,6 +101,16 @@ typedef struct {
   int64_t sample;           /* index of the current sample               */
   double discarded_weight;  /* sum of relative discarded weights         */
   double evolve_seconds;    /* wall time spent in hmps_evolve            */
+  /* Algorithmic work of the updates applied, summed over chains: per
+   * update 2*9*chiL*chiM*chiR (theta) + 2*81*chiL*chiR (gate) + the
+   * Golub-Reinsch count of a thin SVD with both factors of the L x N
+   * vector matrix, 14 L N^2 + 8 N^3 (L >= N). */
+  double algo_flops;
+  double svd_flops;         /* SVD part of algo_flops for the updates    */
+                            /* that took the blocked (multi-workgroup)   */
+                            /* Jacobi path                               */
+  double svd_seconds;       /* device time (event span) of those rounds  */
+  int64_t round_launches;   /* blocked Jacobi round kernels launched     */
 } hmps_stats_t;
 
 /* Bytes of device workspace needed for the given capacities. */

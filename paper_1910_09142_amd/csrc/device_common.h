@@ -35,17 +35,29 @@ static __device__ __forceinline__ void rr_pair(int r, int i, int n, int &p, int 
   }
 }
 
+// FP64 matrix-core product D(16x16) += A(16x4) B(4x16) of one wavefront.
+// Operand layout on gfx950 (checked on the device): lane i + 16k holds
+// A[i][k]; lane j + 16k holds B[k][j]; lane j + 16 (i % 4) holds D[i][j]
+// in element i / 4.
+typedef double v4d __attribute__((ext_vector_type(4)));
+static __device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // Whether two vectors with squared norms a, b and inner product g still need
-// a rotation.  A vector whose squared norm is below 1e-30 -- absolutely
-// (theta' has norm of order one: the state is normalised before every
-// update) or relative to its partner -- is numerically zero: it lies below
-// the singular-value floor and is always discarded, so it is left alone.
+// a rotation.  A vector whose squared norm is at most `skip` times its
+// partner's (skip <= SIGMA_FLOOR^2), or below 1e-30 absolutely (theta' has
+// norm of order one: the state is normalised before every update), lies
+// below the singular-value floor and is always discarded; rotating it
+// would change its partner's squared norm by less than skip relative, so
+// it is left alone.
 static __device__ __forceinline__ bool pair_needs_rotation(double a, double b,
                                                            double g,
-                                                           double tol) {
+                                                           double tol,
+                                                           double skip) {
   if (g == 0.0 || !(a > 0.0) || !(b > 0.0)) return false;
   const double lo = fmin(a, b), hi = fmax(a, b);
-  if (lo <= 1e-30 || lo <= 1e-30 * hi) return false;
+  if (lo <= 1e-30 || lo <= skip * hi) return false;
   return fabs(g) > tol * sqrt(a) * sqrt(b);
 }
 
@@ -53,9 +65,9 @@ static __device__ __forceinline__ bool pair_needs_rotation(double a, double b,
 // product g orthogonal: (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q).
 // Returns false when they are already orthogonal to relative tolerance tol.
 static __device__ __forceinline__ bool jacobi_rotation(double a, double b, double g,
-                                                double tol, double &c,
-                                                double &s) {
-  if (!pair_needs_rotation(a, b, g, tol)) return false;
+                                                double tol, double skip,
+                                                double &c, double &s) {
+  if (!pair_needs_rotation(a, b, g, tol, skip)) return false;
   const double zeta = (b - a) / (2.0 * g);
   double t;
   if (fabs(zeta) > 1e150)

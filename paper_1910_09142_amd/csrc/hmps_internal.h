@@ -61,6 +61,8 @@ struct UpdParams {
   double tol;         // Jacobi relative orthogonality tolerance
   int max_sweeps;
   int mixed;          // FP32 contraction
+  int inner_sweeps;   // cap on the inner Jacobi sweeps of a block pair
+  double skip;        // relative squared norm below which a vector is zero
 };
 
 // ---- launchers (kernels.hip) -----------------------------------------

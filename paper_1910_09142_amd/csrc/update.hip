@@ -7,7 +7,7 @@
 //                   columns are the vectors the Jacobi SVD orthogonalises
 //   k_pad           zero padding vectors of the blocked Jacobi path
 //   k_jacobi_small  one-sided Jacobi SVD with the whole matrix in LDS
-//   k_jacobi_round  one round of the blocked one-sided Jacobi SVD
+//   (the rounds of the blocked one-sided Jacobi SVD are in jacobi.hip)
 //   k_truncate      sort singular values, choose how many to keep
 //   k_writeback_*   new site tensors from the kept singular triplets
 //
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(NT)
             gg += __shfl_xor(gg, off);
           }
           double cr, sr;
-          if (jacobi_rotation(aa, bb, gg, u.tol, cr, sr)) {
+          if (jacobi_rotation(aa, bb, gg, u.tol, u.skip, cr, sr)) {
             for (int i = lane; i < L; i += g) {
               const double x = xs[p * L + i], y = xs[q * L + i];
               xs[p * L + i] = cr * x - sr * y;
@@ -205,148 +205,6 @@ __global__ void __launch_bounds__(NT)
     if (!converged) s.err[c] = 1;
     s.sweeps[c] += converged ? sweep + 1 : sweep;
   }
-}
-
-__global__ void k_jacobi_sweep_begin(UpdScratch s, int B, int sweep) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= B) return;
-  if (sweep == 0)
-    s.done[c] = 0;
-  else if (s.rot_cur[c] == 0)
-    s.done[c] = 1;
-  s.rot_cur[c] = 0;
-}
-
-// =====================================================================
-// One round of the blocked one-sided Jacobi SVD: one workgroup per pair
-// of JB-vector blocks per chain.  Gram matrix of the 2 JB vectors, its
-// eigenvectors Q by cyclic Jacobi in LDS, then X[:, pair] <- X[:, pair] Q.
-// A pair already orthogonal to tolerance records its squared norms in
-// sig2 instead (in the last sweep every pair does).
-// =====================================================================
-__global__ void __launch_bounds__(NT)
-    k_jacobi_round(Batch b, UpdScratch s, UpdParams u, int r) {
-  const int c = blockIdx.y, pi = blockIdx.x;
-  if (s.done[c]) return;
-  const Dims d = dims_of(b, c, u.k);
-  const int L = d.L, N = d.N;
-  const int NB = n_blocks_even(N);
-  if (r >= NB - 1 || pi >= NB / 2) return;
-  int bi, bj;
-  rr_pair(r, pi, NB, bi, bj);
-  double *X = s.X + (size_t)c * s.th_stride;
-  __shared__ double xs[64][33];
-  __shared__ double G[32][33];
-  __shared__ double Q[32][33];
-  __shared__ double cs[16], sn[16];
-  __shared__ int flag;
-  const int tid = threadIdx.x;
-  const int gi = tid >> 3, gj0 = (tid & 7) * 4;
-  auto colidx = [&](int t) { return t < JB ? bi * JB + t : bj * JB + t - JB; };
-
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int e0 = 0; e0 < L; e0 += 64) {
-#pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      const int idx = tid + NT * h;
-      const int col = idx >> 6, row = idx & 63;
-      xs[row][col] = (e0 + row < L)
-                         ? X[(size_t)colidx(col) * L + e0 + row]
-                         : 0.0;
-    }
-    __syncthreads();
-    for (int row = 0; row < 64; ++row) {
-      const double xi = xs[row][gi];
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) acc[jj] += xi * xs[row][gj0 + jj];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int jj = 0; jj < 4; ++jj) G[gi][gj0 + jj] = acc[jj];
-  if (tid == 0) flag = 0;
-  __syncthreads();
-#pragma unroll
-  for (int jj = 0; jj < 4; ++jj) {
-    const int j = gj0 + jj;
-    if (j != gi && pair_needs_rotation(G[gi][gi], G[j][j], G[gi][j], u.tol))
-      flag = 1;
-  }
-  __syncthreads();
-  if (!flag) {
-    if (tid < 2 * JB) {
-      const int col = colidx(tid);
-      if (col < N) s.sig2[(size_t)c * s.n_cap + col] = G[tid][tid];
-    }
-    return;
-  }
-#pragma unroll
-  for (int jj = 0; jj < 4; ++jj) Q[gi][gj0 + jj] = (gi == gj0 + jj) ? 1.0 : 0.0;
-  __syncthreads();
-
-  // eigenvectors of G by cyclic Jacobi: G <- J^T G J, Q <- Q J
-  const double tol_in = fmax(0.125 * u.tol, 4e-16);
-  for (int isw = 0; isw < 20; ++isw) {
-    if (tid == 0) flag = 0;
-    __syncthreads();
-    for (int rr = 0; rr < 2 * JB - 1; ++rr) {
-      if (tid < JB) {
-        int p, q;
-        rr_pair(rr, tid, 2 * JB, p, q);
-        double cr = 1.0, sr = 0.0;
-        if (jacobi_rotation(G[p][p], G[q][q], G[p][q], tol_in, cr, sr))
-          flag = 1;
-        cs[tid] = cr;
-        sn[tid] = sr;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int idx = tid + NT * h;
-        const int pp = idx >> 5, col = idx & 31;
-        int p, q;
-        rr_pair(rr, pp, 2 * JB, p, q);
-        const double cr = cs[pp], sr = sn[pp];
-        const double x = G[p][col], y = G[q][col];
-        G[p][col] = cr * x - sr * y;
-        G[q][col] = sr * x + cr * y;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int idx = tid + NT * h;
-        const int pp = idx >> 5, row = idx & 31;
-        int p, q;
-        rr_pair(rr, pp, 2 * JB, p, q);
-        const double cr = cs[pp], sr = sn[pp];
-        double x = G[row][p], y = G[row][q];
-        G[row][p] = cr * x - sr * y;
-        G[row][q] = sr * x + cr * y;
-        x = Q[row][p];
-        y = Q[row][q];
-        Q[row][p] = cr * x - sr * y;
-        Q[row][q] = sr * x + cr * y;
-      }
-      __syncthreads();
-    }
-    const int f = flag;
-    __syncthreads();
-    if (!f) break;
-  }
-
-  for (int e = tid; e < L; e += NT) {
-    double xin[2 * JB];
-#pragma unroll
-    for (int t = 0; t < 2 * JB; ++t) xin[t] = X[(size_t)colidx(t) * L + e];
-#pragma unroll 4
-    for (int j = 0; j < 2 * JB; ++j) {
-      double v = 0.0;
-#pragma unroll
-      for (int t = 0; t < 2 * JB; ++t) v += xin[t] * Q[t][j];
-      X[(size_t)colidx(j) * L + e] = v;
-    }
-  }
-  if (tid == 0) atomicAdd(&s.rot_cur[c], 1);
 }
 
 // =====================================================================
@@ -547,19 +405,6 @@ void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,
 void launch_jacobi_small(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, hipStream_t st) {
   hipLaunchKernelGGL(k_jacobi_small, dim3(b.B), dim3(NT), 0, st, b, s, u);
-}
-
-void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_sweep_begin, dim3((B + 255) / 256), dim3(256),
-                     0, st, s, B, sweep);
-}
-
-void launch_jacobi_round(const Batch &b, const UpdScratch &s,
-                         const UpdParams &u, int round, int max_pairs,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_round, dim3(max_pairs, b.B), dim3(NT), 0, st, b,
-                     s, u, round);
 }
 
 void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,

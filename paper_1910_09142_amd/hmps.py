@@ -38,7 +38,11 @@ class hmps_options(C.Structure):
                 ("max_chains", C.c_int32), ("max_sites", C.c_int32),
                 ("chi_cap", C.c_int32), ("max_bonds", C.c_int32),
                 ("precision", C.c_int32), ("max_sweeps", C.c_int32),
-                ("jacobi_tol", C.c_double)]
+                ("jacobi_tol", C.c_double),
+                ("progress", C.c_void_p), ("progress_user", C.c_void_p)]
+
+
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int64, C.c_int64)
 
 
 class hmps_lattice(C.Structure):
@@ -56,7 +60,9 @@ class hmps_stats_t(C.Structure):
                 ("max_chi", C.c_int32), ("n_chains", C.c_int32),
                 ("n_sites", C.c_int32), ("n_env", C.c_int32),
                 ("sample", C.c_int64), ("discarded_weight", C.c_double),
-                ("evolve_seconds", C.c_double)]
+                ("evolve_seconds", C.c_double), ("algo_flops", C.c_double),
+                ("svd_flops", C.c_double), ("svd_seconds", C.c_double),
+                ("round_launches", C.c_int64)]
 
 
 _lib = None
@@ -167,7 +173,7 @@ class Context:
 
     def __init__(self, max_chains, max_sites, chi_cap, max_bonds,
                  precision=PREC_FP64, device=0, stream=None, max_sweeps=0,
-                 jacobi_tol=0.0):
+                 jacobi_tol=0.0, progress=None):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -183,10 +189,15 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(device)
         self.stream = stream
+        # progress(done, total) is called after every Trotter step
+        self._progress = (PROGRESS_FN(lambda _u, d, t: progress(d, t))
+                          if progress is not None else None)
         self.opt = hmps_options(device, C.c_void_p(stream.cuda_stream),
                                 C.c_void_p(base), nbytes, max_chains,
                                 max_sites, chi_cap, max_bonds, precision,
-                                max_sweeps, jacobi_tol)
+                                max_sweeps, jacobi_tol,
+                                C.cast(self._progress, C.c_void_p)
+                                if self._progress else None, None)
         h = C.c_void_p()
         st = lib.hmps_create(C.byref(h), C.byref(self.opt))
         if st:

@@ -73,7 +73,7 @@ def test_workspace_bytes_grows_with_capacity():
 def test_create_rejects_bad_options_without_gpu():
     lib = hmps.load()
     h = ctypes.c_void_p()
-    opt = hmps.hmps_options(0, None, None, 0, 0, 8, 32, 7, 0, 0, 0.0)
+    opt = hmps.hmps_options(0, None, None, 0, 0, 8, 32, 7, 0, 0, 0.0, None, None)
     assert lib.hmps_create(ctypes.byref(h), ctypes.byref(opt)) == hmps.HMPS_E_INVALID
-    opt = hmps.hmps_options(0, None, None, 0, 1, 8, 32, 7, 0, 0, 0.0)
+    opt = hmps.hmps_options(0, None, None, 0, 1, 8, 32, 7, 0, 0, 0.0, None, None)
     assert lib.hmps_create(ctypes.byref(h), ctypes.byref(opt)) == hmps.HMPS_E_NOMEM
