@@ -58,7 +58,10 @@ static __device__ __forceinline__ bool pair_needs_rotation(double a, double b,
   if (g == 0.0 || !(a > 0.0) || !(b > 0.0)) return false;
   const double lo = fmin(a, b), hi = fmax(a, b);
   if (lo <= 1e-30 || lo <= skip * hi) return false;
-  return fabs(g) > tol * sqrt(a) * sqrt(b);
+  // |g| > tol sqrt(a b) without square roots: a, b are squared norms of
+  // columns of theta' (norm of order one) and at least 1e-30 here, so a b
+  // neither overflows nor underflows
+  return g * g > (tol * tol) * (a * b);
 }
 
 // Plane rotation that makes two vectors with squared norms a, b and inner

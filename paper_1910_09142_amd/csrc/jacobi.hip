@@ -50,7 +50,8 @@ __device__ __forceinline__ bool pair_rotation(double a, double b, double g,
   return true;
 }
 
-__global__ void __launch_bounds__(NT)
+// at most 128 registers: four workgroups of this kernel fit on a CU
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
     k_jacobi_round(Batch b, UpdScratch s, UpdParams u, int r) {
   const int c = blockIdx.y, pi = blockIdx.x;
   if (s.done[c]) return;
@@ -76,14 +77,31 @@ __global__ void __launch_bounds__(NT)
     const double *xa = X + (size_t)(ba * JB + li) * L;
     const double *xb = X + (size_t)(bb * JB + li) * L;
     v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-    int e0 = 0;
-    for (; e0 + 8 <= L; e0 += 8) {
-      acc0 = mfma_f64(xa[e0 + lk], xb[e0 + lk], acc0);
-      acc1 = mfma_f64(xa[e0 + 4 + lk], xb[e0 + 4 + lk], acc1);
-    }
-    for (; e0 < L; e0 += 4) {
-      const int e = e0 + lk;
-      acc0 = mfma_f64(e < L ? xa[e] : 0.0, e < L ? xb[e] : 0.0, acc0);
+    // software pipeline: the loads of the next GB k-steps are in flight
+    // while the MFMAs of the current ones run
+    constexpr int GB = 4;
+    double ca[GB], cb[GB], na[GB], nb[GB];
+    auto load = [&](int base, double *va, double *vb) {
+#pragma unroll
+      for (int t = 0; t < GB; ++t) {
+        const int e = base + 4 * t + lk;
+        va[t] = e < L ? xa[e] : 0.0;
+        vb[t] = e < L ? xb[e] : 0.0;
+      }
+    };
+    load(0, ca, cb);
+    for (int e0 = 0; e0 < L; e0 += 4 * GB) {
+      if (e0 + 4 * GB < L) load(e0 + 4 * GB, na, nb);
+#pragma unroll
+      for (int t = 0; t < GB; t += 2) {
+        acc0 = mfma_f64(ca[t], cb[t], acc0);
+        acc1 = mfma_f64(ca[t + 1], cb[t + 1], acc1);
+      }
+#pragma unroll
+      for (int t = 0; t < GB; ++t) {
+        ca[t] = na[t];
+        cb[t] = nb[t];
+      }
     }
     const int ro = (w == 2) ? JB : 0, co = (w == 0) ? 0 : JB;
 #pragma unroll
@@ -171,17 +189,30 @@ __global__ void __launch_bounds__(NT)
   }
 
   // ---- 4. Xp <- Xp Q, as D = Q^T Xp^T per 16-row chunk --------------------
+  // the chunk of rows e0 + 64 is loaded while chunk e0 is multiplied
+  constexpr int KB = P2 / 4;
+  double cur[KB], nxt[KB];
+  auto load_chunk = [&](int e0, double *v) {
+    const int e = e0 + li;
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) {
+      const int t = 4 * kk + lk;
+      const int col = t < JB ? bi * JB + t : bj * JB + t - JB;
+      v[kk] = e < L ? X[(size_t)col * L + e] : 0.0;
+    }
+  };
+  if (16 * w < L) load_chunk(16 * w, cur);
   for (int e0 = 16 * w; e0 < L; e0 += 64) {
+    if (e0 + 64 < L) load_chunk(e0 + 64, nxt);
     v4d d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
     const int e = e0 + li;
 #pragma unroll
-    for (int kk = 0; kk < P2 / 4; ++kk) {
-      const int t = 4 * kk + lk;
-      const int col = t < JB ? bi * JB + t : bj * JB + t - JB;
-      const double bv = e < L ? X[(size_t)col * L + e] : 0.0;
-      d0 = mfma_f64(Q[t][li], bv, d0);
-      d1 = mfma_f64(Q[t][JB + li], bv, d1);
+    for (int kk = 0; kk < KB; ++kk) {
+      d0 = mfma_f64(Q[4 * kk + lk][li], cur[kk], d0);
+      d1 = mfma_f64(Q[4 * kk + lk][JB + li], cur[kk], d1);
     }
+#pragma unroll
+    for (int kk = 0; kk < KB; ++kk) cur[kk] = nxt[kk];
     if (e < L) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
