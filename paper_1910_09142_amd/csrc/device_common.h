@@ -82,6 +82,11 @@ static __device__ __forceinline__ bool jacobi_rotation(double a, double b, doubl
   return true;
 }
 
+// Stride between consecutive vectors of the L x N vector matrix: L rounded
+// up to a multiple of 4, so that four consecutive rows are one aligned
+// 32-byte load.
+static __device__ __forceinline__ int vec_ld(int L) { return (L + 3) & ~3; }
+
 static __device__ __forceinline__ int n_blocks_even(int n) {
   const int nb = (n + JB - 1) / JB;
   return nb + (nb & 1);

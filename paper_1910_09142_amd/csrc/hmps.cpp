@@ -281,7 +281,9 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   const size_t site_cap = 3 * chi2;
   const int mc = 3 * chi_cap;
   const int n_cap = (mc + 2 * JB - 1) / (2 * JB) * (2 * JB);
-  const size_t th_stride = (size_t)mc * n_cap;
+  // vectors of length L <= 3 chi_cap are stored with a stride rounded up to
+  // a multiple of 4 (aligned 32-byte loads of four rows)
+  const size_t th_stride = (size_t)((mc + 3) & ~3) * n_cap;
   const int slots = std::max(2, std::min(std::max(max_bonds, 1), 8));
   hmps_ctx tmp;
   hmps_ctx *t = c ? c : &tmp;

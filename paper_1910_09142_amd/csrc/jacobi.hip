@@ -4,23 +4,26 @@
 //
 // The N vectors (columns of the L x N vector matrix X, column-major) are
 // split into NB (even) blocks of JB.  A sweep has NB-1 rounds; in a round
-// the blocks are paired by the circle method and one workgroup handles
-// one block pair of one chain:
-//   1. Gram matrix G = Xp^T Xp of the 2 JB vectors: wavefronts 0, 1, 2
-//      compute the tiles II, IJ, JJ with FP64 MFMA;
+// the blocks are paired by the circle method and one workgroup of eight
+// wavefronts handles one block pair of one chain:
+//   1. Gram matrix G = Xp^T Xp of the 2 JB vectors: six wavefronts compute
+//      the tiles II, IJ, JJ over alternate 16-row chunks (FP64 MFMA fed by
+//      coalesced 32-byte loads, software-pipelined), summed in LDS in a
+//      fixed order;
 //   2. if every off-diagonal element is below tol sqrt(G_ii G_jj) the pair
 //      is orthogonal: record the squared norms and stop;
 //   3. one cyclic two-sided Jacobi sweep on G in LDS accumulating the
-//      rotations in Q (one thread per 2 x 2 block of a rotation round, in
-//      place);
-//   4. Xp <- Xp Q (FP64 MFMA, 16-row chunks, coalesced stores).
-// About 17 KB of LDS per workgroup, so many chains' block pairs share a CU.
+//      rotations in Q (one thread per 2 x 2 block of G and per (row,
+//      column pair) item of Q, in place);
+//   4. Xp <- Xp Q (FP64 MFMA, 16-row chunks over eight wavefronts,
+//      coalesced stores).
 #include "device_common.h"
 
 namespace hmps {
 namespace {
 using namespace dev;
 
+constexpr int RT = 512;     // threads of the round kernel (8 wavefronts)
 constexpr int P2 = 2 * JB;  // vectors in a block pair
 constexpr int NPAIR = JB;   // disjoint pairs in one inner rotation round
 
@@ -50,8 +53,8 @@ __device__ __forceinline__ bool pair_rotation(double a, double b, double g,
   return true;
 }
 
-// at most 128 registers: four workgroups of this kernel fit on a CU
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+// at most 128 registers: two workgroups of this kernel fit on a CU
+__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     k_jacobi_round(Batch b, UpdScratch s, UpdParams u, int r) {
   const int c = blockIdx.y, pi = blockIdx.x;
   if (s.done[c]) return;
@@ -60,69 +63,88 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
   const int L = m > n ? m : n, N = m > n ? n : m;
   const int NB = n_blocks_even(N);
   if (r >= NB - 1 || pi >= NB / 2) return;
+  const int ld = vec_ld(L);
   int bi, bj;
   rr_pair(r, pi, NB, bi, bj);
   double *X = s.X + (size_t)c * s.th_stride;
 
   __shared__ double G[P2][P2 + 1];
-  __shared__ double Q[P2][P2 + 1];
+  // partial Gram tiles [row half][tile][16][16]; reused as Q afterwards
+  __shared__ double scratch[2 * 3 * JB * JB];
+  double (*Q)[P2 + 1] = reinterpret_cast<double (*)[P2 + 1]>(scratch);
+  static_assert(P2 * (P2 + 1) <= 2 * 3 * JB * JB, "Q fits in the scratch");
   __shared__ double cs[NPAIR], sn[NPAIR];
   __shared__ int flag;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
 
-  // ---- 1. Gram tiles: wave 0 = II, 1 = IJ, 2 = JJ; wave 3 sets Q = I ----
-  if (w < 3) {
-    const int ba = (w == 2) ? bj : bi, bb = (w == 0) ? bi : bj;
-    const double *xa = X + (size_t)(ba * JB + li) * L;
-    const double *xb = X + (size_t)(bb * JB + li) * L;
+  // ---- 1. Gram tiles: wave w < 6 computes tile w % 3 (II, IJ, JJ) over
+  //         the groups of k-steps of parity w / 3 ----------------------------
+  if (w < 6) {
+    const int tile = w % 3, half = w / 3;
+    const int ba = (tile == 2) ? bj : bi, bb = (tile == 0) ? bi : bj;
+    const double *xa = X + (size_t)(ba * JB + li) * ld;
+    const double *xb = X + (size_t)(bb * JB + li) * ld;
     v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-    // software pipeline: the loads of the next GB k-steps are in flight
-    // while the MFMAs of the current ones run
-    constexpr int GB = 4;
-    double ca[GB], cb[GB], na[GB], nb[GB];
-    auto load = [&](int base, double *va, double *vb) {
-#pragma unroll
-      for (int t = 0; t < GB; ++t) {
-        const int e = base + 4 * t + lk;
-        va[t] = e < L ? xa[e] : 0.0;
-        vb[t] = e < L ? xb[e] : 0.0;
+    // Chunks of 16 rows: lane (li, lk) reads rows e0 + 4 lk .. e0 + 4 lk + 3
+    // of its column as one aligned 32-byte load, and MFMA step t takes row
+    // e0 + 4 lk + t (the Gram sums over rows, so the row order is free).
+    // The wave of parity `half` takes chunks half, half + 2, ...; the next
+    // chunk is loaded while the current one is multiplied.  Rows L..ld-1
+    // are zero.
+    double4 ca, cb, na, nb;
+    auto load = [&](int e0, double4 &va, double4 &vb) {
+      const int e = e0 + 4 * lk;
+      if (e < ld) {
+        va = *reinterpret_cast<const double4 *>(xa + e);
+        vb = *reinterpret_cast<const double4 *>(xb + e);
+      } else {
+        va = make_double4(0.0, 0.0, 0.0, 0.0);
+        vb = va;
       }
     };
-    load(0, ca, cb);
-    for (int e0 = 0; e0 < L; e0 += 4 * GB) {
-      if (e0 + 4 * GB < L) load(e0 + 4 * GB, na, nb);
-#pragma unroll
-      for (int t = 0; t < GB; t += 2) {
-        acc0 = mfma_f64(ca[t], cb[t], acc0);
-        acc1 = mfma_f64(ca[t + 1], cb[t + 1], acc1);
-      }
-#pragma unroll
-      for (int t = 0; t < GB; ++t) {
-        ca[t] = na[t];
-        cb[t] = nb[t];
-      }
+    int e0 = 16 * half;
+    if (e0 < L) load(e0, ca, cb);
+    for (; e0 < L; e0 += 32) {
+      if (e0 + 32 < L) load(e0 + 32, na, nb);
+      acc0 = mfma_f64(ca.x, cb.x, acc0);
+      acc1 = mfma_f64(ca.y, cb.y, acc1);
+      acc0 = mfma_f64(ca.z, cb.z, acc0);
+      acc1 = mfma_f64(ca.w, cb.w, acc1);
+      ca = na;
+      cb = nb;
     }
-    const int ro = (w == 2) ? JB : 0, co = (w == 0) ? 0 : JB;
+    double *part = scratch + (half * 3 + tile) * JB * JB;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = lk + 4 * q;
-      const double v = acc0[q] + acc1[q];
-      G[ro + i][co + li] = v;
-      if (w == 1) G[JB + li][i] = v;  // G_JI = G_IJ^T
+    for (int q = 0; q < 4; ++q)
+      part[(lk + 4 * q) * JB + li] = acc0[q] + acc1[q];
+  } else if (tid == 6 * 64) {
+    flag = 0;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < P2 * P2; idx += RT) {
+    const int i = idx / P2, j = idx % P2;
+    int t, a, bb;
+    if (i < JB && j < JB) {
+      t = 0; a = i; bb = j;
+    } else if (i < JB) {
+      t = 1; a = i; bb = j - JB;
+    } else if (j < JB) {
+      t = 1; a = j; bb = i - JB;   // G_JI = G_IJ^T
+    } else {
+      t = 2; a = i - JB; bb = j - JB;
     }
-  } else {
-    for (int idx = lane; idx < P2 * P2; idx += 64)
-      Q[idx / P2][idx % P2] = (idx / P2 == idx % P2) ? 1.0 : 0.0;
-    if (lane == 0) flag = 0;
+    G[i][j] = scratch[t * JB * JB + a * JB + bb] +
+              scratch[(3 + t) * JB * JB + a * JB + bb];
   }
   __syncthreads();
 
-  // ---- 2. convergence test -----------------------------------------------
-  for (int idx = tid; idx < P2 * P2; idx += NT) {
+  // ---- 2. convergence test; Q = I over the consumed partials -------------
+  for (int idx = tid; idx < P2 * P2; idx += RT) {
     const int i = idx / P2, j = idx % P2;
     if (i < j && pair_needs_rotation(G[i][i], G[j][j], G[i][j], u.tol, u.skip))
       flag = 1;
+    Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int needs_rotation = flag;
@@ -136,10 +158,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
   }
 
   // ---- 3. inner Jacobi sweeps on G, rotations accumulated in Q ------------
-  // Thread t owns the 2 x 2 block (row pair t / NPAIR, column pair
-  // t % NPAIR) of G and two (row, column pair) items of Q; every element
-  // belongs to exactly one owner, so the update is in place.
-  const int rp = tid / NPAIR, cp = tid % NPAIR;
+  // Threads t < 256 own the 2 x 2 block (row pair t / NPAIR, column pair
+  // t % NPAIR) of G; every thread owns one (row, column pair) item of Q.
+  // Every element has exactly one owner, so the update is in place.
+  const int rp = (tid & 255) / NPAIR, cp = tid % NPAIR;
+  const int qrow = tid / NPAIR;
   const double tol_in = fmax(0.125 * u.tol, 4e-16);
   for (int isw = 0; isw < u.inner_sweeps; ++isw) {
     if (tid == 0) flag = 0;
@@ -154,7 +177,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
         sn[tid] = sr;
       }
       __syncthreads();
-      {
+      if (tid < NPAIR * NPAIR) {
         int p1, q1, p2, q2;
         rr_pair(rr, rp, P2, p1, q1);
         rr_pair(rr, cp, P2, p2, q2);
@@ -170,16 +193,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
         G[q1][p2] = c2 * h21 - s2 * h22;
         G[q1][q2] = s2 * h21 + c2 * h22;
       }
-#pragma unroll
-      for (int h = 0; h < P2 * NPAIR / NT; ++h) {
-        const int item = tid + NT * h;
-        const int row = item / NPAIR, pq = item % NPAIR;
+      {
         int p, q;
-        rr_pair(rr, pq, P2, p, q);
-        const double cq = cs[pq], sq = sn[pq];
-        const double x = Q[row][p], y = Q[row][q];
-        Q[row][p] = cq * x - sq * y;
-        Q[row][q] = sq * x + cq * y;
+        rr_pair(rr, cp, P2, p, q);
+        const double cq = cs[cp], sq = sn[cp];
+        const double x = Q[qrow][p], y = Q[qrow][q];
+        Q[qrow][p] = cq * x - sq * y;
+        Q[qrow][q] = sq * x + cq * y;
       }
       __syncthreads();
     }
@@ -189,7 +209,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
   }
 
   // ---- 4. Xp <- Xp Q, as D = Q^T Xp^T per 16-row chunk --------------------
-  // the chunk of rows e0 + 64 is loaded while chunk e0 is multiplied
+  // each wave takes every eighth chunk; the next chunk is loaded while the
+  // current one is multiplied
   constexpr int KB = P2 / 4;
   double cur[KB], nxt[KB];
   auto load_chunk = [&](int e0, double *v) {
@@ -198,12 +219,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
     for (int kk = 0; kk < KB; ++kk) {
       const int t = 4 * kk + lk;
       const int col = t < JB ? bi * JB + t : bj * JB + t - JB;
-      v[kk] = e < L ? X[(size_t)col * L + e] : 0.0;
+      v[kk] = e < L ? X[(size_t)col * ld + e] : 0.0;
     }
   };
+  constexpr int CSTEP = 16 * (RT / 64);
   if (16 * w < L) load_chunk(16 * w, cur);
-  for (int e0 = 16 * w; e0 < L; e0 += 64) {
-    if (e0 + 64 < L) load_chunk(e0 + 64, nxt);
+  for (int e0 = 16 * w; e0 < L; e0 += CSTEP) {
+    if (e0 + CSTEP < L) load_chunk(e0 + CSTEP, nxt);
     v4d d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
     const int e = e0 + li;
 #pragma unroll
@@ -217,8 +239,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int jo = lk + 4 * q;
-        X[(size_t)(bi * JB + jo) * L + e] = d0[q];
-        X[(size_t)(bj * JB + jo) * L + e] = d1[q];
+        X[(size_t)(bi * JB + jo) * ld + e] = d0[q];
+        X[(size_t)(bj * JB + jo) * ld + e] = d1[q];
       }
     }
   }
@@ -236,7 +258,7 @@ void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
 void launch_jacobi_round(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, int round, int max_pairs,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_round, dim3(max_pairs, b.B), dim3(NT), 0, st, b,
+  hipLaunchKernelGGL(k_jacobi_round, dim3(max_pairs, b.B), dim3(RT), 0, st, b,
                      s, u, round);
 }
 

@@ -25,6 +25,7 @@ using namespace dev;
 
 struct Dims {
   int chiL, chiM, chiR, m, n, L, N, trans;
+  int ld;  // vector stride in X and TH: L rounded up to a multiple of 4
 };
 
 __device__ __forceinline__ Dims dims_of(const Batch &b, int c, int k) {
@@ -38,6 +39,7 @@ __device__ __forceinline__ Dims dims_of(const Batch &b, int c, int k) {
   d.trans = d.n > d.m;
   d.L = d.trans ? d.n : d.m;
   d.N = d.trans ? d.m : d.n;
+  d.ld = vec_ld(d.L);
   return d;
 }
 
@@ -110,7 +112,7 @@ __global__ void __launch_bounds__(NT)
 #pragma unroll
         for (int t = 0; t < 9; ++t) v += G[(s1 * 3 + s2) * 9 + t] * acc[t];
         const size_t row = (size_t)s1 * chiL + a, col = (size_t)s2 * chiR + cc;
-        const size_t off = d.trans ? row * d.n + col : col * d.m + row;
+        const size_t off = d.trans ? row * d.ld + col : col * d.ld + row;
         TH[off] = v;
         X[off] = v;
       }
@@ -118,16 +120,23 @@ __global__ void __launch_bounds__(NT)
   }
 }
 
-// Zero the padding vectors N..npad-1 of the blocked Jacobi path.
+// Zero what the blocked Jacobi path reads beyond theta': the padding rows
+// L..ld-1 of every vector and the padding vectors N..npad-1.
 __global__ void __launch_bounds__(NT) k_pad(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.y;
   const Dims d = dims_of(b, c, u.k);
   const int npad = n_blocks_even(d.N) * JB;
-  const size_t cnt = (size_t)(npad - d.N) * d.L;
-  double *X = s.X + (size_t)c * s.th_stride + (size_t)d.N * d.L;
+  double *X = s.X + (size_t)c * s.th_stride;
+  const int tail = d.ld - d.L;
+  if (tail > 0)
+    for (int i = blockIdx.x * NT + threadIdx.x; i < d.N * tail;
+         i += gridDim.x * NT)
+      X[(size_t)(i / tail) * d.ld + d.L + i % tail] = 0.0;
+  const size_t cnt = (size_t)(npad - d.N) * d.ld;
+  double *P = X + (size_t)d.N * d.ld;
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < cnt;
        i += (size_t)gridDim.x * NT)
-    X[i] = 0.0;
+    P[i] = 0.0;
 }
 
 // =====================================================================
@@ -145,7 +154,8 @@ __global__ void __launch_bounds__(NT)
   __shared__ double xs[SMALL_LDS];
   __shared__ int flag;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < L * N; idx += NT) xs[idx] = X[idx];
+  for (int idx = tid; idx < L * N; idx += NT)
+    xs[idx] = X[(size_t)(idx / L) * d.ld + idx % L];
   const int n_even = N + (N & 1);
   const int npairs = n_even / 2;
   int g = 64;
@@ -194,7 +204,8 @@ __global__ void __launch_bounds__(NT)
       break;
     }
   }
-  for (int idx = tid; idx < L * N; idx += NT) X[idx] = xs[idx];
+  for (int idx = tid; idx < L * N; idx += NT)
+    X[(size_t)(idx / L) * d.ld + idx % L] = xs[idx];
   double *sig2 = s.sig2 + (size_t)c * s.n_cap;
   for (int j = tid; j < N; j += NT) {
     double v = 0.0;
@@ -349,7 +360,7 @@ __global__ void __launch_bounds__(NT)
   const bool vec_center = (d.trans != 0) == (u.right != 0);
   const double f =
       vec_center ? s.fac[c] : 1.0 / s.sig[(size_t)c * s.n_cap + j];
-  const double v = s.X[(size_t)c * s.th_stride + (size_t)col * d.L + l] * f;
+  const double v = s.X[(size_t)c * s.th_stride + (size_t)col * d.ld + l] * f;
   store_vector_side(b, c, u.k, d, k, l, j, v);
 }
 
@@ -370,9 +381,10 @@ __global__ void __launch_bounds__(NT)
   const int pj = (j0 + ty < k) ? perm[j0 + ty] : -1;
   double acc = 0.0;
   for (int i0 = 0; i0 < L; i0 += 16) {
-    As[ty][tx] = (pj >= 0 && i0 + tx < L) ? X[(size_t)pj * L + i0 + tx] : 0.0;
+    As[ty][tx] =
+        (pj >= 0 && i0 + tx < L) ? X[(size_t)pj * d.ld + i0 + tx] : 0.0;
     Bs[tx][ty] = (q0 + ty < d.N && i0 + tx < L)
-                     ? TH[(size_t)(q0 + ty) * L + i0 + tx]
+                     ? TH[(size_t)(q0 + ty) * d.ld + i0 + tx]
                      : 0.0;
     __syncthreads();
 #pragma unroll
