@@ -87,10 +87,6 @@ static __device__ __forceinline__ bool jacobi_rotation(double a, double b, doubl
 // 32-byte load.
 static __device__ __forceinline__ int vec_ld(int L) { return (L + 3) & ~3; }
 
-static __device__ __forceinline__ int n_blocks_even(int n) {
-  const int nb = (n + JB - 1) / JB;
-  return nb + (nb & 1);
-}
 
 // Sum over the workgroup; every thread gets the result.
 static __device__ double wg_sum(double v, double *red) {

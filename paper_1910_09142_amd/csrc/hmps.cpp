@@ -280,6 +280,7 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   const size_t chi2 = (size_t)chi_cap * chi_cap;
   const size_t site_cap = 3 * chi2;
   const int mc = 3 * chi_cap;
+  // padded vector count: an even number of blocks of JB vectors
   const int n_cap = (mc + 2 * JB - 1) / (2 * JB) * (2 * JB);
   // vectors of length L <= 3 chi_cap are stored with a stride rounded up to
   // a multiple of 4 (aligned 32-byte loads of four rows)
@@ -425,9 +426,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
     const int nvec = 3 * std::min(row[k], row[k + 2]);
     max_vlen = std::max(max_vlen, 3 * std::max(row[k], row[k + 2]));
     max_nvec = std::max(max_nvec, nvec);
-    int nb = (nvec + JB - 1) / JB;
-    nb += nb & 1;
-    max_nb = std::max(max_nb, nb);
+    max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
   }
   const bool is_move = (op == OP_IDENT);
   UpdParams u;

@@ -1,5 +1,5 @@
 // Internal interface between the host orchestration (hmps.cpp) and the
-// gfx950 kernels (kernels.hip).  Not part of the public ABI.
+// gfx950 kernels (update.hip, jacobi.hip, observe.hip).  Not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -8,8 +8,13 @@
 namespace hmps {
 
 // Jacobi column-block width of the large-matrix SVD path; a block pair is
-// 2*JB columns.
+// 2 JB vectors.
 constexpr int JB = 16;
+// Number of column blocks, rounded up to an even count.
+__host__ __device__ inline int n_blocks_even(int nvec, int jb) {
+  const int nb = (nvec + jb - 1) / jb;
+  return nb + (nb & 1);
+}
 // Largest m * n_even (doubles) handled by the single-workgroup SVD whose
 // matrix lives entirely in LDS.
 constexpr int SMALL_LDS = 18432;
@@ -65,7 +70,7 @@ struct UpdParams {
   double skip;        // relative squared norm below which a vector is zero
 };
 
-// ---- launchers (kernels.hip) -----------------------------------------
+// ---- launchers (update.hip, jacobi.hip, observe.hip) -----------------------------------------
 void launch_theta(const Batch &b, const UpdScratch &s, const UpdParams &u,
                   int max_chiL, int max_chiR, hipStream_t st);
 void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,

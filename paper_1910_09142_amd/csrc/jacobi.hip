@@ -2,19 +2,19 @@
 // (the SVD that restores the MPS form after every two-site gate;
 // Chen & Stoudenmire, arXiv:1910.09142, Results section).
 //
-// The N vectors (columns of the L x N vector matrix X, column-major) are
-// split into NB (even) blocks of JB.  A sweep has NB-1 rounds; in a round
-// the blocks are paired by the circle method and one workgroup of eight
-// wavefronts handles one block pair of one chain:
-//   1. Gram matrix G = Xp^T Xp of the 2 JB vectors: six wavefronts compute
-//      the tiles II, IJ, JJ over alternate 16-row chunks (FP64 MFMA fed by
-//      coalesced 32-byte loads, software-pipelined), summed in LDS in a
-//      fixed order;
+// The N vectors (columns of the L x N vector matrix X, stride ld, column-
+// major) are split into NB (even) blocks of JB = 16 vectors.  A sweep has
+// NB-1 rounds;
+// in a round the blocks are paired by the circle method and one workgroup
+// of eight wavefronts handles one block pair of one chain:
+//   1. Gram matrix G = Xp^T Xp of the 2 JB vectors, in 16 x 16 tiles
+//      (FP64 MFMA fed by coalesced 32-byte loads of four rows), summed in
+//      LDS in a fixed order;
 //   2. if every off-diagonal element is below tol sqrt(G_ii G_jj) the pair
 //      is orthogonal: record the squared norms and stop;
 //   3. one cyclic two-sided Jacobi sweep on G in LDS accumulating the
-//      rotations in Q (one thread per 2 x 2 block of G and per (row,
-//      column pair) item of Q, in place);
+//      rotations in Q (each 2 x 2 block of a rotation round of G, and each
+//      (row, column pair) item of Q, has one owner: in place);
 //   4. Xp <- Xp Q (FP64 MFMA, 16-row chunks over eight wavefronts,
 //      coalesced stores).
 #include "device_common.h"
@@ -23,9 +23,7 @@ namespace hmps {
 namespace {
 using namespace dev;
 
-constexpr int RT = 512;     // threads of the round kernel (8 wavefronts)
-constexpr int P2 = 2 * JB;  // vectors in a block pair
-constexpr int NPAIR = JB;   // disjoint pairs in one inner rotation round
+constexpr int RT = 512;  // threads of the round kernel (8 wavefronts)
 
 __global__ void k_jacobi_sweep_begin(UpdScratch s, int B, int sweep) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -38,22 +36,83 @@ __global__ void k_jacobi_sweep_begin(UpdScratch s, int B, int sweep) {
 }
 
 // Rotation (x_p, x_q) <- (c x_p - s x_q, s x_p + c x_q) that zeroes the
-// inner product g of two vectors with squared norms a, b (the same angle
-// as tan 2phi = 2g / (b - a), smaller root), written with one square root,
-// one division and one reciprocal square root.
+// inner product g of two vectors with squared norms a, b: the smaller root
+// t = tan(phi) of tan(2 phi) = 2g / (b - a), then c = 1 / sqrt(1 + t^2),
+// s = c t.  The square root and the reciprocal behind t come from the
+// hardware estimates refined by Newton steps (t only has to be close to
+// the optimal angle); c is refined to rounding accuracy, so c^2 + s^2 = 1
+// holds to rounding for the t actually used.
+__device__ __forceinline__ double rsqrt_newton(double x, int steps) {
+  double y = __builtin_amdgcn_rsq(x);
+  for (int i = 0; i < steps; ++i) {
+    const double e = fma(-x * y, y, 1.0);  // 1 - x y^2
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
 __device__ __forceinline__ bool pair_rotation(double a, double b, double g,
                                               double tol, double skip,
                                               double &c, double &s) {
   if (!pair_needs_rotation(a, b, g, tol, skip)) return false;
   const double d = b - a;
-  const double r = sqrt(d * d + 4.0 * g * g);
-  const double t = copysign(1.0, d) * (2.0 * g) / (fabs(d) + r);
-  c = rsqrt(1.0 + t * t);
+  const double x = fma(d, d, 4.0 * g * g);
+  const double r = x * rsqrt_newton(x, 2);  // sqrt(d^2 + 4 g^2)
+  const double den = fabs(d) + r;
+  double inv = __builtin_amdgcn_rcp(den);
+  inv = fma(inv, fma(-den, inv, 1.0), inv);
+  inv = fma(inv, fma(-den, inv, 1.0), inv);
+  const double t = copysign(1.0, d) * (2.0 * g * inv);
+  c = rsqrt_newton(fma(t, t, 1.0), 3);
   s = c * t;
   return true;
 }
 
-// at most 128 registers: two workgroups of this kernel fit on a CU
+// Slot of index x in round r of the circle-method pairing over n indices
+// (the inverse of rr_pair): pair i, and the partner of x in that pair.
+__device__ __forceinline__ void rr_slot(int r, int x, int n, int &i,
+                                        int &partner) {
+  const int mod = n - 1;
+  if (x == n - 1) {
+    i = 0;
+    partner = r;
+    return;
+  }
+  if (x == r) {
+    i = 0;
+    partner = n - 1;
+    return;
+  }
+  int d = x - r;
+  if (d < 0) d += mod;  // x = (r + d) mod (n - 1)
+  if (d <= (mod - 1) / 2) {
+    i = d;
+    partner = r - d < 0 ? r - d + mod : r - d;
+  } else {
+    i = mod - d;
+    partner = r + i >= mod ? r + i - mod : r + i;
+  }
+}
+
+// One 2 x 2 block of J^T G J: rows (p1, q1) rotated by (c1, s1), columns
+// (p2, q2) by (c2, s2); g and n are row-major [row][column].
+__device__ __forceinline__ void rot_block(double c1, double s1, double c2,
+                                          double s2, const double g[4],
+                                          double n[4]) {
+  const double h11 = c1 * g[0] - s1 * g[2], h12 = c1 * g[1] - s1 * g[3];
+  const double h21 = s1 * g[0] + c1 * g[2], h22 = s1 * g[1] + c1 * g[3];
+  n[0] = c2 * h11 - s2 * h12;
+  n[1] = s2 * h11 + c2 * h12;
+  n[2] = c2 * h21 - s2 * h22;
+  n[3] = s2 * h21 + c2 * h22;
+}
+
+constexpr int P2 = 2 * JB;             // vectors in a block pair
+constexpr int NPAIR = JB;              // disjoint pairs per rotation round
+constexpr int NTILE = 3;               // upper Gram tiles: II, IJ, JJ
+constexpr int NWAVE = RT / 64;
+constexpr int NSLOT = 4;               // partial Gram sets summed in LDS
+static_assert(P2 == 32 && RT == 512, "tiling assumes 16-wide blocks");
+
 __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     k_jacobi_round(Batch b, UpdScratch s, UpdParams u, int r) {
   const int c = blockIdx.y, pi = blockIdx.x;
@@ -61,37 +120,58 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   const int32_t *chi = chi_row(b, c);
   const int m = 3 * chi[u.k], n = 3 * chi[u.k + 2];
   const int L = m > n ? m : n, N = m > n ? n : m;
-  const int NB = n_blocks_even(N);
+  const int NB = n_blocks_even(N, JB);
   if (r >= NB - 1 || pi >= NB / 2) return;
   const int ld = vec_ld(L);
   int bi, bj;
   rr_pair(r, pi, NB, bi, bj);
   double *X = s.X + (size_t)c * s.th_stride;
+  auto colidx = [&](int t) { return t < JB ? bi * JB + t : bj * JB + t - JB; };
 
-  __shared__ double G[P2][P2 + 1];
-  // partial Gram tiles [row half][tile][16][16]; reused as Q afterwards
-  __shared__ double scratch[2 * 3 * JB * JB];
+  // G is double-buffered: rotation round k reads G[k & 1] and writes
+  // G[(k + 1) & 1], so nothing read in a round is overwritten in it
+  __shared__ double G[2][P2][P2 + 1];
+  // partial Gram tiles, reused as Q once they are summed into G
+  __shared__ double scratch[NSLOT * NTILE * 256];
   double (*Q)[P2 + 1] = reinterpret_cast<double (*)[P2 + 1]>(scratch);
-  static_assert(P2 * (P2 + 1) <= 2 * 3 * JB * JB, "Q fits in the scratch");
-  __shared__ double cs[NPAIR], sn[NPAIR];
-  __shared__ int flag;
+  __shared__ double cs[2][NPAIR], sn[2][NPAIR];
+  __shared__ int flag[2];
+  // per rotation round rr and pair t of round rr + 1: where that pair's
+  // three Gram entries sit in round rr (see step 3), packed as bytes
+  __shared__ uint2 look[P2 - 1][NPAIR];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
 
-  // ---- 1. Gram tiles: wave w < 6 computes tile w % 3 (II, IJ, JJ) over
-  //         the groups of k-steps of parity w / 3 ----------------------------
-  if (w < 6) {
-    const int tile = w % 3, half = w / 3;
-    const int ba = (tile == 2) ? bj : bi, bb = (tile == 0) ? bi : bj;
-    const double *xa = X + (size_t)(ba * JB + li) * ld;
-    const double *xb = X + (size_t)(bb * JB + li) * ld;
-    v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-    // Chunks of 16 rows: lane (li, lk) reads rows e0 + 4 lk .. e0 + 4 lk + 3
-    // of its column as one aligned 32-byte load, and MFMA step t takes row
-    // e0 + 4 lk + t (the Gram sums over rows, so the row order is free).
-    // The wave of parity `half` takes chunks half, half + 2, ...; the next
-    // chunk is loaded while the current one is multiplied.  Rows L..ld-1
-    // are zero.
+  // ---- 1. Gram matrix -----------------------------------------------------
+  // Wave w takes every eighth chunk of 16 rows.  Lane (li, lk) loads rows
+  // e0 + 4 lk .. e0 + 4 lk + 3 of vector li of both blocks as aligned
+  // 32-byte loads; MFMA step q takes row e0 + 4 lk + q of both operands
+  // (the Gram sums over rows, so their order is free) and the three upper
+  // tiles are accumulated from the same loads.  Rows L..ld-1 are zero.
+  if (tid == 0) {
+    flag[0] = 0;
+    flag[1] = 0;
+  }
+  for (int e = tid; e < (P2 - 1) * NPAIR; e += RT) {
+    const int rr = e / NPAIR, t = e % NPAIR;
+    const int rn = rr + 1 < P2 - 1 ? rr + 1 : 0;
+    int pn, qn, ia, pa, ib, pb;
+    rr_pair(rn, t, P2, pn, qn);
+    rr_slot(rr, pn, P2, ia, pa);
+    rr_slot(rr, qn, P2, ib, pb);
+    const int ra = pn < pa ? 0 : 1, rb = qn < pb ? 0 : 1;
+    const unsigned a0 = ra ? pa : pn, a1 = ra ? pn : pa;
+    const unsigned b0 = rb ? pb : qn, b1 = rb ? qn : pb;
+    look[rr][t] = make_uint2(a0 | a1 << 8 | b0 << 16 | b1 << 24,
+                             ia | ib << 8 | ra << 16 | rb << 24);
+  }
+  {
+    constexpr int CSTEP = 16 * NWAVE;
+    v4d acc[NTILE];
+#pragma unroll
+    for (int t = 0; t < NTILE; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    const double *xa = X + (size_t)colidx(li) * ld;
+    const double *xb = X + (size_t)colidx(JB + li) * ld;
     double4 ca, cb, na, nb;
     auto load = [&](int e0, double4 &va, double4 &vb) {
       const int e = e0 + 4 * lk;
@@ -103,126 +183,174 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
         vb = va;
       }
     };
-    int e0 = 16 * half;
+    int e0 = 16 * w;
     if (e0 < L) load(e0, ca, cb);
-    for (; e0 < L; e0 += 32) {
-      if (e0 + 32 < L) load(e0 + 32, na, nb);
-      acc0 = mfma_f64(ca.x, cb.x, acc0);
-      acc1 = mfma_f64(ca.y, cb.y, acc1);
-      acc0 = mfma_f64(ca.z, cb.z, acc0);
-      acc1 = mfma_f64(ca.w, cb.w, acc1);
+    for (; e0 < L; e0 += CSTEP) {
+      if (e0 + CSTEP < L) load(e0 + CSTEP, na, nb);
+      acc[0] = mfma_f64(ca.x, ca.x, acc[0]);
+      acc[1] = mfma_f64(ca.x, cb.x, acc[1]);
+      acc[2] = mfma_f64(cb.x, cb.x, acc[2]);
+      acc[0] = mfma_f64(ca.y, ca.y, acc[0]);
+      acc[1] = mfma_f64(ca.y, cb.y, acc[1]);
+      acc[2] = mfma_f64(cb.y, cb.y, acc[2]);
+      acc[0] = mfma_f64(ca.z, ca.z, acc[0]);
+      acc[1] = mfma_f64(ca.z, cb.z, acc[1]);
+      acc[2] = mfma_f64(cb.z, cb.z, acc[2]);
+      acc[0] = mfma_f64(ca.w, ca.w, acc[0]);
+      acc[1] = mfma_f64(ca.w, cb.w, acc[1]);
+      acc[2] = mfma_f64(cb.w, cb.w, acc[2]);
       ca = na;
       cb = nb;
     }
-    double *part = scratch + (half * 3 + tile) * JB * JB;
+    // fixed-order sum of the eight wave partials: step j adds waves
+    // 4 j .. 4 j + 3 into slots 0 .. 3
+    double *part = scratch + (w % NSLOT) * NTILE * 256;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      part[(lk + 4 * q) * JB + li] = acc0[q] + acc1[q];
-  } else if (tid == 6 * 64) {
-    flag = 0;
+    for (int step = 0; step < NWAVE / NSLOT; ++step) {
+      if (w / NSLOT == step) {
+#pragma unroll
+        for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double *dst = part + t * 256 + (lk + 4 * q) * 16 + li;
+            *dst = step == 0 ? acc[t][q] : *dst + acc[t][q];
+          }
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
+  // G from the upper tiles (tile 0: II, 1: IJ, 2: JJ); the lower triangle
+  // mirrors the upper one
   for (int idx = tid; idx < P2 * P2; idx += RT) {
     const int i = idx / P2, j = idx % P2;
-    int t, a, bb;
-    if (i < JB && j < JB) {
-      t = 0; a = i; bb = j;
-    } else if (i < JB) {
-      t = 1; a = i; bb = j - JB;
-    } else if (j < JB) {
-      t = 1; a = j; bb = i - JB;   // G_JI = G_IJ^T
-    } else {
-      t = 2; a = i - JB; bb = j - JB;
-    }
-    G[i][j] = scratch[t * JB * JB + a * JB + bb] +
-              scratch[(3 + t) * JB * JB + a * JB + bb];
+    const int a = i < j ? i : j, bb = i < j ? j : i;
+    const int tile = (a >> 4) + (bb >> 4);
+    const double *src = scratch + tile * 256 + (a & 15) * 16 + (bb & 15);
+    double v = src[0];
+#pragma unroll
+    for (int sl = 1; sl < NSLOT; ++sl) v += src[sl * NTILE * 256];
+    G[0][i][j] = v;
   }
   __syncthreads();
 
-  // ---- 2. convergence test; Q = I over the consumed partials -------------
+  // ---- 2. convergence test; Q = I; angles of the first rotation round -----
+  const double tol_in = fmax(0.125 * u.tol, 4e-16);
+  int needs = 0;
   for (int idx = tid; idx < P2 * P2; idx += RT) {
     const int i = idx / P2, j = idx % P2;
-    if (i < j && pair_needs_rotation(G[i][i], G[j][j], G[i][j], u.tol, u.skip))
-      flag = 1;
+    if (i < j &&
+        pair_needs_rotation(G[0][i][i], G[0][j][j], G[0][i][j], u.tol, u.skip))
+      needs = 1;
     Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  __syncthreads();
-  const int needs_rotation = flag;
-  __syncthreads();  // every wave has read flag before it is reused below
-  if (!needs_rotation) {
+  if (tid < NPAIR) {
+    int p, q;
+    rr_pair(0, tid, P2, p, q);
+    double cr = 1.0, sr = 0.0;
+    if (pair_rotation(G[0][p][p], G[0][q][q], G[0][p][q], tol_in, u.skip, cr,
+                      sr))
+      flag[0] = 1;
+    cs[0][tid] = cr;
+    sn[0][tid] = sr;
+  }
+  if (__syncthreads_or(needs) == 0) {
     if (tid < P2) {
-      const int col = tid < JB ? bi * JB + tid : bj * JB + tid - JB;
-      if (col < N) s.sig2[(size_t)c * s.n_cap + col] = G[tid][tid];
+      const int col = colidx(tid);
+      if (col < N) s.sig2[(size_t)c * s.n_cap + col] = G[0][tid][tid];
     }
     return;
   }
 
   // ---- 3. inner Jacobi sweeps on G, rotations accumulated in Q ------------
-  // Threads t < 256 own the 2 x 2 block (row pair t / NPAIR, column pair
-  // t % NPAIR) of G; every thread owns one (row, column pair) item of Q.
-  // Every element has exactly one owner, so the update is in place.
-  const int rp = (tid & 255) / NPAIR, cp = tid % NPAIR;
-  const int qrow = tid / NPAIR;
-  const double tol_in = fmax(0.125 * u.tol, 4e-16);
+  // One barrier per rotation round.  Waves 4-7 own the 16 x 16 blocks
+  // (2 x 2 each) of the round, waves 1-7 the (row, pair) items of Q, and
+  // lanes 0-15 of wave 0 derive the next round's angles: the three entries
+  // of their next pair are recomputed from this round's input with the
+  // same rot_block the block owners use.
+  int gr = 0;                   // rotation rounds done
   for (int isw = 0; isw < u.inner_sweeps; ++isw) {
-    if (tid == 0) flag = 0;
-    for (int rr = 0; rr < P2 - 1; ++rr) {
+    for (int rr = 0; rr < P2 - 1; ++rr, ++gr) {
+      const int cur = gr & 1, nxt = cur ^ 1;
+      const int rn = rr + 1 < P2 - 1 ? rr + 1 : 0;
+      double (*Gc)[P2 + 1] = G[cur];
+      double (*Gn)[P2 + 1] = G[nxt];
       if (tid < NPAIR) {
-        int p, q;
-        rr_pair(rr, tid, P2, p, q);
+        // angles of pair tid of the next round from this round's G: its
+        // members are row ra of pair ia = (a0, a1) and row rb of pair
+        // ib = (b0, b1) of this round
+        const uint2 lk2 = look[rr][tid];
+        const int a0 = lk2.x & 255, a1 = (lk2.x >> 8) & 255;
+        const int b0 = (lk2.x >> 16) & 255, b1 = lk2.x >> 24;
+        const int ia = lk2.y & 255, ib = (lk2.y >> 8) & 255;
+        const int ra = (lk2.y >> 16) & 255, rb = lk2.y >> 24;
+        const double ca = cs[cur][ia], sa = sn[cur][ia];
+        const double cb = cs[cur][ib], sb = sn[cur][ib];
+        double g[4], nv[4];
+        g[0] = Gc[a0][a0]; g[1] = Gc[a0][a1]; g[2] = Gc[a1][a0]; g[3] = Gc[a1][a1];
+        rot_block(ca, sa, ca, sa, g, nv);
+        const double app = nv[3 * ra];
+        g[0] = Gc[b0][b0]; g[1] = Gc[b0][b1]; g[2] = Gc[b1][b0]; g[3] = Gc[b1][b1];
+        rot_block(cb, sb, cb, sb, g, nv);
+        const double aqq = nv[3 * rb];
+        g[0] = Gc[a0][b0]; g[1] = Gc[a0][b1]; g[2] = Gc[a1][b0]; g[3] = Gc[a1][b1];
+        rot_block(ca, sa, cb, sb, g, nv);
+        const double apq = nv[2 * ra + rb];
         double cr = 1.0, sr = 0.0;
-        if (pair_rotation(G[p][p], G[q][q], G[p][q], tol_in, u.skip, cr, sr))
-          flag = 1;
-        cs[tid] = cr;
-        sn[tid] = sr;
+        const bool rot = pair_rotation(app, aqq, apq, tol_in, u.skip, cr, sr);
+        // the angle belongs to the next sweep when rn wraps to 0
+        if (rot) flag[(isw + (rn == 0)) & 1] = 1;
+        cs[nxt][tid] = cr;
+        sn[nxt][tid] = sr;
       }
-      __syncthreads();
-      if (tid < NPAIR * NPAIR) {
+      if (tid >= RT - NPAIR * NPAIR) {
+        const int blk = tid - (RT - NPAIR * NPAIR);
+        const int rp = blk / NPAIR, cp = blk % NPAIR;
         int p1, q1, p2, q2;
         rr_pair(rr, rp, P2, p1, q1);
         rr_pair(rr, cp, P2, p2, q2);
-        const double c1 = cs[rp], s1 = sn[rp], c2 = cs[cp], s2 = sn[cp];
-        const double g11 = G[p1][p2], g12 = G[p1][q2];
-        const double g21 = G[q1][p2], g22 = G[q1][q2];
-        // rows: J^T G
-        const double h11 = c1 * g11 - s1 * g21, h12 = c1 * g12 - s1 * g22;
-        const double h21 = s1 * g11 + c1 * g21, h22 = s1 * g12 + c1 * g22;
-        // columns: (J^T G) J
-        G[p1][p2] = c2 * h11 - s2 * h12;
-        G[p1][q2] = s2 * h11 + c2 * h12;
-        G[q1][p2] = c2 * h21 - s2 * h22;
-        G[q1][q2] = s2 * h21 + c2 * h22;
+        double g[4], nv[4];
+        g[0] = Gc[p1][p2]; g[1] = Gc[p1][q2]; g[2] = Gc[q1][p2]; g[3] = Gc[q1][q2];
+        rot_block(cs[cur][rp], sn[cur][rp], cs[cur][cp], sn[cur][cp], g, nv);
+        Gn[p1][p2] = nv[0];
+        Gn[p1][q2] = nv[1];
+        Gn[q1][p2] = nv[2];
+        Gn[q1][q2] = nv[3];
       }
-      {
+      // Q items go to waves 1-7 (wave 0 carries the angle lanes)
+      for (int item = tid - 64; item >= 0 && item < P2 * NPAIR;
+           item += RT - 64) {
+        const int row = item / NPAIR, cp = item % NPAIR;
         int p, q;
         rr_pair(rr, cp, P2, p, q);
-        const double cq = cs[cp], sq = sn[cp];
-        const double x = Q[qrow][p], y = Q[qrow][q];
-        Q[qrow][p] = cq * x - sq * y;
-        Q[qrow][q] = sq * x + cq * y;
+        const double cq = cs[cur][cp], sq = sn[cur][cp];
+        const double x = Q[row][p], y = Q[row][q];
+        Q[row][p] = cq * x - sq * y;
+        Q[row][q] = sq * x + cq * y;
       }
       __syncthreads();
+      // the flag of sweep isw + 1 is cleared once every thread has read it
+      // as the flag of sweep isw - 1
+      if (rr == 0 && tid == 0) flag[(isw + 1) & 1] = 0;
     }
-    const int rotated = flag;
-    __syncthreads();  // read before the next sweep resets it
-    if (!rotated) break;
+    if (!flag[isw & 1]) break;
   }
 
   // ---- 4. Xp <- Xp Q, as D = Q^T Xp^T per 16-row chunk --------------------
-  // each wave takes every eighth chunk; the next chunk is loaded while the
+  // each wave takes every eighth chunk and loads the next chunk while the
   // current one is multiplied
   constexpr int KB = P2 / 4;
+  // lane (li, lk) reads and writes vectors 4 kk + lk (kk < KB) at row
+  // e0 + li: the same set on both sides, so one offset table serves both
+  int coff[KB];
+#pragma unroll
+  for (int kk = 0; kk < KB; ++kk) coff[kk] = colidx(4 * kk + lk) * ld;
   double cur[KB], nxt[KB];
   auto load_chunk = [&](int e0, double *v) {
     const int e = e0 + li;
 #pragma unroll
-    for (int kk = 0; kk < KB; ++kk) {
-      const int t = 4 * kk + lk;
-      const int col = t < JB ? bi * JB + t : bj * JB + t - JB;
-      v[kk] = e < L ? X[(size_t)col * ld + e] : 0.0;
-    }
+    for (int kk = 0; kk < KB; ++kk) v[kk] = e < L ? X[coff[kk] + e] : 0.0;
   };
-  constexpr int CSTEP = 16 * (RT / 64);
+  constexpr int CSTEP = 16 * NWAVE;
   if (16 * w < L) load_chunk(16 * w, cur);
   for (int e0 = 16 * w; e0 < L; e0 += CSTEP) {
     if (e0 + CSTEP < L) load_chunk(e0 + CSTEP, nxt);
@@ -231,16 +359,17 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
       d0 = mfma_f64(Q[4 * kk + lk][li], cur[kk], d0);
-      d1 = mfma_f64(Q[4 * kk + lk][JB + li], cur[kk], d1);
+      d1 = mfma_f64(Q[4 * kk + lk][16 + li], cur[kk], d1);
     }
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) cur[kk] = nxt[kk];
+    // D[i][j] (vector 16 t + i, row e0 + j) sits in lane j + 16 (i % 4),
+    // element i / 4: vector 16 t + lk + 4 q = 4 (4 t + q) + lk
     if (e < L) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int jo = lk + 4 * q;
-        X[(size_t)(bi * JB + jo) * ld + e] = d0[q];
-        X[(size_t)(bj * JB + jo) * ld + e] = d1[q];
+        X[coff[q] + e] = d0[q];
+        X[coff[4 + q] + e] = d1[q];
       }
     }
   }
