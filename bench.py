@@ -40,7 +40,9 @@ def parse():
                     choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--chains", type=int, default=None,
                     help="override the number of chains of the workload")
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
+                    help="mixed: FP32 theta contraction and gate on the "
+                    "matrix cores, FP64 SVD, truncation and observables")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle baseline (0 disables it)")
     return ap.parse_args()
@@ -111,8 +113,10 @@ def main():
               f"({time.perf_counter() - t_start:.1f} s)", file=sys.stderr,
               flush=True)
 
+    precision = (hmps.PREC_MIXED_FP32 if args.precision == "mixed"
+                 else hmps.PREC_FP64)
     ctx = hmps.Context(B, workloads.mps_length(wl.L, wl.W), wl.chi_max,
-                       len(bonds), progress=progress)
+                       len(bonds), precision=precision, progress=progress)
     ctx.hmps_init_cluster_env(lat, B, wl.seed)
 
     def one_sample(idx):
@@ -151,7 +155,8 @@ def main():
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic (Philox-seeded product states, ladder Hamiltonian)",
         "config": {"workload": wl.name, "n_chains": B, "L": wl.L, "W": wl.W,
                    "J_leg": wl.J_leg, "J_rung": wl.J_rung, "beta": wl.beta,

@@ -50,8 +50,10 @@ typedef int32_t hmps_status;
 #define HMPS_E_STATE 4   /* call out of order (e.g. evolve before init) */
 #define HMPS_E_NUMERIC 5 /* SVD did not converge, NaN/Inf, zero norm    */
 
-/* Precision of the theta contraction (the SVD, truncation, norms and all
- * accumulations are always FP64). */
+/* Precision of the theta contraction and the gate (FP64, or FP32 on the
+ * matrix cores with FP32 accumulation from FP64 site tensors rounded on
+ * load).  The SVD, truncation, norms, observables and all accumulations
+ * are FP64 in both modes. */
 #define HMPS_PREC_FP64 0
 #define HMPS_PREC_MIXED_FP32 1
 

@@ -46,77 +46,98 @@ __device__ __forceinline__ Dims dims_of(const Batch &b, int c, int k) {
 // =====================================================================
 // theta'[(s1,a),(s2,c)] = sum_{t1,t2} G[(s1 s2),(t1 t2)]
 //                          sum_b T_k[t1][a][b] T_{k+1}[t2][b][c]
-// One workgroup per 16 x 16 tile of (a, c); all nine (t1, t2) blocks of
-// the tile are accumulated so the 9 x 9 gate is applied in registers.
+// on the matrix cores.  One wavefront per 16 x 16 tile of (a, c): the nine
+// (t1, t2) blocks of the tile are nine MFMA accumulators fed from the same
+// operand loads, and the 9 x 9 gate is applied to them in registers.
+// Precision T: double (FP64 mode) or float (mixed mode: the FP64 site
+// tensors are rounded to FP32 on load, products and the gate are FP32 with
+// FP32 accumulation, and theta' is stored as FP64 for the SVD).
 // =====================================================================
-__global__ void __launch_bounds__(NT)
-    k_theta(Batch b, UpdScratch s, UpdParams u) {
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef v4d V;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return mfma_f64(a, b, c);
+  }
+  // row of D held by a lane in element e (FP64 16x16x4 layout)
+  static __device__ __forceinline__ int row(int lane, int e) {
+    return (lane >> 4) + 4 * e;
+  }
+};
+template <> struct Mfma<float> {
+  typedef v4f V;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // FP32 16x16x4 layout: lane j + 16 (i / 4) holds D[i][j] in element i % 4
+  static __device__ __forceinline__ int row(int lane, int e) {
+    return 4 * (lane >> 4) + e;
+  }
+};
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_theta(Batch b, UpdScratch s, UpdParams u) {
+  typedef Mfma<T> M;
   const int c = blockIdx.z;
   const Dims d = dims_of(b, c, u.k);
-  const int a0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+  __shared__ T G[81];
+  if (threadIdx.x < 81) G[threadIdx.x] = (T)u.gate[threadIdx.x];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int a0 = blockIdx.x * 32 + 16 * (w & 1);
+  const int c0 = blockIdx.y * 32 + 16 * (w >> 1);
   if (a0 >= d.chiL || c0 >= d.chiR) return;
   const int chiL = d.chiL, chiM = d.chiM, chiR = d.chiR;
   const double *A = site_ptr(b, c, u.k);
   const double *Bt = site_ptr(b, c, u.k + 1);
-  double *TH = s.TH + (size_t)c * s.th_stride;
-  double *X = s.X + (size_t)c * s.th_stride;
-  __shared__ double As[3][16][17];
-  __shared__ double Bs[3][16][17];
-  __shared__ double G[81];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  if (threadIdx.x < 81) G[threadIdx.x] = u.gate[threadIdx.x];
-  double acc[9];
+  typename M::V acc[9];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) acc[t] = 0.0;
-  for (int b0 = 0; b0 < chiM; b0 += 16) {
+  for (int t = 0; t < 9; ++t) acc[t] = typename M::V{0, 0, 0, 0};
+  // operands: lane (li, lk) holds A_t1[a0 + li][b0 + lk] and
+  // B_t2[b0 + lk][c0 + li]
+  const int a = a0 + li, cc = c0 + li;
+  for (int b0 = 0; b0 < chiM; b0 += 4) {
+    const int bb = b0 + lk;
+    T av[3], bv[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      As[t][ty][tx] = (a0 + ty < chiL && b0 + tx < chiM)
-                          ? A[(size_t)t * chiL * chiM +
-                              (size_t)(a0 + ty) * chiM + b0 + tx]
-                          : 0.0;
-      Bs[t][ty][tx] = (b0 + ty < chiM && c0 + tx < chiR)
-                          ? Bt[(size_t)t * chiM * chiR +
-                               (size_t)(b0 + ty) * chiR + c0 + tx]
-                          : 0.0;
+      av[t] = (a < chiL && bb < chiM)
+                  ? (T)A[(size_t)t * chiL * chiM + (size_t)a * chiM + bb]
+                  : (T)0;
+      bv[t] = (bb < chiM && cc < chiR)
+                  ? (T)Bt[(size_t)t * chiM * chiR + (size_t)bb * chiR + cc]
+                  : (T)0;
     }
-    __syncthreads();
-    // normal layout: thread (tx, ty) = (a, c); transposed: (c, a), so
-    // that consecutive threads write consecutive elements of a vector
-    const int ia = d.trans ? ty : tx, ic = d.trans ? tx : ty;
-#pragma unroll 4
-    for (int bb = 0; bb < 16; ++bb) {
-      const double a_0 = As[0][ia][bb], a_1 = As[1][ia][bb],
-                   a_2 = As[2][ia][bb];
-      const double b_0 = Bs[0][bb][ic], b_1 = Bs[1][bb][ic],
-                   b_2 = Bs[2][bb][ic];
-      acc[0] += a_0 * b_0;
-      acc[1] += a_0 * b_1;
-      acc[2] += a_0 * b_2;
-      acc[3] += a_1 * b_0;
-      acc[4] += a_1 * b_1;
-      acc[5] += a_1 * b_2;
-      acc[6] += a_2 * b_0;
-      acc[7] += a_2 * b_1;
-      acc[8] += a_2 * b_2;
-    }
-    __syncthreads();
-  }
-  const int a = a0 + (d.trans ? ty : tx), cc = c0 + (d.trans ? tx : ty);
-  if (a < chiL && cc < chiR) {
 #pragma unroll
-    for (int s1 = 0; s1 < 3; ++s1) {
+    for (int t1 = 0; t1 < 3; ++t1)
+#pragma unroll
+      for (int t2 = 0; t2 < 3; ++t2)
+        acc[3 * t1 + t2] = M::mma(av[t1], bv[t2], acc[3 * t1 + t2]);
+  }
+  double *TH = s.TH + (size_t)c * s.th_stride;
+  double *X = s.X + (size_t)c * s.th_stride;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ai = a0 + M::row(lane, e), ci = c0 + li;
+    if (ai >= chiL || ci >= chiR) continue;
+    T th[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) th[t] = acc[t][e];
+#pragma unroll
+    for (int s1 = 0; s1 < 3; ++s1)
 #pragma unroll
       for (int s2 = 0; s2 < 3; ++s2) {
-        double v = 0.0;
+        T v = 0;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) v += G[(s1 * 3 + s2) * 9 + t] * acc[t];
-        const size_t row = (size_t)s1 * chiL + a, col = (size_t)s2 * chiR + cc;
+        for (int t = 0; t < 9; ++t) v += G[(s1 * 3 + s2) * 9 + t] * th[t];
+        const size_t row = (size_t)s1 * chiL + ai, col = (size_t)s2 * chiR + ci;
         const size_t off = d.trans ? row * d.ld + col : col * d.ld + row;
-        TH[off] = v;
-        X[off] = v;
+        TH[off] = (double)v;
+        X[off] = (double)v;
       }
-    }
   }
 }
 
@@ -405,8 +426,11 @@ __global__ void __launch_bounds__(NT)
 // ---- launchers ---------------------------------------------------------
 void launch_theta(const Batch &b, const UpdScratch &s, const UpdParams &u,
                   int max_chiL, int max_chiR, hipStream_t st) {
-  dim3 grid((max_chiL + 15) / 16, (max_chiR + 15) / 16, b.B);
-  hipLaunchKernelGGL(k_theta, grid, dim3(NT), 0, st, b, s, u);
+  dim3 grid((max_chiL + 31) / 32, (max_chiR + 31) / 32, b.B);
+  if (u.mixed)
+    hipLaunchKernelGGL(k_theta<float>, grid, dim3(NT), 0, st, b, s, u);
+  else
+    hipLaunchKernelGGL(k_theta<double>, grid, dim3(NT), 0, st, b, s, u);
 }
 
 void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,
