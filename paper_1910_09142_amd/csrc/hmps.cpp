@@ -238,6 +238,10 @@ struct hmps_ctx {
   // 2% more outer sweeps and halves the time per round.
   int inner_sweeps = 1;
   double skip = 1e-30;
+  // Outer rounds after the first of a sweep rotate only the pairs across
+  // their two blocks (16 inner rounds instead of 31): measured on the same
+  // ladder, 4% more outer sweeps and 23% less time (one chain).
+  int cross_inner = 1;
   // device buffers (carved from the workspace)
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
   int n_cap = 0, slots = 0;
@@ -443,6 +447,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   u.mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32;
   u.inner_sweeps = ctx->inner_sweeps;
   u.skip = ctx->skip;
+  u.cross_inner = ctx->cross_inner;
   Batch b = batch_of(ctx);
   UpdScratch s = scratch_of(ctx);
   hipStream_t st = ctx->stream;
@@ -595,6 +600,7 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
   if (const char *e = std::getenv("HMPS_SYNC_DEBUG")) ctx->sync_debug = e[0] == '1';
   if (const char *e = std::getenv("HMPS_INNER")) ctx->inner_sweeps = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("HMPS_SKIP")) ctx->skip = std::min(1e-26, std::atof(e));
+  if (const char *e = std::getenv("HMPS_CROSS")) ctx->cross_inner = e[0] == '1';
   hipError_t e = hipSetDevice(opt->device);
   if (e != hipSuccess) {
     delete ctx;

@@ -68,6 +68,7 @@ struct UpdParams {
   int mixed;          // FP32 contraction
   int inner_sweeps;   // cap on the inner Jacobi sweeps of a block pair
   double skip;        // relative squared norm below which a vector is zero
+  int cross_inner;    // inner rotations across the two blocks only (rounds > 0)
 };
 
 // ---- launchers (update.hip, jacobi.hip, observe.hip) -----------------------------------------

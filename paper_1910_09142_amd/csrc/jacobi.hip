@@ -93,6 +93,35 @@ __device__ __forceinline__ void rr_slot(int r, int x, int n, int &i,
   }
 }
 
+// Inner (in-LDS) rotation schedule of a block pair of 2 NPAIR vectors:
+// the circle method over all 2 NPAIR - 1 rounds (every pair), or, with
+// `cross`, NPAIR rounds of the pairs (i, NPAIR + (i + rr) mod NPAIR) that
+// join one vector of each block.
+__device__ __forceinline__ void inner_pair(bool cross, int rr, int i, int n,
+                                           int &p, int &q) {
+  if (cross) {
+    p = i;
+    q = n / 2 + ((i + rr) & (n / 2 - 1));
+  } else {
+    rr_pair(rr, i, n, p, q);
+  }
+}
+__device__ __forceinline__ void inner_slot(bool cross, int rr, int x, int n,
+                                           int &i, int &partner) {
+  if (cross) {
+    const int h = n / 2;
+    if (x < h) {
+      i = x;
+      partner = h + ((x + rr) & (h - 1));
+    } else {
+      i = (x - h - rr) & (h - 1);
+      partner = i;
+    }
+  } else {
+    rr_slot(rr, x, n, i, partner);
+  }
+}
+
 // One 2 x 2 block of J^T G J: rows (p1, q1) rotated by (c1, s1), columns
 // (p2, q2) by (c2, s2); g and n are row-major [row][column].
 __device__ __forceinline__ void rot_block(double c1, double s1, double c2,
@@ -139,6 +168,11 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   // per rotation round rr and pair t of round rr + 1: where that pair's
   // three Gram entries sit in round rr (see step 3), packed as bytes
   __shared__ uint2 look[P2 - 1][NPAIR];
+  // The first round of every outer sweep diagonalises the whole block pair
+  // (all pairs, so the pairs inside each block are rotated once per
+  // sweep); later rounds rotate only the pairs across the two blocks.
+  const bool cross = u.cross_inner && r > 0;
+  const int nrounds = cross ? NPAIR : P2 - 1;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
 
@@ -152,13 +186,13 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     flag[0] = 0;
     flag[1] = 0;
   }
-  for (int e = tid; e < (P2 - 1) * NPAIR; e += RT) {
+  for (int e = tid; e < nrounds * NPAIR; e += RT) {
     const int rr = e / NPAIR, t = e % NPAIR;
-    const int rn = rr + 1 < P2 - 1 ? rr + 1 : 0;
+    const int rn = rr + 1 < nrounds ? rr + 1 : 0;
     int pn, qn, ia, pa, ib, pb;
-    rr_pair(rn, t, P2, pn, qn);
-    rr_slot(rr, pn, P2, ia, pa);
-    rr_slot(rr, qn, P2, ib, pb);
+    inner_pair(cross, rn, t, P2, pn, qn);
+    inner_slot(cross, rr, pn, P2, ia, pa);
+    inner_slot(cross, rr, qn, P2, ib, pb);
     const int ra = pn < pa ? 0 : 1, rb = qn < pb ? 0 : 1;
     const unsigned a0 = ra ? pa : pn, a1 = ra ? pn : pa;
     const unsigned b0 = rb ? pb : qn, b1 = rb ? qn : pb;
@@ -172,21 +206,24 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     for (int t = 0; t < NTILE; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
     const double *xa = X + (size_t)colidx(li) * ld;
     const double *xb = X + (size_t)colidx(JB + li) * ld;
-    double4 ca, cb, na, nb;
-    auto load = [&](int e0, double4 &va, double4 &vb) {
+    // native vector type: HIP's double4 is a union and, assigned through
+    // references, left dead stores to scratch
+    v4d ca, cb, na, nb;
+    auto load = [&](const double *x, int e0) -> v4d {
       const int e = e0 + 4 * lk;
-      if (e < ld) {
-        va = *reinterpret_cast<const double4 *>(xa + e);
-        vb = *reinterpret_cast<const double4 *>(xb + e);
-      } else {
-        va = make_double4(0.0, 0.0, 0.0, 0.0);
-        vb = va;
-      }
+      return e < ld ? *reinterpret_cast<const v4d *>(x + e)
+                    : v4d{0.0, 0.0, 0.0, 0.0};
     };
     int e0 = 16 * w;
-    if (e0 < L) load(e0, ca, cb);
+    if (e0 < L) {
+      ca = load(xa, e0);
+      cb = load(xb, e0);
+    }
     for (; e0 < L; e0 += CSTEP) {
-      if (e0 + CSTEP < L) load(e0 + CSTEP, na, nb);
+      if (e0 + CSTEP < L) {
+        na = load(xa, e0 + CSTEP);
+        nb = load(xb, e0 + CSTEP);
+      }
       acc[0] = mfma_f64(ca.x, ca.x, acc[0]);
       acc[1] = mfma_f64(ca.x, cb.x, acc[1]);
       acc[2] = mfma_f64(cb.x, cb.x, acc[2]);
@@ -238,14 +275,17 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   int needs = 0;
   for (int idx = tid; idx < P2 * P2; idx += RT) {
     const int i = idx / P2, j = idx % P2;
-    if (i < j &&
+    // a cross round tests only the pairs it rotates; the pairs inside a
+    // block are tested (and rotated) in the first round of every sweep, and
+    // a sweep without any rotation leaves them as tested there
+    if (i < j && (!cross || (i < NPAIR && j >= NPAIR)) &&
         pair_needs_rotation(G[0][i][i], G[0][j][j], G[0][i][j], u.tol, u.skip))
       needs = 1;
     Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
   if (tid < NPAIR) {
     int p, q;
-    rr_pair(0, tid, P2, p, q);
+    inner_pair(cross, 0, tid, P2, p, q);
     double cr = 1.0, sr = 0.0;
     if (pair_rotation(G[0][p][p], G[0][q][q], G[0][p][q], tol_in, u.skip, cr,
                       sr))
@@ -268,17 +308,18 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   // of their next pair are recomputed from this round's input with the
   // same rot_block the block owners use.
   int gr = 0;                   // rotation rounds done
+  // pairing entry of the current round (angle lanes), read one round ahead
+  uint2 lk2 = tid < NPAIR ? look[0][tid] : make_uint2(0u, 0u);
   for (int isw = 0; isw < u.inner_sweeps; ++isw) {
-    for (int rr = 0; rr < P2 - 1; ++rr, ++gr) {
+    for (int rr = 0; rr < nrounds; ++rr, ++gr) {
       const int cur = gr & 1, nxt = cur ^ 1;
-      const int rn = rr + 1 < P2 - 1 ? rr + 1 : 0;
+      const int rn = rr + 1 < nrounds ? rr + 1 : 0;
       double (*Gc)[P2 + 1] = G[cur];
       double (*Gn)[P2 + 1] = G[nxt];
       if (tid < NPAIR) {
         // angles of pair tid of the next round from this round's G: its
         // members are row ra of pair ia = (a0, a1) and row rb of pair
         // ib = (b0, b1) of this round
-        const uint2 lk2 = look[rr][tid];
         const int a0 = lk2.x & 255, a1 = (lk2.x >> 8) & 255;
         const int b0 = (lk2.x >> 16) & 255, b1 = lk2.x >> 24;
         const int ia = lk2.y & 255, ib = (lk2.y >> 8) & 255;
@@ -288,26 +329,28 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
         double g[4], nv[4];
         g[0] = Gc[a0][a0]; g[1] = Gc[a0][a1]; g[2] = Gc[a1][a0]; g[3] = Gc[a1][a1];
         rot_block(ca, sa, ca, sa, g, nv);
-        const double app = nv[3 * ra];
+        // selects, not indexing: a runtime index would put nv in scratch
+        const double app = ra ? nv[3] : nv[0];
         g[0] = Gc[b0][b0]; g[1] = Gc[b0][b1]; g[2] = Gc[b1][b0]; g[3] = Gc[b1][b1];
         rot_block(cb, sb, cb, sb, g, nv);
-        const double aqq = nv[3 * rb];
+        const double aqq = rb ? nv[3] : nv[0];
         g[0] = Gc[a0][b0]; g[1] = Gc[a0][b1]; g[2] = Gc[a1][b0]; g[3] = Gc[a1][b1];
         rot_block(ca, sa, cb, sb, g, nv);
-        const double apq = nv[2 * ra + rb];
+        const double apq = ra ? (rb ? nv[3] : nv[2]) : (rb ? nv[1] : nv[0]);
         double cr = 1.0, sr = 0.0;
         const bool rot = pair_rotation(app, aqq, apq, tol_in, u.skip, cr, sr);
         // the angle belongs to the next sweep when rn wraps to 0
         if (rot) flag[(isw + (rn == 0)) & 1] = 1;
         cs[nxt][tid] = cr;
         sn[nxt][tid] = sr;
+        lk2 = look[rn][tid];
       }
       if (tid >= RT - NPAIR * NPAIR) {
         const int blk = tid - (RT - NPAIR * NPAIR);
         const int rp = blk / NPAIR, cp = blk % NPAIR;
         int p1, q1, p2, q2;
-        rr_pair(rr, rp, P2, p1, q1);
-        rr_pair(rr, cp, P2, p2, q2);
+        inner_pair(cross, rr, rp, P2, p1, q1);
+        inner_pair(cross, rr, cp, P2, p2, q2);
         double g[4], nv[4];
         g[0] = Gc[p1][p2]; g[1] = Gc[p1][q2]; g[2] = Gc[q1][p2]; g[3] = Gc[q1][q2];
         rot_block(cs[cur][rp], sn[cur][rp], cs[cur][cp], sn[cur][cp], g, nv);
@@ -321,7 +364,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
            item += RT - 64) {
         const int row = item / NPAIR, cp = item % NPAIR;
         int p, q;
-        rr_pair(rr, cp, P2, p, q);
+        inner_pair(cross, rr, cp, P2, p, q);
         const double cq = cs[cur][cp], sq = sn[cur][cp];
         const double x = Q[row][p], y = Q[row][q];
         Q[row][p] = cq * x - sq * y;
