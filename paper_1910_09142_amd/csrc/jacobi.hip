@@ -157,13 +157,14 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   double *X = s.X + (size_t)c * s.th_stride;
   auto colidx = [&](int t) { return t < JB ? bi * JB + t : bj * JB + t - JB; };
 
-  // G is double-buffered: rotation round k reads G[k & 1] and writes
-  // G[(k + 1) & 1], so nothing read in a round is overwritten in it
+  // G is symmetric and only its upper triangle (i <= j) is kept.  It is
+  // double-buffered: rotation round k reads G[k & 1] and writes
+  // G[(k + 1) & 1], so nothing read in a round is overwritten in it.
   __shared__ double G[2][P2][P2 + 1];
   // partial Gram tiles, reused as Q once they are summed into G
   __shared__ double scratch[NSLOT * NTILE * 256];
   double (*Q)[P2 + 1] = reinterpret_cast<double (*)[P2 + 1]>(scratch);
-  __shared__ double cs[2][NPAIR], sn[2][NPAIR];
+  __shared__ double2 csn[2][NPAIR];  // (c, s) of every pair of a round
   __shared__ int flag[2];
   // per rotation round rr and pair t of round rr + 1: where that pair's
   // three Gram entries sit in round rr (see step 3), packed as bytes
@@ -256,13 +257,12 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
       __syncthreads();
     }
   }
-  // G from the upper tiles (tile 0: II, 1: IJ, 2: JJ); the lower triangle
-  // mirrors the upper one
+  // upper triangle of G from the upper tiles (tile 0: II, 1: IJ, 2: JJ)
   for (int idx = tid; idx < P2 * P2; idx += RT) {
     const int i = idx / P2, j = idx % P2;
-    const int a = i < j ? i : j, bb = i < j ? j : i;
-    const int tile = (a >> 4) + (bb >> 4);
-    const double *src = scratch + tile * 256 + (a & 15) * 16 + (bb & 15);
+    if (i > j) continue;
+    const int tile = (i >> 4) + (j >> 4);
+    const double *src = scratch + tile * 256 + (i & 15) * 16 + (j & 15);
     double v = src[0];
 #pragma unroll
     for (int sl = 1; sl < NSLOT; ++sl) v += src[sl * NTILE * 256];
@@ -290,8 +290,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     if (pair_rotation(G[0][p][p], G[0][q][q], G[0][p][q], tol_in, u.skip, cr,
                       sr))
       flag[0] = 1;
-    cs[0][tid] = cr;
-    sn[0][tid] = sr;
+    csn[0][tid] = make_double2(cr, sr);
   }
   if (__syncthreads_or(needs) == 0) {
     if (tid < P2) {
@@ -302,11 +301,27 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   }
 
   // ---- 3. inner Jacobi sweeps on G, rotations accumulated in Q ------------
-  // One barrier per rotation round.  Waves 4-7 own the 16 x 16 blocks
-  // (2 x 2 each) of the round, waves 1-7 the (row, pair) items of Q, and
-  // lanes 0-15 of wave 0 derive the next round's angles: the three entries
-  // of their next pair are recomputed from this round's input with the
-  // same rot_block the block owners use.
+  // One barrier per rotation round.  Threads 256.. own the 2 x 2 blocks
+  // (pair rp, pair cp), rp <= cp, of the upper triangle of the round,
+  // waves 1-7 the (row, pair) items of Q, and lanes 0-15 of wave 0 derive
+  // the next round's angles: the three entries of their next pair are
+  // recomputed from this round's input exactly as their block owners
+  // compute them.
+  constexpr int NBLK = NPAIR * (NPAIR + 1) / 2;
+  auto gs = [&](double (*Gm)[P2 + 1], int x, int y) -> double & {
+    return x <= y ? Gm[x][y] : Gm[y][x];
+  };
+  // block of the upper triangle owned by this thread (rp <= cp)
+  int brp = 0, bcp = 0;
+  const bool owner = tid >= 256 && tid < 256 + NBLK;
+  if (owner) {
+    int k = tid - 256;
+    while (k >= NPAIR - brp) {
+      k -= NPAIR - brp;
+      ++brp;
+    }
+    bcp = brp + k;
+  }
   int gr = 0;                   // rotation rounds done
   // pairing entry of the current round (angle lanes), read one round ahead
   uint2 lk2 = tid < NPAIR ? look[0][tid] : make_uint2(0u, 0u);
@@ -324,40 +339,50 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
         const int b0 = (lk2.x >> 16) & 255, b1 = lk2.x >> 24;
         const int ia = lk2.y & 255, ib = (lk2.y >> 8) & 255;
         const int ra = (lk2.y >> 16) & 255, rb = lk2.y >> 24;
-        const double ca = cs[cur][ia], sa = sn[cur][ia];
-        const double cb = cs[cur][ib], sb = sn[cur][ib];
+        const double2 ja = csn[cur][ia], jb = csn[cur][ib];
         double g[4], nv[4];
-        g[0] = Gc[a0][a0]; g[1] = Gc[a0][a1]; g[2] = Gc[a1][a0]; g[3] = Gc[a1][a1];
-        rot_block(ca, sa, ca, sa, g, nv);
+        g[0] = Gc[a0][a0]; g[1] = Gc[a0][a1]; g[2] = g[1]; g[3] = Gc[a1][a1];
+        rot_block(ja.x, ja.y, ja.x, ja.y, g, nv);
         // selects, not indexing: a runtime index would put nv in scratch
         const double app = ra ? nv[3] : nv[0];
-        g[0] = Gc[b0][b0]; g[1] = Gc[b0][b1]; g[2] = Gc[b1][b0]; g[3] = Gc[b1][b1];
-        rot_block(cb, sb, cb, sb, g, nv);
+        g[0] = Gc[b0][b0]; g[1] = Gc[b0][b1]; g[2] = g[1]; g[3] = Gc[b1][b1];
+        rot_block(jb.x, jb.y, jb.x, jb.y, g, nv);
         const double aqq = rb ? nv[3] : nv[0];
-        g[0] = Gc[a0][b0]; g[1] = Gc[a0][b1]; g[2] = Gc[a1][b0]; g[3] = Gc[a1][b1];
-        rot_block(ca, sa, cb, sb, g, nv);
-        const double apq = ra ? (rb ? nv[3] : nv[2]) : (rb ? nv[1] : nv[0]);
+        // the cross entry as its owner, block (min(ia,ib), max(ia,ib)),
+        // computes it: rows of the smaller pair index first
+        double apq;
+        if (ia < ib) {
+          g[0] = gs(Gc, a0, b0); g[1] = gs(Gc, a0, b1);
+          g[2] = gs(Gc, a1, b0); g[3] = gs(Gc, a1, b1);
+          rot_block(ja.x, ja.y, jb.x, jb.y, g, nv);
+          apq = ra ? (rb ? nv[3] : nv[2]) : (rb ? nv[1] : nv[0]);
+        } else {
+          g[0] = gs(Gc, b0, a0); g[1] = gs(Gc, b0, a1);
+          g[2] = gs(Gc, b1, a0); g[3] = gs(Gc, b1, a1);
+          rot_block(jb.x, jb.y, ja.x, ja.y, g, nv);
+          apq = rb ? (ra ? nv[3] : nv[2]) : (ra ? nv[1] : nv[0]);
+        }
         double cr = 1.0, sr = 0.0;
         const bool rot = pair_rotation(app, aqq, apq, tol_in, u.skip, cr, sr);
         // the angle belongs to the next sweep when rn wraps to 0
         if (rot) flag[(isw + (rn == 0)) & 1] = 1;
-        cs[nxt][tid] = cr;
-        sn[nxt][tid] = sr;
+        csn[nxt][tid] = make_double2(cr, sr);
         lk2 = look[rn][tid];
       }
-      if (tid >= RT - NPAIR * NPAIR) {
-        const int blk = tid - (RT - NPAIR * NPAIR);
-        const int rp = blk / NPAIR, cp = blk % NPAIR;
+      if (owner) {
         int p1, q1, p2, q2;
-        inner_pair(cross, rr, rp, P2, p1, q1);
-        inner_pair(cross, rr, cp, P2, p2, q2);
+        inner_pair(cross, rr, brp, P2, p1, q1);
+        inner_pair(cross, rr, bcp, P2, p2, q2);
+        const double2 j1 = csn[cur][brp], j2 = csn[cur][bcp];
         double g[4], nv[4];
-        g[0] = Gc[p1][p2]; g[1] = Gc[p1][q2]; g[2] = Gc[q1][p2]; g[3] = Gc[q1][q2];
-        rot_block(cs[cur][rp], sn[cur][rp], cs[cur][cp], sn[cur][cp], g, nv);
-        Gn[p1][p2] = nv[0];
-        Gn[p1][q2] = nv[1];
-        Gn[q1][p2] = nv[2];
-        Gn[q1][q2] = nv[3];
+        g[0] = gs(Gc, p1, p2); g[1] = gs(Gc, p1, q2);
+        g[2] = gs(Gc, q1, p2); g[3] = gs(Gc, q1, q2);
+        rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
+        gs(Gn, p1, p2) = nv[0];
+        gs(Gn, p1, q2) = nv[1];
+        // a diagonal block holds (p, q) once: its (q, p) element is skipped
+        if (brp != bcp) gs(Gn, q1, p2) = nv[2];
+        gs(Gn, q1, q2) = nv[3];
       }
       // Q items go to waves 1-7 (wave 0 carries the angle lanes)
       for (int item = tid - 64; item >= 0 && item < P2 * NPAIR;
@@ -365,7 +390,8 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
         const int row = item / NPAIR, cp = item % NPAIR;
         int p, q;
         inner_pair(cross, rr, cp, P2, p, q);
-        const double cq = cs[cur][cp], sq = sn[cur][cp];
+        const double2 jq = csn[cur][cp];
+        const double cq = jq.x, sq = jq.y;
         const double x = Q[row][p], y = Q[row][q];
         Q[row][p] = cq * x - sq * y;
         Q[row][q] = sq * x + cq * y;
