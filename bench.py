@@ -48,6 +48,45 @@ def parse():
     return ap.parse_args()
 
 
+# Sources that make up the round kernel; a traffic figure measured with
+# hardware counters holds only for the code it was measured on.
+KERNEL_SOURCES = ("jacobi.hip", "device_common.h", "hmps_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1910_09142_amd", "csrc", name),
+                  "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(wl):
+    """HBM bytes per round-kernel launch from the committed rocprofv3
+    counter summary of this workload (FETCH_SIZE and WRITE_SIZE scaled by
+    the copy-kernel calibration), or None when there is none or it was
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles",
+                        f"k_jacobi_round_traffic_{wl.name}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.split(":", 1)[0].strip() in (
+                    "source_sha256", "traffic_bytes_per_launch"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(wl, seconds):
     """The FP64 oracle on the same workload: chain 0, seed 0, sample 0,
     Trotter updates in order until the time budget is spent."""
@@ -150,6 +189,7 @@ def main():
     launches = s1.round_launches - s0.round_launches
     svd_s = s1.svd_seconds - s0.svd_seconds
     svd_f = s1.svd_flops - s0.svd_flops
+    svd_b = s1.svd_bytes - s0.svd_bytes
     achieved = (svd_f / svd_s / 1e12) if svd_s > 0 else 0.0
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
@@ -171,11 +211,17 @@ def main():
         "roofline": {
             "bound": "mfma", "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": (measured_traffic(wl)
+                        if args.precision == "fp64" and B == wl.n_chains
+                        else None),
             "kernel": "k_jacobi_round",
             "launches": launches,
             "avg_launch_us": 1e6 * svd_s / launches if launches else None,
             "flops_per_launch": svd_f / launches if launches else None,
+            "algo_bytes_per_launch": svd_b / launches if launches else None,
+            "algo_hbm_GBps": svd_b / svd_s / 1e9 if svd_s > 0 else None,
+            "hbm_peak_GBps": 8000.0,
         },
     }
     ctx.hmps_destroy()

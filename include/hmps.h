@@ -113,6 +113,9 @@ typedef struct {
                             /* Jacobi path                               */
   double svd_seconds;       /* device time (event span) of those rounds  */
   int64_t round_launches;   /* blocked Jacobi round kernels launched     */
+  double svd_bytes;         /* algorithmic bytes of those rounds: each
+                               vector read once per round, and written
+                               once while its chain still rotates        */
 } hmps_stats_t;
 
 /* Bytes of device workspace needed for the given capacities. */

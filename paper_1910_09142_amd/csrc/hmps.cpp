@@ -475,6 +475,18 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       HIPCHK(hipEventRecord(ctx->sweep_ev[sweep & 1], st));
       return HMPS_OK;
     };
+    // algorithmic bytes of the rounds: in every round a chain's block pairs
+    // are read once and, in a sweep where the chain still rotates, written
+    // once (its last, checking sweep only reads them)
+    std::vector<double> round_bytes(ctx->B);
+    std::vector<uint8_t> active(ctx->B, 1);
+    for (int c = 0; c < ctx->B; ++c) {
+      const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
+      const int nvec = 3 * std::min(row[k], row[k + 2]);
+      const int len = 3 * std::max(row[k], row[k + 2]);
+      const int nb = n_blocks_even(nvec, JB);
+      round_bytes[c] = (double)(nb - 1) * nb * JB * ((len + 3) & ~3) * 8.0;
+    }
     HIPCHK(hipEventRecord(ctx->svd_ev[0], st));
     hmps_status est = enqueue_sweep(0);
     if (est) return est;
@@ -487,7 +499,12 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       HIPCHK(hipEventSynchronize(ctx->sweep_ev[prev]));
       const int32_t *slot = ctx->h_stage + (size_t)(2 + prev) * ctx->opt.max_chains;
       bool any = false;
-      for (int c = 0; c < ctx->B; ++c) any |= slot[c] != 0;
+      for (int c = 0; c < ctx->B; ++c) {
+        if (active[c])
+          ctx->stats.svd_bytes += round_bytes[c] * (slot[c] != 0 ? 2.0 : 1.0);
+        active[c] = slot[c] != 0;
+        any |= slot[c] != 0;
+      }
       if (!any) {
         converged = true;
         break;

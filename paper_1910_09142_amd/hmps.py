@@ -62,7 +62,7 @@ class hmps_stats_t(C.Structure):
                 ("sample", C.c_int64), ("discarded_weight", C.c_double),
                 ("evolve_seconds", C.c_double), ("algo_flops", C.c_double),
                 ("svd_flops", C.c_double), ("svd_seconds", C.c_double),
-                ("round_launches", C.c_int64)]
+                ("round_launches", C.c_int64), ("svd_bytes", C.c_double)]
 
 
 _lib = None
