@@ -67,7 +67,7 @@ typedef struct {
   int32_t chi_cap;         /* largest chi_max accepted by evolve          */
   int32_t max_bonds;       /* largest number of Hamiltonian bonds         */
   int32_t precision;       /* HMPS_PREC_*                                 */
-  int32_t max_sweeps;      /* Jacobi sweep cap, 0 = default (30)          */
+  int32_t max_sweeps;      /* Jacobi sweep cap, 0 = default (100)         */
   double jacobi_tol;       /* relative orthogonality tolerance, 0 = auto  */
   /* Optional: called on the calling thread after every Trotter step of
    * hmps_evolve with (progress_user, steps done, steps in this call).  It
@@ -178,6 +178,26 @@ hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out);
 /* Bond dimensions chi[c][b], b = 0..n_sites, of every chain (host array
  * of n_chains * (n_sites + 1) int32).  Synchronises. */
 hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi);
+
+/* Diagnostic: the truncated SVD that follows every two-site gate (Ancilla
+ * Method subsection: the bond is restored to MPS form by an SVD truncated
+ * by discarded weight; Results section: the cutoff and chi_max), applied
+ * to a given theta'.  theta: host array, m x n row-major with m = 3 chi_l
+ * (rows (s1, a)) and n = 3 chi_r (columns (s2, c)), 1 <= chi_l, chi_r <=
+ * chi_cap, finite.  It runs the device kernels of an update of hmps_evolve
+ * (blocked one-sided Jacobi, truncation with the rules of hmps_evolve,
+ * write-back with the singular values absorbed to the right) on chain 0.
+ * Outputs (host, caller-owned): rank = k kept; sigma[k] the kept singular
+ * values of theta' (descending, not renormalised); left (optional,
+ * 3*chi_l*k) = U as T[s1][a][j]; right (optional, 3*k*chi_r) =
+ * Sigma V^T / ||Sigma_kept|| as T[s2][j][c].  The context's chains are
+ * replaced (hmps_init_cluster_env must be called again before evolve).
+ * Needs max_sites >= 2; E_INVALID on bad arguments, E_NUMERIC if the SVD
+ * does not converge.  Synchronises. */
+hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
+                           const double *theta, int32_t chi_max,
+                           double cutoff, double *sigma, int32_t *rank,
+                           double *left, double *right);
 
 /* Destroy a context (NULL is accepted).  Does not free the workspace. */
 void hmps_destroy(hmps_ctx *ctx);

@@ -242,6 +242,7 @@ struct hmps_ctx {
   // their two blocks (16 inner rounds instead of 31): measured on the same
   // ladder, 4% more outer sweeps and 23% less time (one chain).
   int cross_inner = 1;
+  bool skip_theta = false;  // hmps_svd_probe: theta' is placed by the host
   // device buffers (carved from the workspace)
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
   int n_cap = 0, slots = 0;
@@ -452,8 +453,10 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   UpdScratch s = scratch_of(ctx);
   hipStream_t st = ctx->stream;
   bool timed_svd = false;
-  launch_theta(b, s, u, max_chiL, max_chiR, st);
-  LAUNCHCHK(ctx);
+  if (!ctx->skip_theta) {
+    launch_theta(b, s, u, max_chiL, max_chiR, st);
+    LAUNCHCHK(ctx);
+  }
   if (max_mn <= (size_t)SMALL_LDS) {
     launch_jacobi_small(b, s, u, st);
     LAUNCHCHK(ctx);
@@ -607,7 +610,9 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
   if (((uintptr_t)opt->workspace) % ALIGN) return HMPS_E_INVALID;
   hmps_ctx *ctx = new hmps_ctx();
   ctx->opt = *opt;
-  if (ctx->opt.max_sweeps <= 0) ctx->opt.max_sweeps = 30;
+  // A dense theta' with a graded spectrum (sigma_j = exp(-j/40), 1536 x
+  // 1536) needs 63 sweeps; typical updates of the ladders need about 10.
+  if (ctx->opt.max_sweeps <= 0) ctx->opt.max_sweeps = 100;
   if (!(ctx->opt.jacobi_tol > 0.0)) {
     // relative orthogonality reachable with rounded inner products of
     // length 3 chi_cap: a few sqrt(m) eps
@@ -900,6 +905,70 @@ hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out) {
     }
   }
   *out = s;
+  return HMPS_OK;
+}
+
+hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
+                           const double *theta, int32_t chi_max,
+                           double cutoff, double *sigma, int32_t *rank,
+                           double *left, double *right) {
+  hmps_status st = check_usable(ctx, false);
+  if (st) return st;
+  if (!theta || !sigma || !rank)
+    return fail(ctx, HMPS_E_INVALID, "theta, sigma and rank must not be NULL");
+  if (chi_l < 1 || chi_r < 1 || chi_l > ctx->opt.chi_cap ||
+      chi_r > ctx->opt.chi_cap)
+    return fail(ctx, HMPS_E_INVALID, "chi_l and chi_r must be in [1, chi_cap]");
+  if (ctx->opt.max_sites < 2)
+    return fail(ctx, HMPS_E_INVALID, "the context needs max_sites >= 2");
+  if (chi_max < 1 || !(cutoff >= 0.0) || !(cutoff < 1.0))
+    return fail(ctx, HMPS_E_INVALID, "chi_max >= 1 and 0 <= cutoff < 1");
+  const int m = 3 * chi_l, n = 3 * chi_r;
+  for (size_t i = 0; i < (size_t)m * n; ++i)
+    if (!std::isfinite(theta[i]))
+      return fail(ctx, HMPS_E_INVALID, "theta has a non-finite entry");
+  // the context's chains are replaced by one chain of two sites whose
+  // update on bond (0, 1) finds theta' already in place
+  Plan P;
+  P.len = 2;
+  ctx->plan = P;
+  ctx->B = 1;
+  ctx->ready = false;
+  ctx->center = 0;
+  ctx->h_chi = {chi_l, 1, chi_r};
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipMemcpyAsync(ctx->d_chi, ctx->h_chi.data(), sizeof(int32_t) * 3,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(ctx->d_err, 0, sizeof(int32_t), s));
+  HIPCHK(hipMemsetAsync(ctx->d_disc, 0, sizeof(double), s));
+  HIPCHK(hipMemsetAsync(ctx->d_logw, 0, sizeof(double), s));
+  // theta' in the vector layout of the SVD: the min(m, n) vectors of length
+  // max(m, n), stride rounded up to 4, column-major
+  const bool trans = n > m;
+  const int len = trans ? n : m, nvec = trans ? m : n, ld = (len + 3) & ~3;
+  std::vector<double> h((size_t)ld * nvec, 0.0);
+  for (int r = 0; r < m; ++r)
+    for (int c = 0; c < n; ++c)
+      h[trans ? (size_t)r * ld + c : (size_t)c * ld + r] =
+          theta[(size_t)r * n + c];
+  HIPCHK(hipMemcpyAsync(ctx->d_TH, h.data(), sizeof(double) * h.size(),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctx->d_X, h.data(), sizeof(double) * h.size(),
+                        hipMemcpyHostToDevice, s));
+  ctx->skip_theta = true;
+  st = do_update(ctx, 0, OP_SWAP, true, chi_max, cutoff);
+  ctx->skip_theta = false;
+  if (st) return st;
+  const int k = ctx->h_chi[1];
+  *rank = k;
+  HIPCHK(hipMemcpy(sigma, ctx->d_sig, sizeof(double) * k,
+                   hipMemcpyDeviceToHost));
+  if (left)
+    HIPCHK(hipMemcpy(left, ctx->d_sites, sizeof(double) * 3 * chi_l * k,
+                     hipMemcpyDeviceToHost));
+  if (right)
+    HIPCHK(hipMemcpy(right, ctx->d_sites + ctx->site_cap,
+                     sizeof(double) * 3 * k * chi_r, hipMemcpyDeviceToHost));
   return HMPS_OK;
 }
 

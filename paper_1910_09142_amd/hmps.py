@@ -28,7 +28,7 @@ EXPORTS = [
     "hmps_workspace_bytes", "hmps_create", "hmps_init_cluster_env",
     "hmps_evolve", "hmps_measure", "hmps_collapse_resample", "hmps_stats",
     "hmps_bond_dims", "hmps_destroy", "hmps_last_error", "hmps_gate",
-    "hmps_schedule",
+    "hmps_schedule", "hmps_svd_probe",
 ]
 
 
@@ -92,6 +92,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                            P(C.c_uint8)]
     lib.hmps_stats.argtypes = [C.c_void_p, P(hmps_stats_t)]
     lib.hmps_bond_dims.argtypes = [C.c_void_p, P(C.c_int32)]
+    lib.hmps_svd_probe.argtypes = [C.c_void_p, C.c_int32, C.c_int32,
+                                   P(C.c_double), C.c_int32, C.c_double,
+                                   P(C.c_double), P(C.c_int32),
+                                   P(C.c_double), P(C.c_double)]
     lib.hmps_destroy.argtypes = [C.c_void_p]
     lib.hmps_destroy.restype = None
     lib.hmps_last_error.argtypes = [C.c_void_p]
@@ -102,7 +106,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                   C.c_int32]
     for name in ("hmps_create", "hmps_init_cluster_env", "hmps_evolve",
                  "hmps_measure", "hmps_collapse_resample", "hmps_stats",
-                 "hmps_bond_dims", "hmps_gate", "hmps_schedule"):
+                 "hmps_bond_dims", "hmps_gate", "hmps_schedule",
+                 "hmps_svd_probe"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -258,6 +263,30 @@ class Context:
         self._check(self.lib.hmps_bond_dims(self.h, _ptr(out, C.c_int32)),
                     "hmps_bond_dims")
         return out
+
+    def hmps_svd_probe(self, theta, chi_max, cutoff):
+        """Truncated SVD of one update applied to theta' (m x n, m and n
+        multiples of 3) on the device.  Returns (sigma[k], left[3, chi_l,
+        k], right[3, k, chi_r]).  Replaces the context's chains."""
+        theta = np.ascontiguousarray(theta, np.float64)
+        m, n = theta.shape
+        if m % 3 or n % 3:
+            raise ValueError("theta dimensions must be multiples of 3")
+        chi_l, chi_r = m // 3, n // 3
+        kmax = min(m, n)
+        sigma = np.zeros(kmax, np.float64)
+        left = np.zeros(3 * chi_l * kmax, np.float64)
+        right = np.zeros(3 * kmax * chi_r, np.float64)
+        rank = C.c_int32(0)
+        self._check(self.lib.hmps_svd_probe(
+            self.h, chi_l, chi_r, _ptr(theta, C.c_double), int(chi_max),
+            float(cutoff), _ptr(sigma, C.c_double), C.byref(rank),
+            _ptr(left, C.c_double), _ptr(right, C.c_double)),
+            "hmps_svd_probe")
+        k = rank.value
+        self.n_chains, self.n_sites = 1, 2
+        return (sigma[:k].copy(), left[:3 * chi_l * k].reshape(3, chi_l, k),
+                right[:3 * k * chi_r].reshape(3, k, chi_r))
 
     def hmps_destroy(self):
         if getattr(self, "h", None):

@@ -1,0 +1,92 @@
+"""The truncated SVD of one update (blocked one-sided Jacobi, truncation,
+write-back), through the C ABI, at every size the workloads reach: up to
+theta' of 1536 x 1536 (chi_max = 512), both layouts, both SVD paths.
+
+Reference: LAPACK (numpy.linalg.svd) for the singular values and the best
+rank-k approximation, the oracle's truncation rule for k.  Spectra are
+chosen away from the cutoff threshold; the multiplet case puts the chi_max
+cut inside a degenerate run so that the tie rule decides.
+Tolerances: singular values 1e-11 sigma_0 absolute; rank-k approximation
+1e-10 ||theta|| (Frobenius); left factor orthonormal to 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle import mps
+from paper_1910_09142_amd import hmps
+
+pytestmark = pytest.mark.gpu
+
+SIGMA_FLOOR = 1e-13  # singular values below this fraction of sigma_0 are zero
+
+
+def haar(rng, n, k):
+    q, r = np.linalg.qr(rng.standard_normal((n, k)))
+    return q * np.sign(np.diag(r))
+
+
+def make_theta(rng, m, n, kind):
+    r = min(m, n)
+    if kind == "gaussian":
+        return rng.standard_normal((m, n)) / np.sqrt(m * n)
+    if kind == "decay":
+        s = np.exp(-np.arange(r) / 40.0)
+    elif kind == "multiplets":
+        # runs of 3 and 5 equal singular values (SU(2) multiplets)
+        sizes = [3, 5] * r
+        s = np.repeat(np.exp(-np.arange(len(sizes)) / 6.0), sizes)[:r]
+    elif kind == "rankdef":
+        s = np.zeros(r)
+        s[: r // 2] = np.exp(-np.arange(r // 2) / 30.0)
+    else:
+        raise ValueError(kind)
+    s = s / np.linalg.norm(s)
+    return (haar(rng, m, r) * s) @ haar(rng, n, r).T
+
+
+CASES = [
+    # chi_l, chi_r, spectrum, chi_max, cutoff
+    (32, 32, "decay", 32, 1e-12),          # 96 x 96: in-LDS path
+    (64, 128, "gaussian", 128, 1e-10),     # 192 x 384: blocked, rows orthogonalised
+    (128, 40, "multiplets", 62, 1e-10),    # 384 x 120: cap inside a multiplet
+    (256, 256, "decay", 256, 1e-10),       # 768 x 768: the chi = 256 ladder
+    (333, 100, "rankdef", 256, 1e-12),     # 999 x 300: ragged, rank deficient
+    (512, 512, "decay", 512, 1e-10),       # 1536 x 1536: the chi = 512 ladder
+]
+
+
+@pytest.mark.parametrize("chi_l,chi_r,kind,chi_max,cutoff", CASES)
+def test_truncated_svd_against_lapack(chi_l, chi_r, kind, chi_max, cutoff):
+    rng = np.random.default_rng(chi_l * 1000 + chi_r)
+    m, n = 3 * chi_l, 3 * chi_r
+    theta = make_theta(rng, m, n, kind)
+    print(f"case: svd {m}x{n} {kind} chi_max={chi_max}", flush=True)
+    ctx = hmps.Context(1, 2, max(chi_l, chi_r), 1)
+    sigma, left, right = ctx.hmps_svd_probe(theta, chi_max, cutoff)
+    ctx.hmps_destroy()
+    u, s, vt = np.linalg.svd(theta, full_matrices=False)
+    k_ref = mps.truncation_rank(s, chi_max, cutoff)
+    k_ref = min(k_ref, int((s > SIGMA_FLOOR * s[0]).sum()))
+    k = len(sigma)
+    print(f"  k gpu={k} ref={k_ref}", flush=True)
+    assert k == k_ref
+    assert np.abs(sigma - s[:k]).max() <= 1e-11 * s[0]
+    # U (left, rows (s1, a)) and Sigma V^T / ||Sigma_kept|| (right)
+    U = left.reshape(m, k)
+    R = right.transpose(1, 0, 2).reshape(k, n) * np.linalg.norm(sigma)
+    assert np.abs(U.T @ U - np.eye(k)).max() <= 1e-12
+    best = (u[:, :k] * s[:k]) @ vt[:k]
+    err = np.linalg.norm(U @ R - best) / np.linalg.norm(theta)
+    print(f"  rank-k approximation error {err:.2e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_probe_rejects_bad_arguments():
+    ctx = hmps.Context(1, 2, 8, 1)
+    with pytest.raises(hmps.HmpsError):
+        ctx.hmps_svd_probe(np.ones((3 * 9, 3)), 4, 0.0)   # chi_l > chi_cap
+    with pytest.raises(hmps.HmpsError):
+        bad = np.ones((6, 6))
+        bad[0, 0] = np.nan
+        ctx.hmps_svd_probe(bad, 4, 0.0)
+    ctx.hmps_destroy()
