@@ -179,6 +179,28 @@ hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out);
  * of n_chains * (n_sites + 1) int32).  Synchronises. */
 hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi);
 
+/* Correlators <S_i.S_j> of the current sample of every chain for
+ * arbitrary physical-site pairs (Results section: the susceptibility is
+ * built from the correlations of central spins with all spins; the same
+ * transfer-matrix strings as hmps_measure, at any distance along the MPS).
+ * site_i, site_j: host arrays of n_pairs physical ids in [0, n_phys);
+ * i == j gives s(s+1) = 2.  ss: host array, n_chains * n_pairs,
+ * ss[c * n_pairs + t].  Needs hmps_init_cluster_env; moves the
+ * orthogonality centre to site 0 if needed.  E_INVALID on bad ids.
+ * Synchronises. */
+hmps_status hmps_measure_pairs(hmps_ctx *ctx, int32_t n_pairs,
+                               const int32_t *site_i, const int32_t *site_j,
+                               double *ss);
+
+/* Susceptibility estimator of every chain (Results section, equation of
+ * chi_6): chi = (beta / 3) (1 / n_center) sum_{j in center} sum_{i in all}
+ * <S_j.S_i>, i running over every physical site including j.  center: host
+ * array of n_center physical ids (the paper averages over the middle 6 x 2
+ * sites of the ladder); chi: host array of n_chains.  beta is the inverse
+ * temperature of the ensemble (the state was evolved to beta/2). */
+hmps_status hmps_susceptibility(hmps_ctx *ctx, double beta, int32_t n_center,
+                                const int32_t *center, double *chi);
+
 /* Diagnostic: the truncated SVD that follows every two-site gate (Ancilla
  * Method subsection: the bond is restored to MPS form by an SVD truncated
  * by discarded weight; Results section: the cutoff and chi_max), applied

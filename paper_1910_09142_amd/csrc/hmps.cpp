@@ -251,9 +251,11 @@ struct hmps_ctx {
          *d_logw = nullptr, *d_disc = nullptr, *d_gates = nullptr,
          *d_envs = nullptr, *d_wsz = nullptr, *d_bscr = nullptr,
          *d_norm = nullptr, *d_bond_ss = nullptr, *d_energy = nullptr,
+         *d_pair_ss = nullptr,
          *d_qn = nullptr, *d_bond_J = nullptr;
   int32_t *d_chi = nullptr, *d_perm = nullptr, *d_knew = nullptr,
           *d_rot = nullptr, *d_done = nullptr, *d_err = nullptr,
+          *d_pair_p = nullptr, *d_pair_q = nullptr,
           *d_sweeps = nullptr, *d_near = nullptr, *d_bond_p = nullptr,
           *d_bond_q = nullptr, *d_is_cluster = nullptr,
           *d_is_ancilla = nullptr, *d_env_index = nullptr;
@@ -325,6 +327,9 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_bond_J = cv.take<double>(std::max(max_bonds, 1));
   t->d_bond_p = cv.take<int32_t>(std::max(max_bonds, 1));
   t->d_bond_q = cv.take<int32_t>(std::max(max_bonds, 1));
+  t->d_pair_ss = cv.take<double>(B * PAIR_CHUNK);
+  t->d_pair_p = cv.take<int32_t>(PAIR_CHUNK);
+  t->d_pair_q = cv.take<int32_t>(PAIR_CHUNK);
   t->d_is_cluster = cv.take<int32_t>(max_sites);
   t->d_is_ancilla = cv.take<int32_t>(max_sites);
   t->d_env_index = cv.take<int32_t>(max_sites);
@@ -905,6 +910,125 @@ hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out) {
     }
   }
   *out = s;
+  return HMPS_OK;
+}
+
+// <S_i.S_j> of every chain for physical-site pairs (i != j), written to
+// out[c * n + t]: the transfer-matrix strings of the bond measurement on a
+// list of arbitrary pairs, PAIR_CHUNK pairs per pass.
+static hmps_status measure_pairs(hmps_ctx *ctx, int n, const int32_t *si,
+                                 const int32_t *sj, double *out) {
+  if (ctx->center != 0) {
+    hmps_status st = move_center(ctx, 0);
+    if (st) return st;
+  }
+  const Plan &P = ctx->plan;
+  Batch b = batch_of(ctx);
+  hipStream_t s = ctx->stream;
+  MeasureArgs ma;
+  ma.bond_p = ctx->d_pair_p;
+  ma.bond_q = ctx->d_pair_q;
+  ma.bond_J = nullptr;
+  ma.is_ancilla = ctx->d_is_ancilla;
+  ma.envs = ctx->d_envs;
+  ma.wsz = ctx->d_wsz;
+  ma.bond_scratch = ctx->d_bscr;
+  ma.slots = ctx->slots;
+  ma.chi2 = ctx->chi2;
+  ma.norm = ctx->d_norm;
+  ma.bond_ss = ctx->d_pair_ss;
+  launch_measure_envs(b, ma, s);
+  std::vector<int32_t> pp(PAIR_CHUNK), qq(PAIR_CHUNK);
+  std::vector<double> chunk((size_t)ctx->B * PAIR_CHUNK);
+  for (int t0 = 0; t0 < n; t0 += PAIR_CHUNK) {
+    const int cnt = std::min(PAIR_CHUNK, n - t0);
+    for (int t = 0; t < cnt; ++t) {
+      const int a = P.pos_of_phys[si[t0 + t]], c = P.pos_of_phys[sj[t0 + t]];
+      pp[t] = std::min(a, c);
+      qq[t] = std::max(a, c);
+    }
+    HIPCHK(hipMemcpyAsync(ctx->d_pair_p, pp.data(), sizeof(int32_t) * cnt,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ctx->d_pair_q, qq.data(), sizeof(int32_t) * cnt,
+                          hipMemcpyHostToDevice, s));
+    ma.n_bonds = cnt;
+    for (int b0 = 0; b0 < cnt; b0 += ctx->slots)
+      launch_measure_bonds(b, ma, b0, std::min(ctx->slots, cnt - b0), s);
+    launch_measure_scale(b, ma, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(chunk.data(), ctx->d_pair_ss,
+                          sizeof(double) * ctx->B * cnt,
+                          hipMemcpyDeviceToHost, s));
+    // the host arrays are reused by the next pass
+    HIPCHK(hipStreamSynchronize(s));
+    for (int c = 0; c < ctx->B; ++c)
+      for (int t = 0; t < cnt; ++t)
+        out[(size_t)c * n + t0 + t] = chunk[(size_t)c * cnt + t];
+  }
+  return HMPS_OK;
+}
+
+hmps_status hmps_measure_pairs(hmps_ctx *ctx, int32_t n_pairs,
+                               const int32_t *site_i, const int32_t *site_j,
+                               double *ss) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  if (n_pairs < 0 || (n_pairs > 0 && (!site_i || !site_j || !ss)))
+    return fail(ctx, HMPS_E_INVALID, "bad pair arrays");
+  const int np = ctx->plan.n_phys;
+  std::vector<int32_t> ii, jj;
+  std::vector<int> where;
+  for (int t = 0; t < n_pairs; ++t) {
+    if (site_i[t] < 0 || site_i[t] >= np || site_j[t] < 0 || site_j[t] >= np)
+      return fail(ctx, HMPS_E_INVALID, "site id outside [0, n_phys)");
+    if (site_i[t] != site_j[t]) {
+      ii.push_back(site_i[t]);
+      jj.push_back(site_j[t]);
+      where.push_back(t);
+    }
+  }
+  std::vector<double> vals((size_t)ctx->B * ii.size());
+  if (!ii.empty()) {
+    st = measure_pairs(ctx, (int)ii.size(), ii.data(), jj.data(), vals.data());
+    if (st) return st;
+  }
+  // S_i.S_i = s(s+1) = 2 for spin 1
+  for (int c = 0; c < ctx->B; ++c) {
+    for (int t = 0; t < n_pairs; ++t) ss[(size_t)c * n_pairs + t] = 2.0;
+    for (size_t u = 0; u < ii.size(); ++u)
+      ss[(size_t)c * n_pairs + where[u]] = vals[(size_t)c * ii.size() + u];
+  }
+  return HMPS_OK;
+}
+
+hmps_status hmps_susceptibility(hmps_ctx *ctx, double beta, int32_t n_center,
+                                const int32_t *center, double *chi) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  const int np = ctx->plan.n_phys;
+  if (n_center < 1 || !center || !chi || !(beta >= 0.0))
+    return fail(ctx, HMPS_E_INVALID, "bad susceptibility arguments");
+  std::vector<int32_t> ii, jj;
+  for (int t = 0; t < n_center; ++t) {
+    if (center[t] < 0 || center[t] >= np)
+      return fail(ctx, HMPS_E_INVALID, "center site outside [0, n_phys)");
+    for (int i = 0; i < np; ++i)
+      if (i != center[t]) {
+        ii.push_back(center[t]);
+        jj.push_back(i);
+      }
+  }
+  std::vector<double> vals((size_t)ctx->B * ii.size());
+  if (!ii.empty()) {
+    st = measure_pairs(ctx, (int)ii.size(), ii.data(), jj.data(), vals.data());
+    if (st) return st;
+  }
+  for (int c = 0; c < ctx->B; ++c) {
+    // the i = j terms: S_j.S_j = 2
+    double sum = 2.0 * n_center;
+    for (size_t u = 0; u < ii.size(); ++u) sum += vals[(size_t)c * ii.size() + u];
+    chi[c] = beta / 3.0 * sum / n_center;
+  }
   return HMPS_OK;
 }
 

@@ -107,6 +107,11 @@ void launch_measure_bonds(const Batch &b, const MeasureArgs &m, int b0,
                           int nb, hipStream_t st);
 void launch_measure_finish(const Batch &b, const MeasureArgs &m,
                            double *energy, double *qn, hipStream_t st);
+// bond_ss[c][i] /= norm[c] for i < n_bonds (correlators of arbitrary pairs)
+void launch_measure_scale(const Batch &b, const MeasureArgs &m,
+                          hipStream_t st);
+// site pairs measured per pass by hmps_measure_pairs
+constexpr int PAIR_CHUNK = 256;
 
 struct CollapseArgs {
   const int32_t *is_cluster;  // [nsites]

@@ -126,6 +126,14 @@ __global__ void __launch_bounds__(NT)
   if (threadIdx.x == 0) ma.bond_ss[(size_t)c * ma.n_bonds + bond] = total;
 }
 
+// Correlators of arbitrary site pairs: divide by the norm <psi|psi>.
+__global__ void k_measure_scale(Batch b, MeasureArgs ma) {
+  const int c = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b.B || i >= ma.n_bonds) return;
+  ma.bond_ss[(size_t)c * ma.n_bonds + i] /= ma.norm[c];
+}
+
 __global__ void k_measure_finish(Batch b, MeasureArgs ma, double *energy,
                                  double *qn) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -258,6 +266,12 @@ void launch_measure_finish(const Batch &b, const MeasureArgs &m,
                            double *energy, double *qn, hipStream_t st) {
   hipLaunchKernelGGL(k_measure_finish, dim3((b.B + 255) / 256), dim3(256), 0,
                      st, b, m, energy, qn);
+}
+
+void launch_measure_scale(const Batch &b, const MeasureArgs &m,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_measure_scale, dim3((m.n_bonds + NT - 1) / NT, b.B),
+                     dim3(NT), 0, st, b, m);
 }
 
 void launch_collapse(const Batch &b, const CollapseArgs &a, hipStream_t st) {

@@ -28,7 +28,8 @@ EXPORTS = [
     "hmps_workspace_bytes", "hmps_create", "hmps_init_cluster_env",
     "hmps_evolve", "hmps_measure", "hmps_collapse_resample", "hmps_stats",
     "hmps_bond_dims", "hmps_destroy", "hmps_last_error", "hmps_gate",
-    "hmps_schedule", "hmps_svd_probe",
+    "hmps_schedule", "hmps_svd_probe", "hmps_measure_pairs",
+    "hmps_susceptibility",
 ]
 
 
@@ -92,6 +93,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                            P(C.c_uint8)]
     lib.hmps_stats.argtypes = [C.c_void_p, P(hmps_stats_t)]
     lib.hmps_bond_dims.argtypes = [C.c_void_p, P(C.c_int32)]
+    lib.hmps_measure_pairs.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32),
+                                       P(C.c_int32), P(C.c_double)]
+    lib.hmps_susceptibility.argtypes = [C.c_void_p, C.c_double, C.c_int32,
+                                        P(C.c_int32), P(C.c_double)]
     lib.hmps_svd_probe.argtypes = [C.c_void_p, C.c_int32, C.c_int32,
                                    P(C.c_double), C.c_int32, C.c_double,
                                    P(C.c_double), P(C.c_int32),
@@ -107,7 +112,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     for name in ("hmps_create", "hmps_init_cluster_env", "hmps_evolve",
                  "hmps_measure", "hmps_collapse_resample", "hmps_stats",
                  "hmps_bond_dims", "hmps_gate", "hmps_schedule",
-                 "hmps_svd_probe"):
+                 "hmps_svd_probe", "hmps_measure_pairs",
+                 "hmps_susceptibility"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -262,6 +268,27 @@ class Context:
         out = np.zeros((self.n_chains, self.n_sites + 1), np.int32)
         self._check(self.lib.hmps_bond_dims(self.h, _ptr(out, C.c_int32)),
                     "hmps_bond_dims")
+        return out
+
+    def hmps_measure_pairs(self, pairs):
+        """<S_i.S_j> for physical-site pairs [(i, j)]: array [n_chains,
+        n_pairs]."""
+        pairs = np.asarray(pairs, np.int32).reshape(-1, 2)
+        si = np.ascontiguousarray(pairs[:, 0])
+        sj = np.ascontiguousarray(pairs[:, 1])
+        out = np.zeros((self.n_chains, len(pairs)), np.float64)
+        self._check(self.lib.hmps_measure_pairs(
+            self.h, len(pairs), _ptr(si, C.c_int32), _ptr(sj, C.c_int32),
+            _ptr(out, C.c_double)), "hmps_measure_pairs")
+        return out
+
+    def hmps_susceptibility(self, beta, center):
+        """(beta/3) mean over j in center of sum_i <S_j.S_i>, per chain."""
+        center = np.ascontiguousarray(center, np.int32)
+        out = np.zeros(self.n_chains, np.float64)
+        self._check(self.lib.hmps_susceptibility(
+            self.h, float(beta), len(center), _ptr(center, C.c_int32),
+            _ptr(out, C.c_double)), "hmps_susceptibility")
         return out
 
     def hmps_svd_probe(self, theta, chi_max, cutoff):

@@ -64,5 +64,12 @@ def ladder_arrays(L: int, J_leg: float, J_rung: float, W: int,
     return 2 * L, bonds, order, mask
 
 
+def central_sites(L: int, ncols: int = 6):
+    """Physical ids of the middle ncols x 2 sites of a 2 x L ladder (the
+    centre set of the susceptibility estimator; the paper uses 6 x 2)."""
+    c0 = (L - ncols) // 2
+    return [2 * c + leg for c in range(c0, c0 + ncols) for leg in range(2)]
+
+
 def mps_length(L: int, W: int) -> int:
     return 2 * L + 2 * W
