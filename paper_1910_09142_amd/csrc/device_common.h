@@ -82,10 +82,9 @@ static __device__ __forceinline__ bool jacobi_rotation(double a, double b, doubl
   return true;
 }
 
-// Stride between consecutive vectors of the L x N vector matrix: L rounded
-// up to a multiple of 4, so that four consecutive rows are one aligned
-// 32-byte load.
-static __device__ __forceinline__ int vec_ld(int L) { return (L + 3) & ~3; }
+// Stride between consecutive vectors of the vector matrix (see
+// vector_stride): four consecutive rows are one aligned 32-byte load.
+static __device__ __forceinline__ int vec_ld(int L) { return vector_stride(L); }
 
 
 // Sum over the workgroup; every thread gets the result.

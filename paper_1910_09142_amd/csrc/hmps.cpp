@@ -289,9 +289,8 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   const int mc = 3 * chi_cap;
   // padded vector count: an even number of blocks of JB vectors
   const int n_cap = (mc + 2 * JB - 1) / (2 * JB) * (2 * JB);
-  // vectors of length L <= 3 chi_cap are stored with a stride rounded up to
-  // a multiple of 4 (aligned 32-byte loads of four rows)
-  const size_t th_stride = (size_t)((mc + 3) & ~3) * n_cap;
+  // vectors of length L <= 3 chi_cap are stored with stride vector_stride
+  const size_t th_stride = (size_t)vector_stride(mc) * n_cap;
   const int slots = std::max(2, std::min(std::max(max_bonds, 1), 8));
   hmps_ctx tmp;
   hmps_ctx *t = c ? c : &tmp;
@@ -493,7 +492,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       const int nvec = 3 * std::min(row[k], row[k + 2]);
       const int len = 3 * std::max(row[k], row[k + 2]);
       const int nb = n_blocks_even(nvec, JB);
-      round_bytes[c] = (double)(nb - 1) * nb * JB * ((len + 3) & ~3) * 8.0;
+      round_bytes[c] = (double)(nb - 1) * nb * JB * vector_stride(len) * 8.0;
     }
     HIPCHK(hipEventRecord(ctx->svd_ev[0], st));
     hmps_status est = enqueue_sweep(0);
@@ -1067,9 +1066,10 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
   HIPCHK(hipMemsetAsync(ctx->d_disc, 0, sizeof(double), s));
   HIPCHK(hipMemsetAsync(ctx->d_logw, 0, sizeof(double), s));
   // theta' in the vector layout of the SVD: the min(m, n) vectors of length
-  // max(m, n), stride rounded up to 4, column-major
+  // max(m, n), stride vector_stride, column-major, zero padding rows
   const bool trans = n > m;
-  const int len = trans ? n : m, nvec = trans ? m : n, ld = (len + 3) & ~3;
+  const int len = trans ? n : m, nvec = trans ? m : n,
+            ld = vector_stride(len);
   std::vector<double> h((size_t)ld * nvec, 0.0);
   for (int r = 0; r < m; ++r)
     for (int c = 0; c < n; ++c)

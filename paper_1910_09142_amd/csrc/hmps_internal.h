@@ -10,6 +10,14 @@ namespace hmps {
 // Jacobi column-block width of the large-matrix SVD path; a block pair is
 // 2 JB vectors.
 constexpr int JB = 16;
+// Stride between consecutive vectors of the L x N vector matrix: L rounded
+// up to a multiple of 16, so that every 16-row chunk of a vector lies
+// inside it (the padding rows are zero) and the Jacobi kernels load and
+// store whole chunks without bounds tests.
+__host__ __device__ inline int vector_stride(int len) {
+  return (len + 15) & ~15;
+}
+
 // Number of column blocks, rounded up to an even count.
 __host__ __device__ inline int n_blocks_even(int nvec, int jb) {
   const int nb = (nvec + jb - 1) / jb;

@@ -182,7 +182,11 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   // e0 + 4 lk .. e0 + 4 lk + 3 of vector li of both blocks as aligned
   // 32-byte loads; MFMA step q takes row e0 + 4 lk + q of both operands
   // (the Gram sums over rows, so their order is free) and the three upper
-  // tiles are accumulated from the same loads.  Rows L..ld-1 are zero.
+  // tiles are accumulated from the same loads.  Rows L..ld-1 are zero and
+  // ld is a multiple of 16, so chunks are loaded without bounds tests (a
+  // branch around a load makes the compiler wait for every load in flight,
+  // which would serialise the prefetch); past the last chunk the prefetch
+  // re-reads the last one.
   if (tid == 0) {
     flag[0] = 0;
     flag[1] = 0;
@@ -205,40 +209,45 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     v4d acc[NTILE];
 #pragma unroll
     for (int t = 0; t < NTILE; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    const double *xa = X + (size_t)colidx(li) * ld;
-    const double *xb = X + (size_t)colidx(JB + li) * ld;
-    // native vector type: HIP's double4 is a union and, assigned through
-    // references, left dead stores to scratch
-    v4d ca, cb, na, nb;
+    const double *xa = X + (size_t)colidx(li) * ld + 4 * lk;
+    const double *xb = X + (size_t)colidx(JB + li) * ld + 4 * lk;
     auto load = [&](const double *x, int e0) -> v4d {
-      const int e = e0 + 4 * lk;
-      return e < ld ? *reinterpret_cast<const v4d *>(x + e)
-                    : v4d{0.0, 0.0, 0.0, 0.0};
+      return *reinterpret_cast<const v4d *>(x + e0);
     };
+    auto gram4 = [&](const v4d &a, const v4d &b) {
+      acc[0] = mfma_f64(a.x, a.x, acc[0]);
+      acc[1] = mfma_f64(a.x, b.x, acc[1]);
+      acc[2] = mfma_f64(b.x, b.x, acc[2]);
+      acc[0] = mfma_f64(a.y, a.y, acc[0]);
+      acc[1] = mfma_f64(a.y, b.y, acc[1]);
+      acc[2] = mfma_f64(b.y, b.y, acc[2]);
+      acc[0] = mfma_f64(a.z, a.z, acc[0]);
+      acc[1] = mfma_f64(a.z, b.z, acc[1]);
+      acc[2] = mfma_f64(b.z, b.z, acc[2]);
+      acc[0] = mfma_f64(a.w, a.w, acc[0]);
+      acc[1] = mfma_f64(a.w, b.w, acc[1]);
+      acc[2] = mfma_f64(b.w, b.w, acc[2]);
+    };
+    // two register buffers, unrolled by two: the next chunk's loads are
+    // issued before this chunk's products (the compiler barrier keeps them
+    // there) and no register copy forces an early wait
+    const int elast = ld - 16;
     int e0 = 16 * w;
-    if (e0 < L) {
-      ca = load(xa, e0);
-      cb = load(xb, e0);
-    }
-    for (; e0 < L; e0 += CSTEP) {
-      if (e0 + CSTEP < L) {
-        na = load(xa, e0 + CSTEP);
-        nb = load(xb, e0 + CSTEP);
-      }
-      acc[0] = mfma_f64(ca.x, ca.x, acc[0]);
-      acc[1] = mfma_f64(ca.x, cb.x, acc[1]);
-      acc[2] = mfma_f64(cb.x, cb.x, acc[2]);
-      acc[0] = mfma_f64(ca.y, ca.y, acc[0]);
-      acc[1] = mfma_f64(ca.y, cb.y, acc[1]);
-      acc[2] = mfma_f64(cb.y, cb.y, acc[2]);
-      acc[0] = mfma_f64(ca.z, ca.z, acc[0]);
-      acc[1] = mfma_f64(ca.z, cb.z, acc[1]);
-      acc[2] = mfma_f64(cb.z, cb.z, acc[2]);
-      acc[0] = mfma_f64(ca.w, ca.w, acc[0]);
-      acc[1] = mfma_f64(ca.w, cb.w, acc[1]);
-      acc[2] = mfma_f64(cb.w, cb.w, acc[2]);
-      ca = na;
-      cb = nb;
+    v4d a0 = load(xa, min(e0, elast)), b0 = load(xb, min(e0, elast));
+    v4d a1, b1;
+    while (e0 < L) {
+      const int e1 = min(e0 + CSTEP, elast);
+      a1 = load(xa, e1);
+      b1 = load(xb, e1);
+      asm volatile("" ::: "memory");
+      gram4(a0, b0);
+      if (e0 + CSTEP >= L) break;
+      const int e2 = min(e0 + 2 * CSTEP, elast);
+      a0 = load(xa, e2);
+      b0 = load(xb, e2);
+      asm volatile("" ::: "memory");
+      gram4(a1, b1);
+      e0 += 2 * CSTEP;
     }
     // fixed-order sum of the eight wave partials: step j adds waves
     // 4 j .. 4 j + 3 into slots 0 .. 3
@@ -414,33 +423,42 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
   for (int kk = 0; kk < KB; ++kk) coff[kk] = colidx(4 * kk + lk) * ld;
   double cur[KB], nxt[KB];
+  // rows L..ld-1 are zero and stay zero under the rotation, and every
+  // 16-row chunk lies inside ld: loads and stores need no bounds tests
   auto load_chunk = [&](int e0, double *v) {
     const int e = e0 + li;
 #pragma unroll
-    for (int kk = 0; kk < KB; ++kk) v[kk] = e < L ? X[coff[kk] + e] : 0.0;
+    for (int kk = 0; kk < KB; ++kk) v[kk] = X[coff[kk] + e];
   };
   constexpr int CSTEP = 16 * NWAVE;
-  if (16 * w < L) load_chunk(16 * w, cur);
-  for (int e0 = 16 * w; e0 < L; e0 += CSTEP) {
-    if (e0 + CSTEP < L) load_chunk(e0 + CSTEP, nxt);
+  auto rotate16 = [&](int e0, const double *v) {
     v4d d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
-    const int e = e0 + li;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
-      d0 = mfma_f64(Q[4 * kk + lk][li], cur[kk], d0);
-      d1 = mfma_f64(Q[4 * kk + lk][16 + li], cur[kk], d1);
+      d0 = mfma_f64(Q[4 * kk + lk][li], v[kk], d0);
+      d1 = mfma_f64(Q[4 * kk + lk][16 + li], v[kk], d1);
     }
-#pragma unroll
-    for (int kk = 0; kk < KB; ++kk) cur[kk] = nxt[kk];
     // D[i][j] (vector 16 t + i, row e0 + j) sits in lane j + 16 (i % 4),
     // element i / 4: vector 16 t + lk + 4 q = 4 (4 t + q) + lk
-    if (e < L) {
+    const int e = e0 + li;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        X[coff[q] + e] = d0[q];
-        X[coff[4 + q] + e] = d1[q];
-      }
+    for (int q = 0; q < 4; ++q) {
+      X[coff[q] + e] = d0[q];
+      X[coff[4 + q] + e] = d1[q];
     }
+  };
+  // two register buffers, unrolled by two, as in the Gram loop
+  int e0 = 16 * w;
+  load_chunk(min(e0, ld - 16), cur);
+  while (e0 < L) {
+    load_chunk(min(e0 + CSTEP, ld - 16), nxt);
+    asm volatile("" ::: "memory");
+    rotate16(e0, cur);
+    if (e0 + CSTEP >= L) break;
+    load_chunk(min(e0 + 2 * CSTEP, ld - 16), cur);
+    asm volatile("" ::: "memory");
+    rotate16(e0 + CSTEP, nxt);
+    e0 += 2 * CSTEP;
   }
   if (tid == 0) atomicAdd(&s.rot_cur[c], 1);
 }
