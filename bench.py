@@ -132,9 +132,10 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this path shards independent "
-              "Markov chains over GPUs with no communication, and no run on "
-              "more than one GPU is part of this build", file=sys.stderr)
+        print("bench.py measures one GPU only: the chains are independent "
+              "Markov chains that shard over GPUs without communication, and "
+              "this benchmark does not run on more than one GPU",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1910_09142_amd import hmps, workloads
