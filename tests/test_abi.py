@@ -43,6 +43,21 @@ def test_schedule_matches_oracle(L, W, Jr):
     assert ups == [(k, op) for (k, op) in sch.step]
 
 
+@pytest.mark.parametrize("L,sites", [(3, {0, 3, 4}), (4, {0, 1, 4, 5}),
+                                     (6, {1, 2, 7, 8, 11}), (5, set())])
+def test_schedule_matches_oracle_for_any_cluster_mask(L, sites):
+    # checkerboard / interleaved / scattered purified sites
+    base = model.ladder(L, 1.0, 1.0, W=0)
+    mask = [int(i in sites) for i in range(base.n_phys)]
+    olat = model.Lattice(base.n_phys, base.bonds, base.order,
+                         [bool(m) for m in mask])
+    ns, ups = hmps.hmps_schedule(hmps.Lattice(base.n_phys, base.bonds,
+                                              base.order, mask))
+    lay = model.layout(olat)
+    assert ns == lay.length == base.n_phys + len(sites)
+    assert ups == [(k, op) for (k, op) in model.schedule(olat).step]
+
+
 @pytest.mark.parametrize("J,x", [(1.0, 0.025), (0.5, 0.05), (2.0, 0.3)])
 def test_gate_matches_expm(J, x):
     h = exact.bond_operator(0, 1, 2)
