@@ -54,12 +54,20 @@ KERNEL_SOURCES = ("jacobi.hip", "device_common.h", "hmps_internal.h")
 
 
 def kernel_source_hash():
+    """SHA-256 of the round-kernel sources with comments removed and runs of
+    whitespace collapsed: edits to comments keep a measurement valid, any
+    change to the code does not."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1910_09142_amd", "csrc", name),
-                  "rb") as f:
-            h.update(f.read())
+                  encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        text = " ".join(text.split())
+        h.update(name.encode() + b"\0" + text.encode() + b"\0")
     return h.hexdigest()
 
 
