@@ -2,21 +2,23 @@
 // (the SVD that restores the MPS form after every two-site gate;
 // Chen & Stoudenmire, arXiv:1910.09142, Results section).
 //
-// The N vectors (columns of the L x N vector matrix X, stride ld, column-
-// major) are split into NB (even) blocks of JB = 16 vectors.  A sweep has
-// NB-1 rounds;
-// in a round the blocks are paired by the circle method and one workgroup
-// of eight wavefronts handles one block pair of one chain:
-//   1. Gram matrix G = Xp^T Xp of the 2 JB vectors, in 16 x 16 tiles
-//      (FP64 MFMA fed by coalesced 32-byte loads of four rows), summed in
-//      LDS in a fixed order;
-//   2. if every off-diagonal element is below tol sqrt(G_ii G_jj) the pair
-//      is orthogonal: record the squared norms and stop;
-//   3. one cyclic two-sided Jacobi sweep on G in LDS accumulating the
-//      rotations in Q (each 2 x 2 block of a rotation round of G, and each
-//      (row, column pair) item of Q, has one owner: in place);
-//   4. Xp <- Xp Q (FP64 MFMA, 16-row chunks over eight wavefronts,
-//      coalesced stores).
+// The N vectors (columns of the L x N vector matrix X, stride ld = L
+// rounded up to 16, column-major) are split into NB (even) blocks of
+// JB = 16 vectors.  A sweep has NB-1 rounds; in a round the blocks are
+// paired by the circle method and one workgroup of eight wavefronts handles
+// one block pair of one chain:
+//   1. Gram matrix G = Xp^T Xp of the 2 JB vectors: its three upper 16 x 16
+//      tiles by FP64 MFMA from coalesced 32-byte loads of four rows, the
+//      next chunk in flight while the current one is multiplied; the eight
+//      wavefront partials are summed in LDS in a fixed order;
+//   2. if every pair the round rotates is orthogonal to tol sqrt(G_ii G_jj),
+//      record the squared norms and stop;
+//   3. one cyclic two-sided Jacobi sweep on the upper triangle of G in LDS,
+//      rotations accumulated in Q, one barrier per rotation round (all
+//      pairs in the first round of a sweep, the pairs across the two blocks
+//      afterwards);
+//   4. Xp <- Xp Q (FP64 MFMA, 16-row chunks over eight wavefronts, loads
+//      of the next chunk in flight, coalesced stores).
 #include "device_common.h"
 
 namespace hmps {
