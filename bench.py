@@ -95,6 +95,25 @@ def measured_traffic(wl):
         return None
 
 
+def model_steps(wl):
+    """Trotter steps of one evolution to beta/2."""
+    return int(round(wl.beta / (2.0 * wl.tau)))
+
+
+def prefix_rate(marks, t0, n_updates, per_step):
+    """(steps, updates, updates/s) of the GPU over the fewest leading
+    Trotter steps of the timed sample that cover n_updates, from the
+    (steps done, time) marks of the progress callback; None without marks."""
+    if not marks or per_step <= 0:
+        return None
+    need = max(1, int(-(-n_updates // per_step)))
+    for done, t in marks:
+        if done >= need and t > t0:
+            ups = int(round(done * per_step))
+            return done, ups, ups / (t - t0)
+    return None
+
+
 def cpu_baseline(wl, seconds):
     """The FP64 oracle on the same workload: chain 0, seed 0, sample 0,
     Trotter updates in order until the time budget is spent."""
@@ -128,7 +147,7 @@ def cpu_baseline(wl, seconds):
     dt = time.perf_counter() - t0
     total = M * len(sch.step)
     return {"value": n / dt, "unit": UNIT, "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "n_updates": n,
             "sample": (f"first {n} of the {total} Trotter updates of sample 0 "
                        f"(chain 0, seed {wl.seed}); chi reached "
                        f"{st.max_chi} of {wl.chi_max}; the rest of the "
@@ -154,12 +173,14 @@ def main():
                                                     wl.J_rung, wl.W)
     lat = hmps.Lattice(n, bonds, order, mask)
     t_start = time.perf_counter()
+    step_marks = []  # (Trotter steps done, time) of the first timed sample
 
     def progress(done, total):
         # one line per Trotter step: evolutions at chi = 256 take minutes
-        print(f"trotter step {done}/{total} "
-              f"({time.perf_counter() - t_start:.1f} s)", file=sys.stderr,
-              flush=True)
+        now = time.perf_counter()
+        step_marks.append((done, now))
+        print(f"trotter step {done}/{total} ({now - t_start:.1f} s)",
+              file=sys.stderr, flush=True)
 
     precision = (hmps.PREC_MIXED_FP32 if args.precision == "mixed"
                  else hmps.PREC_FP64)
@@ -182,8 +203,12 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     energies = []
+    timed_marks = None
     for _ in range(args.steps):
+        step_marks.clear()
         m = one_sample(sample)
+        if timed_marks is None:
+            timed_marks = list(step_marks)
         energies += m["energy"].tolist()
         sample += 1
         print(f"timed sample done ({time.perf_counter() - t0:.1f} s)",
@@ -235,7 +260,19 @@ def main():
     }
     ctx.hmps_destroy()
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        cb = cpu_baseline(wl, args.cpu_seconds)
+        # the oracle covers only the first updates of the sample (small chi):
+        # the GPU's rate over the same leading Trotter steps, for comparison
+        per_step = trotter_updates / max(1, args.steps) / max(
+            1, model_steps(wl))
+        g = (prefix_rate(timed_marks or [], t0, cb["n_updates"], per_step)
+             if B == 1 else None)
+        if g is not None:
+            cb["sample"] += (f"; the GPU ran the first {g[0]} Trotter steps "
+                             f"of the timed sample ({g[1]} updates) at "
+                             f"{g[2]:.1f} updates/s")
+        del cb["n_updates"]
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

@@ -36,3 +36,13 @@ def test_traffic_is_used_only_for_the_measured_sources(monkeypatch):
     assert bench.measured_traffic(workloads.C3) is None
     # a workload without a counter summary has no traffic figure
     assert bench.measured_traffic(workloads.C1) is None
+
+
+def test_prefix_rate_covers_the_oracle_updates():
+    marks = [(i, 100.0 + 2.0 * i) for i in range(1, 51)]
+    # 2573 updates at 252 per Trotter step need 11 steps
+    assert bench.prefix_rate(marks, 100.0, 2573, 252.0) == (11, 2772, 126.0)
+    assert bench.prefix_rate(marks, 100.0, 252, 252.0) == (1, 252, 126.0)
+    assert bench.prefix_rate([], 100.0, 10, 252.0) is None
+    assert bench.prefix_rate(marks, 100.0, 10 ** 9, 252.0) is None
+    assert bench.model_steps(workloads.C3) == 50
