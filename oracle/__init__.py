@@ -17,6 +17,8 @@ arXiv:1910.09142, that it follows):
 * ``mps``     the MPS state, two-site Trotter updates with truncated SVD,
   measurement and the sequential projective collapse.
 * ``hybrid``  the Markov chain of the hybrid METTS-ancilla algorithm.
+* ``observables``  long-range correlators and the susceptibility estimator.
 
-Parity status of each function is listed in its module header.
+Parity status (what pins each function, or "parity unpinned") is listed in
+each module header.
 """

@@ -4,6 +4,10 @@ estimator built from them.
 
 Test infrastructure: the reference the GPU path is checked against, never
 called by it.
+
+Parity: pinned against dense exact diagonalisation of sum_{j in C} sum_i
+S_j.S_i through the exhaustive hybrid identity (any centre set C, both
+bases) and against product states, where <S_i.S_j> = m_i m_j.
 """
 from __future__ import annotations
 
