@@ -197,7 +197,9 @@ hmps_status hmps_measure_pairs(hmps_ctx *ctx, int32_t n_pairs,
  * <S_j.S_i>, i running over every physical site including j.  center: host
  * array of n_center physical ids (the paper averages over the middle 6 x 2
  * sites of the ladder); chi: host array of n_chains.  beta is the inverse
- * temperature of the ensemble (the state was evolved to beta/2). */
+ * temperature of the ensemble (the state was evolved to beta/2).  Needs
+ * hmps_init_cluster_env; E_INVALID for an id outside [0, n_phys),
+ * n_center < 1 or beta < 0.  Synchronises. */
 hmps_status hmps_susceptibility(hmps_ctx *ctx, double beta, int32_t n_center,
                                 const int32_t *center, double *chi);
 
