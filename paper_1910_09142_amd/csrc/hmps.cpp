@@ -401,6 +401,19 @@ void init_host_chi(hmps_ctx *ctx) {
           (ctx->plan.is_cluster[p] && !ctx->plan.is_ancilla[p]) ? 3 : 1;
 }
 
+// Makes the context's device current for the duration of a call and
+// restores the caller's device afterwards.
+struct DeviceGuard {
+  int prev = -1, dev;
+  explicit DeviceGuard(int d) : dev(d) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+  }
+};
+
 hmps_status check_usable(hmps_ctx *ctx, bool need_init) {
   if (!ctx) return HMPS_E_INVALID;
   if (ctx->poisoned)
@@ -623,12 +636,14 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
     ctx->opt.jacobi_tol = 8.0 * std::sqrt(3.0 * opt->chi_cap) * 2.220446e-16;
   }
   ctx->stream = reinterpret_cast<hipStream_t>(opt->stream);
+  DeviceGuard guard(opt->device);
   if (const char *e = std::getenv("HMPS_SYNC_DEBUG")) ctx->sync_debug = e[0] == '1';
   if (const char *e = std::getenv("HMPS_INNER")) ctx->inner_sweeps = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("HMPS_SKIP")) ctx->skip = std::min(1e-26, std::atof(e));
   if (const char *e = std::getenv("HMPS_CROSS")) ctx->cross_inner = e[0] == '1';
-  hipError_t e = hipSetDevice(opt->device);
-  if (e != hipSuccess) {
+  int current = -1;
+  hipError_t e = hipGetDevice(&current);
+  if (e != hipSuccess || current != opt->device) {
     delete ctx;
     return HMPS_E_DEVICE;
   }
@@ -640,7 +655,7 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
     e = hipHostMalloc((void **)&ctx->h_stage,
                     sizeof(int32_t) * 4 * opt->max_chains);
   if (e != hipSuccess) {
-    delete ctx;
+    hmps_destroy(ctx);  // releases what was created so far
     return HMPS_E_DEVICE;
   }
   carve(ctx, reinterpret_cast<char *>(opt->workspace), opt->max_chains,
@@ -651,6 +666,7 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
 
 void hmps_destroy(hmps_ctx *ctx) {
   if (!ctx) return;
+  DeviceGuard guard(ctx->opt.device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   for (hipEvent_t ev : ctx->sweep_ev)
@@ -669,6 +685,7 @@ hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
                                   const uint8_t *env_state, int32_t basis) {
   hmps_status st = check_usable(ctx, false);
   if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
   Plan P;
   std::string why = validate_and_plan(lat, P);
   if (!why.empty()) return fail(ctx, HMPS_E_INVALID, why);
@@ -749,6 +766,7 @@ hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
                         int32_t chi_max, double cutoff) {
   hmps_status st = check_usable(ctx, true);
   if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
   if (!(std::isfinite(beta) && beta >= 0.0))
     return fail(ctx, HMPS_E_INVALID, "beta must be finite and >= 0");
   if (chi_max < 1 || chi_max > ctx->opt.chi_cap)
@@ -804,6 +822,7 @@ hmps_status hmps_measure(hmps_ctx *ctx, double *energy, double *bond_ss,
                          double *logw, double *qn) {
   hmps_status st = check_usable(ctx, true);
   if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
   if (ctx->center != 0) {
     st = move_center(ctx, 0);
     if (st) return st;
@@ -851,6 +870,7 @@ hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
                                    uint8_t *env_out) {
   hmps_status st = check_usable(ctx, true);
   if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
   if (basis != 0 && basis != 1)
     return fail(ctx, HMPS_E_INVALID, "basis must be 0 or 1");
   if (ctx->center != 0) {
@@ -972,6 +992,7 @@ hmps_status hmps_measure_pairs(hmps_ctx *ctx, int32_t n_pairs,
                                double *ss) {
   hmps_status st = check_usable(ctx, true);
   if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
   if (n_pairs < 0 || (n_pairs > 0 && (!site_i || !site_j || !ss)))
     return fail(ctx, HMPS_E_INVALID, "bad pair arrays");
   const int np = ctx->plan.n_phys;
@@ -1004,6 +1025,7 @@ hmps_status hmps_susceptibility(hmps_ctx *ctx, double beta, int32_t n_center,
                                 const int32_t *center, double *chi) {
   hmps_status st = check_usable(ctx, true);
   if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
   const int np = ctx->plan.n_phys;
   if (n_center < 1 || !center || !chi || !(beta >= 0.0))
     return fail(ctx, HMPS_E_INVALID, "bad susceptibility arguments");
@@ -1037,6 +1059,7 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
                            double *left, double *right) {
   hmps_status st = check_usable(ctx, false);
   if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
   if (!theta || !sigma || !rank)
     return fail(ctx, HMPS_E_INVALID, "theta, sigma and rank must not be NULL");
   if (chi_l < 1 || chi_r < 1 || chi_l > ctx->opt.chi_cap ||
@@ -1099,6 +1122,7 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
 hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi) {
   hmps_status st = check_usable(ctx, true);
   if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
   if (!chi) return fail(ctx, HMPS_E_INVALID, "chi is NULL");
   HIPCHK(hipMemcpyAsync(chi, ctx->d_chi,
                         sizeof(int32_t) * ctx->B * (ctx->plan.len + 1),
