@@ -96,26 +96,51 @@ __global__ void __launch_bounds__(NT) k_theta(Batch b, UpdScratch s, UpdParams u
   typename M::V acc[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) acc[t] = typename M::V{0, 0, 0, 0};
-  // operands: lane (li, lk) holds A_t1[a0 + li][b0 + lk] and
-  // B_t2[b0 + lk][c0 + li]
-  const int a = a0 + li, cc = c0 + li;
-  for (int b0 = 0; b0 < chiM; b0 += 4) {
-    const int bb = b0 + lk;
-    T av[3], bv[3];
+  // Chunks of 16 b: lane (li, lk) holds A_t[a0 + li][b0 + 4 lk + q] and
+  // B_t[b0 + 4 lk + q][c0 + li] for q < 4, and MFMA step q takes k-slot lk
+  // = b0 + 4 lk + q (the contraction sums over b, so the order is free).
+  // Out-of-range rows, columns and b are read at a clamped address and
+  // zeroed by a select: no branch around a load, so the next chunk's loads
+  // stay in flight while this chunk is multiplied.
+  const int a = min(a0 + li, chiL - 1), cc = min(c0 + li, chiR - 1);
+  const bool arow = a0 + li < chiL, bcol = c0 + li < chiR;
+  const double *Ar = A + (size_t)a * chiM;
+  const double *Bc = Bt + cc;
+  const size_t As = (size_t)chiL * chiM, Bs = (size_t)chiM * chiR;
+  auto load = [&](int b0, T (&av)[3][4], T (&bv)[3][4]) {
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      av[t] = (a < chiL && bb < chiM)
-                  ? (T)A[(size_t)t * chiL * chiM + (size_t)a * chiM + bb]
-                  : (T)0;
-      bv[t] = (bb < chiM && cc < chiR)
-                  ? (T)Bt[(size_t)t * chiM * chiR + (size_t)bb * chiR + cc]
-                  : (T)0;
+    for (int q = 0; q < 4; ++q) {
+      const int bb = b0 + 4 * lk + q;
+      const int bcl = min(bb, chiM - 1);
+      const bool ok = bb < chiM;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const double x = Ar[t * As + bcl];
+        const double y = Bc[t * Bs + (size_t)bcl * chiR];
+        av[t][q] = (arow && ok) ? (T)x : (T)0;
+        bv[t][q] = (bcol && ok) ? (T)y : (T)0;
+      }
     }
+  };
+  auto mult = [&](const T (&av)[3][4], const T (&bv)[3][4]) {
 #pragma unroll
-    for (int t1 = 0; t1 < 3; ++t1)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int t2 = 0; t2 < 3; ++t2)
-        acc[3 * t1 + t2] = M::mma(av[t1], bv[t2], acc[3 * t1 + t2]);
+      for (int t1 = 0; t1 < 3; ++t1)
+#pragma unroll
+        for (int t2 = 0; t2 < 3; ++t2)
+          acc[3 * t1 + t2] = M::mma(av[t1][q], bv[t2][q], acc[3 * t1 + t2]);
+  };
+  T a0v[3][4], b0v[3][4], a1v[3][4], b1v[3][4];
+  load(0, a0v, b0v);
+  for (int b0 = 0; b0 < chiM; b0 += 32) {
+    load(b0 + 16, a1v, b1v);
+    asm volatile("" ::: "memory");  // next chunk's loads go first
+    mult(a0v, b0v);
+    if (b0 + 16 >= chiM) break;
+    load(b0 + 32, a0v, b0v);
+    asm volatile("" ::: "memory");
+    mult(a1v, b1v);
   }
   double *TH = s.TH + (size_t)c * s.th_stride;
   double *X = s.X + (size_t)c * s.th_stride;
