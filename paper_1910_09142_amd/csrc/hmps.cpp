@@ -20,6 +20,7 @@
 
 #include "../../include/hmps.h"
 #include "hmps_internal.h"
+#include "small_path.h"
 
 using namespace hmps;
 
@@ -242,6 +243,11 @@ struct hmps_ctx {
   // their two blocks (16 inner rounds instead of 31): measured on the same
   // ladder, 4% more outer sweeps and 23% less time (one chain).
   int cross_inner = 1;
+  // largest theta' (m * n doubles) whose SVD runs in one workgroup's LDS;
+  // larger ones take the blocked rounds.  The in-LDS kernel runs its pair
+  // products on vector lanes, so beyond a few thousand entries the blocked
+  // MFMA rounds win even at a single chain (at most SMALL_LDS).
+  size_t small_max = 2048;
   bool skip_theta = false;  // hmps_svd_probe: theta' is placed by the host
   // device buffers (carved from the workspace)
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
@@ -428,7 +434,10 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
                       double cutoff) {
   const int L = ctx->plan.len;
   int max_chiL = 1, max_chiR = 1;
-  size_t max_mn = 0;
+  // each chain's SVD runs in LDS when its theta' has at most small_max
+  // entries, else on the blocked rounds; the rounds' grid is sized by the
+  // blocked chains alone
+  int n_small = 0, n_blocked = 0;
   int max_nb = 2, max_vlen = 1, max_nvec = 1;
   double flops = 0.0, svd_flops = 0.0;
   for (int c = 0; c < ctx->B; ++c) {
@@ -443,12 +452,16 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
     }
     max_chiL = std::max(max_chiL, row[k]);
     max_chiR = std::max(max_chiR, row[k + 2]);
-    max_mn = std::max(max_mn, (size_t)(3 * row[k]) * (3 * row[k + 2]));
     // the Jacobi SVD orthogonalises min(m, n) vectors of length max(m, n)
     const int nvec = 3 * std::min(row[k], row[k + 2]);
     max_vlen = std::max(max_vlen, 3 * std::max(row[k], row[k + 2]));
     max_nvec = std::max(max_nvec, nvec);
-    max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
+    if ((size_t)(3 * row[k]) * (3 * row[k + 2]) <= ctx->small_max) {
+      ++n_small;
+    } else {
+      ++n_blocked;
+      max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
+    }
   }
   const bool is_move = (op == OP_IDENT);
   UpdParams u;
@@ -474,10 +487,11 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
     launch_theta(b, s, u, max_chiL, max_chiR, st);
     LAUNCHCHK(ctx);
   }
-  if (max_mn <= (size_t)SMALL_LDS) {
-    launch_jacobi_small(b, s, u, st);
+  if (n_small > 0) {
+    launch_jacobi_small_upto(b, s, u, ctx->small_max, st);
     LAUNCHCHK(ctx);
-  } else {
+  }
+  if (n_blocked > 0) {
     launch_pad(b, s, u, st);
     bool converged = false;
     // Sweep s is enqueued before the host waits for the rotation count of
@@ -485,6 +499,8 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
     // after convergence finds every chain done and exits at once.
     auto enqueue_sweep = [&](int sweep) -> hmps_status {
       launch_jacobi_sweep_begin(s, ctx->B, sweep, st);
+      if (sweep == 0 && n_small > 0)
+        launch_mark_small_done(b, s, u, ctx->small_max, st);
       for (int r = 0; r < max_nb - 1; ++r)
         launch_jacobi_round(b, s, u, r, max_nb / 2, st);
       ctx->stats.jacobi_sweeps += 1;
@@ -505,7 +521,9 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       const int nvec = 3 * std::min(row[k], row[k + 2]);
       const int len = 3 * std::max(row[k], row[k + 2]);
       const int nb = n_blocks_even(nvec, JB);
-      round_bytes[c] = (double)(nb - 1) * nb * JB * vector_stride(len) * 8.0;
+      const bool small = (size_t)(3 * row[k]) * (3 * row[k + 2]) <= ctx->small_max;
+      round_bytes[c] =
+          small ? 0.0 : (double)(nb - 1) * nb * JB * vector_stride(len) * 8.0;
     }
     HIPCHK(hipEventRecord(ctx->svd_ev[0], st));
     hmps_status est = enqueue_sweep(0);
@@ -641,6 +659,8 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
   if (const char *e = std::getenv("HMPS_INNER")) ctx->inner_sweeps = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("HMPS_SKIP")) ctx->skip = std::min(1e-26, std::atof(e));
   if (const char *e = std::getenv("HMPS_CROSS")) ctx->cross_inner = e[0] == '1';
+  if (const char *e = std::getenv("HMPS_SMALL_MAX"))
+    ctx->small_max = std::min<size_t>(SMALL_LDS, std::strtoull(e, nullptr, 10));
   int current = -1;
   hipError_t e = hipGetDevice(&current);
   if (e != hipSuccess || current != opt->device) {

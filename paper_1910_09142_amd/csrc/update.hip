@@ -18,6 +18,7 @@
 // length could never all become orthogonal.  X and TH hold the L x N
 // vector matrix column-major (vector j at offset j*L).
 #include "device_common.h"
+#include "small_path.h"
 
 namespace hmps {
 namespace {
@@ -25,7 +26,7 @@ using namespace dev;
 
 struct Dims {
   int chiL, chiM, chiR, m, n, L, N, trans;
-  int ld;  // vector stride in X and TH: L rounded up to a multiple of 4
+  int ld;  // vector stride in X and TH: L rounded up to a multiple of 16
 };
 
 __device__ __forceinline__ Dims dims_of(const Batch &b, int c, int k) {
@@ -192,10 +193,11 @@ __global__ void __launch_bounds__(NT) k_pad(Batch b, UpdScratch s, UpdParams u) 
 // the squared vector norms are written to sig2.
 // =====================================================================
 __global__ void __launch_bounds__(NT)
-    k_jacobi_small(Batch b, UpdScratch s, UpdParams u) {
+    k_jacobi_small(Batch b, UpdScratch s, UpdParams u, size_t small_max) {
   const int c = blockIdx.x;
   const Dims d = dims_of(b, c, u.k);
   const int L = d.L, N = d.N;
+  if ((size_t)L * N > small_max) return;  // this chain takes the blocked path
   double *X = s.X + (size_t)c * s.th_stride;
   __shared__ double xs[SMALL_LDS];
   __shared__ int flag;
@@ -262,6 +264,15 @@ __global__ void __launch_bounds__(NT)
     if (!converged) s.err[c] = 1;
     s.sweeps[c] += converged ? sweep + 1 : sweep;
   }
+}
+
+// Chains whose SVD runs in LDS take no part in the blocked rounds.
+__global__ void k_mark_small_done(Batch b, UpdScratch s, UpdParams u,
+                                  size_t small_max) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= b.B) return;
+  const Dims d = dims_of(b, c, u.k);
+  if ((size_t)d.L * d.N <= small_max) s.done[c] = 1;
 }
 
 // =====================================================================
@@ -465,7 +476,21 @@ void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,
 
 void launch_jacobi_small(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_small, dim3(b.B), dim3(NT), 0, st, b, s, u);
+  launch_jacobi_small_upto(b, s, u, SMALL_LDS, st);
+}
+
+void launch_jacobi_small_upto(const Batch &b, const UpdScratch &s,
+                              const UpdParams &u, size_t small_max,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_small, dim3(b.B), dim3(NT), 0, st, b, s, u,
+                     small_max);
+}
+
+void launch_mark_small_done(const Batch &b, const UpdScratch &s,
+                            const UpdParams &u, size_t small_max,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_mark_small_done, dim3((b.B + NT - 1) / NT), dim3(NT),
+                     0, st, b, s, u, small_max);
 }
 
 void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
