@@ -12,6 +12,12 @@ FP64 (one chain); inputs are synthetic (Philox product states).
 Prints one JSON line.  `value` counts the two-site Trotter updates (gates
 and swaps; orthogonality-centre moves excluded) per second of the timed
 region, all chains together.
+
+`--workload m1` measures single gate applications at chi = 256 instead:
+every chain holds one bond with chi_l = chi_m = chi_r = 256 (synthetic
+Haar factors, Schmidt values exp(-j/24)); one step applies exp(-(tau/2) J
+S.S) with tau = 0.05, J = 1 to every chain, with the truncated SVD back to
+chi_max = 256 at cutoff 1e-10, sweeping the bond back and forth.
 """
 from __future__ import annotations
 
@@ -34,10 +40,12 @@ FP64_PEAK_TFLOPS = 78.6
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 1 sample; m1: 20 gates)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps (default 0; m1: 2)")
     ap.add_argument("--workload", default="c3",
-                    choices=["c1", "c2", "c3", "c4", "c5"])
+                    choices=["c1", "c2", "c3", "c4", "c5", "m1"])
     ap.add_argument("--chains", type=int, default=None,
                     help="override the number of chains of the workload")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
@@ -45,7 +53,13 @@ def parse():
                     "matrix cores, FP64 SVD, truncation and observables")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle baseline (0 disables it)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    bond = args.workload == "m1"
+    if args.steps is None:
+        args.steps = 20 if bond else 1
+    if args.warmup is None:
+        args.warmup = 2 if bond else 0
+    return args
 
 
 # Sources that make up the round kernel; a traffic figure measured with
@@ -118,12 +132,7 @@ def cpu_baseline(wl, seconds):
     """The FP64 oracle on the same workload: chain 0, seed 0, sample 0,
     Trotter updates in order until the time budget is spent."""
     from oracle import model, mps
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()]
-                      or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    threads = oracle_threads()
     lat = model.ladder(wl.L, wl.J_leg, wl.J_rung, W=wl.W)
     lay = model.layout(lat)
     sch = model.schedule(lat, lay)
@@ -155,6 +164,115 @@ def cpu_baseline(wl, seconds):
                        "bound for the oracle")}
 
 
+def svd_roofline(wl, s0, s1, use_traffic):
+    """Roofline object of the round kernel over the timed region."""
+    launches = s1.round_launches - s0.round_launches
+    svd_s = s1.svd_seconds - s0.svd_seconds
+    svd_f = s1.svd_flops - s0.svd_flops
+    svd_b = s1.svd_bytes - s0.svd_bytes
+    achieved = (svd_f / svd_s / 1e12) if svd_s > 0 else 0.0
+    return {
+        "bound": "mfma", "achieved": achieved,
+        "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "frac": achieved / FP64_PEAK_TFLOPS,
+        "traffic": measured_traffic(wl) if use_traffic else None,
+        "kernel": "k_jacobi_round",
+        "launches": launches,
+        "avg_launch_us": 1e6 * svd_s / launches if launches else None,
+        "flops_per_launch": svd_f / launches if launches else None,
+        "algo_bytes_per_launch": svd_b / launches if launches else None,
+        "algo_hbm_GBps": svd_b / svd_s / 1e9 if svd_s > 0 else None,
+        "hbm_peak_GBps": 8000.0,
+    }
+
+
+def oracle_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()]
+                       or [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_bond(wl, center, right, seconds):
+    """The FP64 oracle's two-site update on chain 0's bond, repeated with
+    the centre sweeping back and forth until the time budget is spent."""
+    import numpy as np
+    from oracle import model, mps
+    tensors = [np.ascontiguousarray(T.transpose(1, 0, 2))   # [a, s, b]
+               for T in (center[0], right[0])]
+    psi = mps.MPS(tensors, 0)
+    g = model.gate(wl.J, wl.x)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        mps.apply_update(psi, 0, g, True, n % 2 == 0, wl.chi_max, wl.cutoff)
+        n += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": UNIT, "cores": oracle_threads(),
+            "kind": "oracle",
+            "sample": (f"{n} gate applications on chain 0's bond (chi "
+                       f"{wl.chi} x {wl.chi} x {wl.chi}, the same input) in "
+                       f"{dt:.1f} s")}
+
+
+def main_bond(args):
+    """Single gate applications at chi = 256 (the m1 workload)."""
+    import torch
+    from paper_1910_09142_amd import hmps, workloads
+    wl = workloads.M1
+    B = args.chains or 1
+    chi = wl.chi
+    center, right = workloads.bond_tensors(wl.seed, B, chi, chi, chi,
+                                           wl.decay)
+    precision = (hmps.PREC_MIXED_FP32 if args.precision == "mixed"
+                 else hmps.PREC_FP64)
+    ctx = hmps.Context(B, 2, chi, 1, precision=precision)
+    ctx.hmps_load_bond(center, right)
+    for i in range(args.warmup):
+        ctx.hmps_apply_gate(wl.J, wl.x, wl.chi_max, wl.cutoff)
+    print(f"warmup done ({args.warmup} gate applications)", file=sys.stderr,
+          flush=True)
+    s0 = ctx.hmps_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.hmps_apply_gate(wl.J, wl.x, wl.chi_max, wl.cutoff)
+        if (i + 1) % 10 == 0:
+            print(f"gate application {i + 1}/{args.steps} "
+                  f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+                  flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s1 = ctx.hmps_stats()
+    chi_now = ctx.hmps_bond_dims()[:, 1]
+    ctx.hmps_destroy()
+    gates = s1.gate_updates - s0.gate_updates
+    out = {
+        "metric": METRIC, "value": gates / elapsed, "unit": UNIT,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic (Philox-seeded Haar bond tensors)",
+        "config": {"workload": wl.name, "n_chains": B, "chi_l": chi,
+                   "chi_m": chi, "chi_r": chi, "J": wl.J, "x": wl.x,
+                   "chi_max": wl.chi_max, "cutoff": wl.cutoff,
+                   "schmidt_decay": wl.decay, "precision": args.precision},
+        "bond_dim_after": int(chi_now.min()),
+        "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12,
+        "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
+        "roofline": svd_roofline(wl, s0, s1, args.precision == "fp64"),
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline_bond(wl, center, right,
+                                                args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -164,6 +282,9 @@ def main():
               "this benchmark does not run on more than one GPU",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "m1":
+        main_bond(args)
+        return
     import torch
     from paper_1910_09142_amd import hmps, workloads
 
@@ -220,11 +341,6 @@ def main():
                        - (s1.move_updates - s0.move_updates))
     gates = s1.gate_updates - s0.gate_updates
     value = trotter_updates / elapsed
-    launches = s1.round_launches - s0.round_launches
-    svd_s = s1.svd_seconds - s0.svd_seconds
-    svd_f = s1.svd_flops - s0.svd_flops
-    svd_b = s1.svd_bytes - s0.svd_bytes
-    achieved = (svd_f / svd_s / 1e12) if svd_s > 0 else 0.0
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -242,21 +358,8 @@ def main():
         "max_chi": s1.max_chi,
         "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
         "energy_mean": sum(energies) / len(energies),
-        "roofline": {
-            "bound": "mfma", "achieved": achieved,
-            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": (measured_traffic(wl)
-                        if args.precision == "fp64" and B == wl.n_chains
-                        else None),
-            "kernel": "k_jacobi_round",
-            "launches": launches,
-            "avg_launch_us": 1e6 * svd_s / launches if launches else None,
-            "flops_per_launch": svd_f / launches if launches else None,
-            "algo_bytes_per_launch": svd_b / launches if launches else None,
-            "algo_hbm_GBps": svd_b / svd_s / 1e9 if svd_s > 0 else None,
-            "hbm_peak_GBps": 8000.0,
-        },
+        "roofline": svd_roofline(
+            wl, s0, s1, args.precision == "fp64" and B == wl.n_chains),
     }
     ctx.hmps_destroy()
     if args.cpu_seconds > 0:

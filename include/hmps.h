@@ -176,8 +176,49 @@ hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
 hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out);
 
 /* Bond dimensions chi[c][b], b = 0..n_sites, of every chain (host array
- * of n_chains * (n_sites + 1) int32).  Synchronises. */
+ * of n_chains * (n_sites + 1) int32), after hmps_init_cluster_env or
+ * hmps_load_bond.  Synchronises. */
 hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi);
+
+/* Site tensor `site` of chain `chain` (host array out of 3 * chi[site] *
+ * chi[site + 1] doubles, layout T[s][a][b], s the S^z index m = +1, 0, -1,
+ * a the left and b the right bond; bond dimensions from hmps_bond_dims),
+ * after hmps_init_cluster_env or hmps_load_bond.  E_INVALID for an index
+ * out of range.  Synchronises. */
+hmps_status hmps_read_site(hmps_ctx *ctx, int32_t chain, int32_t site,
+                           double *out);
+
+/* One bond of an MPS as the workload of a single gate application (Ancilla
+ * Method subsection: a two-site gate contracts the two site tensors with
+ * the bond weights, and an SVD truncated by discarded weight restores the
+ * MPS form).  Every one of n_chains chains becomes an open two-site
+ * segment: site 0 is the orthogonality centre C with outer bond chi_l,
+ * site 1 a right-orthonormal tensor B with outer bond chi_r, and chi_m the
+ * bond between them.  center: host, n_chains blocks of 3 * chi_l * chi_m
+ * doubles, C[s][a][b]; right: host, n_chains blocks of 3 * chi_m * chi_r
+ * doubles, B[s][b][c] (layout of hmps_read_site).  Bond dimensions in
+ * [1, chi_cap], n_chains in [1, max_chains], max_sites >= 2, finite
+ * entries, else E_INVALID.  The context's chains are replaced
+ * (hmps_init_cluster_env must be called again before evolve); log-weights
+ * and counters restart at 0.  Synchronises. */
+hmps_status hmps_load_bond(hmps_ctx *ctx, int32_t n_chains, int32_t chi_l,
+                           int32_t chi_m, int32_t chi_r, const double *center,
+                           const double *right);
+
+/* One application of exp(-x J S_0.S_1) to the loaded bond of every chain,
+ * the update that hmps_evolve runs for each Trotter gate (Ancilla Method
+ * subsection; Results section for chi_max and the cutoff): theta =
+ * T_0 T_1, theta' = G theta in the context's precision, log ||theta'||^2
+ * added to the chain's log-weight, theta' normalised and split by the
+ * truncated SVD.  With the centre on site 0 the singular values go to
+ * site 1 (the centre moves right), otherwise to site 0, so repeated calls
+ * sweep the bond back and forth.  logw (host, may be NULL): n_chains
+ * accumulated log-weights.  Needs hmps_load_bond (E_STATE otherwise);
+ * E_INVALID for non-finite J or x, chi_max outside [1, chi_cap] or a
+ * negative or non-finite cutoff; E_NUMERIC if the SVD fails.
+ * Synchronises. */
+hmps_status hmps_apply_gate(hmps_ctx *ctx, double J, double x,
+                            int32_t chi_max, double cutoff, double *logw);
 
 /* Correlators <S_i.S_j> of the current sample of every chain for
  * arbitrary physical-site pairs (Results section: the susceptibility is

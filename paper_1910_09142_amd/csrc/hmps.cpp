@@ -225,7 +225,8 @@ struct hmps_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool poisoned = false;
-  bool ready = false;
+  bool ready = false;        // chains from hmps_init_cluster_env
+  bool bond_loaded = false;  // chains from hmps_load_bond
   Plan plan;
   int B = 0;
   uint64_t seed = 0;
@@ -741,6 +742,7 @@ hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
   ctx->sample = 0;
   ctx->center = 0;
   ctx->ready = false;
+  ctx->bond_loaded = false;
   std::memset(&ctx->stats, 0, sizeof(ctx->stats));
   hipStream_t s = ctx->stream;
   std::vector<int32_t> bp(P.bond_p), bq(P.bond_q);
@@ -935,8 +937,9 @@ hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
 
 hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out) {
   if (!ctx || !out) return HMPS_E_INVALID;
+  DeviceGuard guard(ctx->opt.device);
   hmps_stats_t s = ctx->stats;
-  if (ctx->ready && !ctx->poisoned) {
+  if ((ctx->ready || ctx->bond_loaded) && !ctx->poisoned) {
     std::vector<double> disc(ctx->B);
     std::vector<int32_t> sw(ctx->B);
     if (hipMemcpy(disc.data(), ctx->d_disc, sizeof(double) * ctx->B,
@@ -1100,6 +1103,7 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
   ctx->plan = P;
   ctx->B = 1;
   ctx->ready = false;
+  ctx->bond_loaded = false;
   ctx->center = 0;
   ctx->h_chi = {chi_l, 1, chi_r};
   hipStream_t s = ctx->stream;
@@ -1139,10 +1143,126 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
   return HMPS_OK;
 }
 
-hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi) {
-  hmps_status st = check_usable(ctx, true);
+hmps_status hmps_load_bond(hmps_ctx *ctx, int32_t n_chains, int32_t chi_l,
+                           int32_t chi_m, int32_t chi_r, const double *center,
+                           const double *right) {
+  hmps_status st = check_usable(ctx, false);
   if (st) return st;
   DeviceGuard guard(ctx->opt.device);
+  if (!center || !right)
+    return fail(ctx, HMPS_E_INVALID, "center and right must not be NULL");
+  if (n_chains < 1 || n_chains > ctx->opt.max_chains)
+    return fail(ctx, HMPS_E_INVALID, "n_chains outside [1, max_chains]");
+  const int cap = ctx->opt.chi_cap;
+  if (chi_l < 1 || chi_m < 1 || chi_r < 1 || chi_l > cap || chi_m > cap ||
+      chi_r > cap)
+    return fail(ctx, HMPS_E_INVALID, "bond dimensions outside [1, chi_cap]");
+  if (ctx->opt.max_sites < 2)
+    return fail(ctx, HMPS_E_INVALID, "the context needs max_sites >= 2");
+  const size_t nc = (size_t)3 * chi_l * chi_m, nr = (size_t)3 * chi_m * chi_r;
+  for (size_t i = 0; i < nc * n_chains; ++i)
+    if (!std::isfinite(center[i]))
+      return fail(ctx, HMPS_E_INVALID, "center has a non-finite entry");
+  for (size_t i = 0; i < nr * n_chains; ++i)
+    if (!std::isfinite(right[i]))
+      return fail(ctx, HMPS_E_INVALID, "right has a non-finite entry");
+  // every chain becomes an open two-site segment (0, 1) with outer bonds
+  // chi_l and chi_r, the centre on site 0
+  Plan P;
+  P.len = 2;
+  ctx->plan = P;
+  ctx->B = n_chains;
+  ctx->ready = false;
+  ctx->bond_loaded = false;
+  ctx->center = 0;
+  std::memset(&ctx->stats, 0, sizeof(ctx->stats));
+  ctx->h_chi.resize((size_t)3 * n_chains);
+  for (int c = 0; c < n_chains; ++c) {
+    ctx->h_chi[3 * c] = chi_l;
+    ctx->h_chi[3 * c + 1] = chi_m;
+    ctx->h_chi[3 * c + 2] = chi_r;
+  }
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipMemcpyAsync(ctx->d_chi, ctx->h_chi.data(),
+                        sizeof(int32_t) * 3 * n_chains, hipMemcpyHostToDevice,
+                        s));
+  for (int c = 0; c < n_chains; ++c) {
+    double *site0 = ctx->d_sites + (size_t)2 * c * ctx->site_cap;
+    HIPCHK(hipMemcpyAsync(site0, center + nc * c, sizeof(double) * nc,
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(site0 + ctx->site_cap, right + nr * c,
+                          sizeof(double) * nr, hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipMemsetAsync(ctx->d_err, 0, sizeof(int32_t) * n_chains, s));
+  HIPCHK(hipMemsetAsync(ctx->d_disc, 0, sizeof(double) * n_chains, s));
+  HIPCHK(hipMemsetAsync(ctx->d_logw, 0, sizeof(double) * n_chains, s));
+  HIPCHK(hipMemsetAsync(ctx->d_sweeps, 0, sizeof(int32_t) * n_chains, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->stats.n_chains = n_chains;
+  ctx->stats.n_sites = 2;
+  ctx->bond_loaded = true;
+  return HMPS_OK;
+}
+
+hmps_status hmps_apply_gate(hmps_ctx *ctx, double J, double x,
+                            int32_t chi_max, double cutoff, double *logw) {
+  hmps_status st = check_usable(ctx, false);
+  if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
+  if (!ctx->bond_loaded)
+    return fail(ctx, HMPS_E_STATE, "hmps_load_bond has not been called");
+  if (!std::isfinite(J) || !std::isfinite(x))
+    return fail(ctx, HMPS_E_INVALID, "J and x must be finite");
+  if (chi_max < 1 || chi_max > ctx->opt.chi_cap)
+    return fail(ctx, HMPS_E_INVALID, "chi_max outside [1, chi_cap]");
+  if (!(cutoff >= 0.0) || !std::isfinite(cutoff))
+    return fail(ctx, HMPS_E_INVALID, "cutoff must be finite and >= 0");
+  // the gate takes coupling slot 0; do_update synchronises the stream
+  // before g goes out of scope
+  double g[81];
+  gate9(J, x, g);
+  ctx->plan.couplings.assign(1, J);
+  HIPCHK(hipMemcpyAsync(ctx->d_gates, g, sizeof(g), hipMemcpyHostToDevice,
+                        ctx->stream));
+  const bool right = ctx->center == 0;
+  st = do_update(ctx, 0, 0, right, chi_max, cutoff);
+  if (st) return st;
+  ctx->center = right ? 1 : 0;
+  if (logw) {
+    HIPCHK(hipMemcpyAsync(logw, ctx->d_logw, sizeof(double) * ctx->B,
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  return HMPS_OK;
+}
+
+hmps_status hmps_read_site(hmps_ctx *ctx, int32_t chain, int32_t site,
+                           double *out) {
+  hmps_status st = check_usable(ctx, false);
+  if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
+  if (!ctx->ready && !ctx->bond_loaded)
+    return fail(ctx, HMPS_E_STATE, "the context holds no chains");
+  if (!out) return fail(ctx, HMPS_E_INVALID, "out is NULL");
+  const int L = ctx->plan.len;
+  if (chain < 0 || chain >= ctx->B || site < 0 || site >= L)
+    return fail(ctx, HMPS_E_INVALID, "chain or site out of range");
+  const int *row = &ctx->h_chi[(size_t)chain * (L + 1)];
+  const size_t n = (size_t)3 * row[site] * row[site + 1];
+  const double *src =
+      ctx->d_sites + ((size_t)chain * L + site) * ctx->site_cap;
+  HIPCHK(hipMemcpyAsync(out, src, sizeof(double) * n, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HMPS_OK;
+}
+
+hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi) {
+  hmps_status st = check_usable(ctx, false);
+  if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
+  if (!ctx->ready && !ctx->bond_loaded)
+    return fail(ctx, HMPS_E_STATE, "hmps_init_cluster_env has not been called");
   if (!chi) return fail(ctx, HMPS_E_INVALID, "chi is NULL");
   HIPCHK(hipMemcpyAsync(chi, ctx->d_chi,
                         sizeof(int32_t) * ctx->B * (ctx->plan.len + 1),

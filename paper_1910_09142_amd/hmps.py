@@ -29,7 +29,8 @@ EXPORTS = [
     "hmps_evolve", "hmps_measure", "hmps_collapse_resample", "hmps_stats",
     "hmps_bond_dims", "hmps_destroy", "hmps_last_error", "hmps_gate",
     "hmps_schedule", "hmps_svd_probe", "hmps_measure_pairs",
-    "hmps_susceptibility",
+    "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
+    "hmps_apply_gate",
 ]
 
 
@@ -101,6 +102,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                    P(C.c_double), C.c_int32, C.c_double,
                                    P(C.c_double), P(C.c_int32),
                                    P(C.c_double), P(C.c_double)]
+    lib.hmps_read_site.argtypes = [C.c_void_p, C.c_int32, C.c_int32,
+                                   P(C.c_double)]
+    lib.hmps_load_bond.argtypes = [C.c_void_p] + [C.c_int32] * 4 + [
+        P(C.c_double), P(C.c_double)]
+    lib.hmps_apply_gate.argtypes = [C.c_void_p, C.c_double, C.c_double,
+                                    C.c_int32, C.c_double, P(C.c_double)]
     lib.hmps_destroy.argtypes = [C.c_void_p]
     lib.hmps_destroy.restype = None
     lib.hmps_last_error.argtypes = [C.c_void_p]
@@ -113,7 +120,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "hmps_measure", "hmps_collapse_resample", "hmps_stats",
                  "hmps_bond_dims", "hmps_gate", "hmps_schedule",
                  "hmps_svd_probe", "hmps_measure_pairs",
-                 "hmps_susceptibility"):
+                 "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
+                 "hmps_apply_gate"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -314,6 +322,44 @@ class Context:
         self.n_chains, self.n_sites = 1, 2
         return (sigma[:k].copy(), left[:3 * chi_l * k].reshape(3, chi_l, k),
                 right[:3 * k * chi_r].reshape(3, k, chi_r))
+
+    def hmps_read_site(self, chain, site):
+        """Site tensor T[s, a, b] of one chain."""
+        chi = self.hmps_bond_dims()[chain]
+        out = np.zeros((3, int(chi[site]), int(chi[site + 1])), np.float64)
+        self._check(self.lib.hmps_read_site(self.h, int(chain), int(site),
+                                            _ptr(out, C.c_double)),
+                    "hmps_read_site")
+        return out
+
+    def hmps_load_bond(self, center, right):
+        """Replaces the chains by two-site segments: center [B, 3, chi_l,
+        chi_m] (orthogonality centre) and right [B, 3, chi_m, chi_r]
+        (right-orthonormal), layout T[s, a, b]."""
+        center = np.ascontiguousarray(center, np.float64)
+        right = np.ascontiguousarray(right, np.float64)
+        if center.ndim != 4 or right.ndim != 4 or center.shape[1] != 3 or \
+                right.shape[1] != 3 or center.shape[0] != right.shape[0] or \
+                center.shape[3] != right.shape[2]:
+            raise ValueError("center [B, 3, chi_l, chi_m] and right "
+                             "[B, 3, chi_m, chi_r] expected")
+        B, _, chi_l, chi_m = center.shape
+        chi_r = right.shape[3]
+        self._check(self.lib.hmps_load_bond(
+            self.h, B, chi_l, chi_m, chi_r, _ptr(center, C.c_double),
+            _ptr(right, C.c_double)), "hmps_load_bond")
+        self.n_chains, self.n_sites = B, 2
+        self.n_env = self.n_bonds = 0
+
+    def hmps_apply_gate(self, J, x, chi_max, cutoff, want_logw=False):
+        """One application of exp(-x J S.S) with its truncated SVD on the
+        loaded bond of every chain; returns the log-weights if asked."""
+        logw = np.zeros(self.n_chains, np.float64) if want_logw else None
+        self._check(self.lib.hmps_apply_gate(
+            self.h, float(J), float(x), int(chi_max), float(cutoff),
+            _ptr(logw, C.c_double) if want_logw else None),
+            "hmps_apply_gate")
+        return logw
 
     def hmps_destroy(self):
         if getattr(self, "h", None):

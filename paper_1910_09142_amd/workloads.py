@@ -73,3 +73,57 @@ def central_sites(L: int, ncols: int = 6):
 
 def mps_length(L: int, W: int) -> int:
     return 2 * L + 2 * W
+
+
+# Single-gate workload: every update at chi_l = chi_m = chi_r = 256, the
+# gate exp(-(tau/2) J S.S) with J = 1, tau = 0.05, chi_max 256, cutoff
+# 1e-10 (the chi = 256 ladder's half-step gate and truncation).
+@dataclass(frozen=True)
+class BondWorkload:
+    name: str
+    chi: int
+    J: float
+    x: float
+    chi_max: int
+    cutoff: float
+    decay: float
+    seed: int = 0
+
+
+M1 = BondWorkload("bond_chi256_gate_J1_x0.025", 256, 1.0, 0.025, 256, 1e-10,
+                  24.0)
+
+
+def _haar_columns(rng, rows: int, cols: int):
+    """rows x cols matrix with orthonormal columns, Haar distributed (QR of
+    a Gaussian matrix, signs fixed by the diagonal of R)."""
+    import numpy as np
+    q, r = np.linalg.qr(rng.standard_normal((rows, cols)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def bond_tensors(seed: int, n_chains: int, chi_l: int, chi_m: int,
+                 chi_r: int, decay: float = 24.0):
+    """Synthetic bond of an MPS for each chain, in the layout T[s, a, b] of
+    the C ABI: the centre C (3, chi_l, chi_m) with Schmidt values
+    sigma_j proportional to exp(-j / decay) on its right bond (C = Q1
+    diag(sigma) Q2 as a (chi_l*3) x chi_m matrix, Q1 and Q2 Haar), and a
+    right-orthonormal B (3, chi_m, chi_r) (rows of a Haar isometry).
+    Needs 3 chi_l >= chi_m and 3 chi_r >= chi_m.  numpy Generator on
+    Philox(seed)."""
+    import numpy as np
+    if 3 * chi_l < chi_m or 3 * chi_r < chi_m:
+        raise ValueError("3 chi_l >= chi_m and 3 chi_r >= chi_m needed")
+    rng = np.random.Generator(np.random.Philox(seed))
+    sigma = np.exp(-np.arange(chi_m) / decay)
+    sigma /= np.sqrt(np.sum(sigma * sigma))
+    center = np.empty((n_chains, 3, chi_l, chi_m))
+    right = np.empty((n_chains, 3, chi_m, chi_r))
+    for c in range(n_chains):
+        q1 = _haar_columns(rng, 3 * chi_l, chi_m)
+        q2 = _haar_columns(rng, chi_m, chi_m)
+        cm = (q1 * sigma[None, :]) @ q2.T            # rows (a, s)
+        center[c] = cm.reshape(chi_l, 3, chi_m).transpose(1, 0, 2)
+        bm = _haar_columns(rng, 3 * chi_r, chi_m).T  # columns (s, c)
+        right[c] = bm.reshape(chi_m, 3, chi_r).transpose(1, 0, 2)
+    return center, right

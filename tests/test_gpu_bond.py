@@ -1,0 +1,175 @@
+"""One gate application on a loaded bond (hmps_load_bond, hmps_apply_gate,
+hmps_read_site) against the oracle's two-site update on the same tensors.
+
+The update is the one every Trotter gate runs (Ancilla Method subsection):
+theta = T_0 T_1, theta' = G theta, log ||theta'||^2 into the log-weight,
+theta' normalised, truncated SVD (Results section: chi_max and the cutoff).
+Inputs: the synthetic bond of the chi = 256 gate workload (Haar factors,
+Schmidt values exp(-j/24)) at several sizes, so that theta' takes the
+in-LDS SVD (m n <= 2048) and the blocked rounds (several 16-vector blocks
+and a ragged tail).
+
+Compared (gauge-invariant, FP64): bond dimensions exactly; the two-site
+state T_0 T_1 after each application to 1e-10 relative (Frobenius), the
+log-weights to 1e-12 absolute; the factor left of the centre
+left-orthonormal, the one right of it right-orthonormal.  One of the two
+factors is the normalised Jacobi vectors, the other the projections
+theta'^T u_j / sigma_j, whose orthonormality error grows like
+eps sqrt(len) sigma_0 / sigma_k (len = max(m, n)); the bound is
+max(1e-12, 2 eps sqrt(len) sigma_0 / sigma_k) over the kept spectrum.
+Mixed mode (FP32 theta and gate): the state to 5e-6 relative, log-weights
+to 1e-6.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import model, mps
+from paper_1910_09142_amd import hmps, workloads
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def to_oracle(T):
+    """[s, a, b] (C ABI) -> [a, s, b] (oracle)."""
+    return np.ascontiguousarray(T.transpose(1, 0, 2))
+
+
+def state(T0, T1):
+    """Two-site state as a (3 chi_l) x (3 chi_r) matrix, rows (a, s)."""
+    l, r = T0.shape[1], T1.shape[2]
+    return np.einsum("sab,tbc->astc", T0, T1).reshape(3 * l, 3 * r)
+
+
+def oracle_state(psi):
+    A, B = psi.tensors
+    return np.einsum("asb,btc->astc", A, B).reshape(A.shape[0] * 3, -1)
+
+
+def run_case(chi_l, chi_m, chi_r, n_chains, chi_max, cutoff, n_apply,
+             precision=hmps.PREC_FP64, J=1.0, x=0.025, seed=3,
+             tol_state=1e-10, tol_logw=1e-12):
+    print(f"case: bond {chi_l}x{chi_m}x{chi_r}, {n_chains} chains, "
+          f"chi_max {chi_max}, precision {precision}", flush=True)
+    center, right = workloads.bond_tensors(seed, n_chains, chi_l, chi_m,
+                                           chi_r)
+    cap = max(chi_l, chi_m, chi_r, chi_max)
+    ctx = hmps.Context(n_chains, 2, cap, 1, precision=precision)
+    ctx.hmps_load_bond(center, right)
+    psis = [mps.MPS([to_oracle(center[c]), to_oracle(right[c])], 0)
+            for c in range(n_chains)]
+    g = model.gate(J, x)
+    for it in range(n_apply):
+        go_right = it % 2 == 0
+        logw = ctx.hmps_apply_gate(J, x, chi_max, cutoff, want_logw=True)
+        chi = ctx.hmps_bond_dims()
+        for c in range(n_chains):
+            S = mps.apply_update(psis[c], 0, g, True, go_right, chi_max,
+                                 cutoff)
+            A, B = psis[c].tensors
+            assert chi[c].tolist() == [chi_l, A.shape[2], chi_r], (it, c)
+            T0 = ctx.hmps_read_site(c, 0)
+            T1 = ctx.hmps_read_site(c, 1)
+            want = oracle_state(psis[c])
+            got = state(T0, T1)
+            err = np.linalg.norm(got - want) / np.linalg.norm(want)
+            assert err < tol_state, (it, c, err)
+            assert abs(logw[c] - psis[c].logw) < tol_logw, (it, c)
+            k = T0.shape[2]
+            if go_right:   # T0 left-orthonormal: rows (a, s)
+                U = T0.transpose(1, 0, 2).reshape(-1, k)
+                iso = U.T @ U
+            else:          # T1 right-orthonormal: columns (s, c)
+                V = T1.transpose(1, 0, 2).reshape(k, -1)
+                iso = V @ V.T
+            length = 3 * max(chi_l, chi_r)
+            tol_iso = max(1e-12, 2 * EPS * np.sqrt(length) * S[0] / S[-1])
+            assert np.abs(iso - np.eye(k)).max() < tol_iso, (it, c)
+    ctx.hmps_destroy()
+
+
+def test_in_lds_path_three_applications():
+    # theta' 24 x 27 = 648 entries: the single-workgroup SVD
+    run_case(8, 10, 9, 2, 16, 1e-10, 3)
+
+
+def test_blocked_path_truncating():
+    # theta' 120 x 120: eight 16-vector blocks with a ragged tail, chi_max
+    # binds (40 -> 32)
+    run_case(40, 40, 40, 3, 32, 1e-10, 3)
+
+
+def test_blocked_path_wide():
+    # more columns than rows: the SVD orthogonalises the 66 rows
+    run_case(22, 50, 60, 2, 50, 1e-12, 2)
+
+
+def test_chi256_gate_workload():
+    wl = workloads.M1
+    run_case(wl.chi, wl.chi, wl.chi, 2, wl.chi_max, wl.cutoff, 2, J=wl.J,
+             x=wl.x)
+
+
+def test_mixed_precision_bond():
+    run_case(64, 64, 64, 2, 64, 1e-10, 2, precision=hmps.PREC_MIXED_FP32,
+             tol_state=5e-6, tol_logw=1e-6)
+
+
+def test_identity_gate_keeps_the_state():
+    # exp(0) = identity: theta' = theta, unit norm, nothing truncated
+    chi = 12
+    center, right = workloads.bond_tensors(5, 1, chi, chi, chi)
+    ctx = hmps.Context(1, 2, chi, 1)
+    ctx.hmps_load_bond(center, right)
+    logw = ctx.hmps_apply_gate(1.0, 0.0, chi, 0.0, want_logw=True)
+    got = state(ctx.hmps_read_site(0, 0), ctx.hmps_read_site(0, 1))
+    want = state(center[0], right[0])
+    ctx.hmps_destroy()
+    assert np.linalg.norm(got - want) < 1e-12 * np.linalg.norm(want)
+    assert abs(logw[0]) < 1e-13
+
+
+def test_batch_is_bit_identical_to_single_chains():
+    chi, n = 40, 3
+    center, right = workloads.bond_tensors(9, n, chi, chi, chi)
+    ctx = hmps.Context(n, 2, chi, 1)
+    ctx.hmps_load_bond(center, right)
+    for _ in range(2):
+        ctx.hmps_apply_gate(1.0, 0.025, 32, 1e-10)
+    batch = [(ctx.hmps_read_site(c, 0), ctx.hmps_read_site(c, 1))
+             for c in range(n)]
+    for c in range(n):
+        ctx.hmps_load_bond(center[c:c + 1], right[c:c + 1])
+        for _ in range(2):
+            ctx.hmps_apply_gate(1.0, 0.025, 32, 1e-10)
+        assert np.array_equal(ctx.hmps_read_site(0, 0), batch[c][0])
+        assert np.array_equal(ctx.hmps_read_site(0, 1), batch[c][1])
+    ctx.hmps_destroy()
+
+
+def test_bond_entry_points_reject_bad_calls():
+    ctx = hmps.Context(2, 2, 8, 1)
+    with pytest.raises(hmps.HmpsError, match="status 4"):
+        ctx.hmps_apply_gate(1.0, 0.1, 8, 0.0)        # nothing loaded
+    center, right = workloads.bond_tensors(0, 1, 4, 12, 4)
+    with pytest.raises(hmps.HmpsError, match="status 1"):
+        ctx.hmps_load_bond(center, right)            # chi_m 12 > chi_cap 8
+    center, right = workloads.bond_tensors(0, 1, 4, 8, 4)
+    bad = center.copy()
+    bad[0, 1, 2, 3] = np.nan
+    with pytest.raises(hmps.HmpsError, match="status 1"):
+        ctx.hmps_load_bond(bad, right)
+    ctx.hmps_load_bond(center, right)
+    with pytest.raises(hmps.HmpsError, match="status 1"):
+        ctx.hmps_apply_gate(1.0, 0.1, 9, 0.0)        # chi_max > chi_cap
+    with pytest.raises(hmps.HmpsError, match="status 1"):
+        ctx.hmps_apply_gate(1.0, 0.1, 8, -1.0)       # negative cutoff
+    out = np.zeros(3 * 4 * 8)
+    ptr = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert ctx.lib.hmps_read_site(ctx.h, 1, 0, ptr) == 1   # one chain only
+    assert ctx.lib.hmps_read_site(ctx.h, 0, 2, ptr) == 1   # two sites only
+    assert ctx.lib.hmps_read_site(ctx.h, 0, 0, None) == 1
+    ctx.hmps_destroy()
