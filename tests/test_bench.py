@@ -46,3 +46,31 @@ def test_prefix_rate_covers_the_oracle_updates():
     assert bench.prefix_rate([], 100.0, 10, 252.0) is None
     assert bench.prefix_rate(marks, 100.0, 10 ** 9, 252.0) is None
     assert bench.model_steps(workloads.C3) == 50
+
+
+def test_step_defaults_follow_the_workload(monkeypatch):
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert (a.workload, a.steps, a.warmup) == ("c3", 1, 0)
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "m1"])
+    a = bench.parse()
+    assert (a.steps, a.warmup) == (20, 2)
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--workload", "m1",
+                                      "--steps", "3", "--warmup", "0"])
+    a = bench.parse()
+    assert (a.steps, a.warmup) == (3, 0)
+
+
+def test_gate_workload_has_no_traffic_figure():
+    # the committed counters cover the ladder workload only
+    assert bench.measured_traffic(workloads.M1) is None
+
+
+def test_oracle_baseline_on_a_small_bond():
+    # the oracle leg of the gate workload on a reduced bond (chi 12)
+    wl = workloads.BondWorkload("bond_chi12", 12, 1.0, 0.025, 12, 1e-10,
+                                24.0)
+    center, right = workloads.bond_tensors(0, 1, 12, 12, 12)
+    cb = bench.cpu_baseline_bond(wl, center, right, 0.05)
+    assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
+    assert "gate applications" in cb["sample"]

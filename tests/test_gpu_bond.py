@@ -11,7 +11,10 @@ and a ragged tail).
 
 Compared (gauge-invariant, FP64): bond dimensions exactly; the two-site
 state T_0 T_1 after each application to 1e-10 relative (Frobenius), the
-log-weights to 1e-12 absolute; the factor left of the centre
+log-weights to 1e-10 absolute, i.e. the weights exp(log w) to 1e-10
+relative (the Jacobi rotations preserve ||theta'||^2 only to rounding per
+rotation: 1.8e-12 after the ~46k rotations per vector of a 1536 x 1536
+theta'); the factor left of the centre
 left-orthonormal, the one right of it right-orthonormal.  One of the two
 factors is the normalised Jacobi vectors, the other the projections
 theta'^T u_j / sigma_j, whose orthonormality error grows like
@@ -51,7 +54,7 @@ def oracle_state(psi):
 
 def run_case(chi_l, chi_m, chi_r, n_chains, chi_max, cutoff, n_apply,
              precision=hmps.PREC_FP64, J=1.0, x=0.025, seed=3,
-             tol_state=1e-10, tol_logw=1e-12):
+             tol_state=1e-10, tol_logw=1e-10):
     print(f"case: bond {chi_l}x{chi_m}x{chi_r}, {n_chains} chains, "
           f"chi_max {chi_max}, precision {precision}", flush=True)
     center, right = workloads.bond_tensors(seed, n_chains, chi_l, chi_m,
@@ -111,6 +114,12 @@ def test_chi256_gate_workload():
     wl = workloads.M1
     run_case(wl.chi, wl.chi, wl.chi, 2, wl.chi_max, wl.cutoff, 2, J=wl.J,
              x=wl.x)
+
+
+def test_chi512_largest_bond():
+    # the largest chi_max of the ladder workloads: theta' 1536 x 1536,
+    # 96 blocks of 16 vectors, theta and write-back at full size
+    run_case(512, 512, 512, 1, 512, 1e-10, 2, seed=11)
 
 
 def test_mixed_precision_bond():
