@@ -344,10 +344,17 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   return cv.off;
 }
 
+// Records the error.  A device or numeric failure poisons the context and
+// drains its stream first: entry points enqueue host-to-device copies from
+// their own local buffers and the caller's arrays, and none of those may
+// still be in flight once the entry point has returned.
 hmps_status fail(hmps_ctx *c, hmps_status st, const std::string &msg) {
   if (c) {
     c->err = msg;
-    if (st == HMPS_E_DEVICE || st == HMPS_E_NUMERIC) c->poisoned = true;
+    if (st == HMPS_E_DEVICE || st == HMPS_E_NUMERIC) {
+      c->poisoned = true;
+      (void)hipStreamSynchronize(c->stream);  // null: the default stream
+    }
   }
   return st;
 }
