@@ -62,7 +62,7 @@ typedef struct {
   void *stream;            /* hipStream_t; NULL = the null stream         */
   void *workspace;         /* device buffer owned by the caller           */
   size_t workspace_bytes;  /* its size; see hmps_workspace_bytes          */
-  int32_t max_chains;      /* largest n_chains accepted by init           */
+  int32_t max_chains;      /* largest n_chains accepted, <= 65535         */
   int32_t max_sites;       /* largest MPS length (physical + ancilla)     */
   int32_t chi_cap;         /* largest chi_max accepted by evolve          */
   int32_t max_bonds;       /* largest number of Hamiltonian bonds         */
@@ -122,9 +122,13 @@ typedef struct {
 size_t hmps_workspace_bytes(int32_t max_chains, int32_t max_sites,
                             int32_t chi_cap, int32_t max_bonds);
 
-/* Create a context on opt->device using the caller's workspace.
- * E_INVALID for bad capacities or a workspace smaller than
- * hmps_workspace_bytes(...); E_DEVICE if the device is unusable. */
+/* Create a context on opt->device using the caller's workspace (device
+ * memory aligned to 256 bytes, at least hmps_workspace_bytes(...) long,
+ * owned by the caller and not freed by the library).  E_INVALID for bad
+ * capacities (max_chains outside [1, 65535]: chains are a grid dimension
+ * of the launches; max_sites < 1; chi_cap outside [3, 640]; max_bonds <
+ * 0; an unknown precision) or a misaligned workspace; E_NOMEM for a NULL
+ * or too small workspace; E_DEVICE if opt->device is not usable. */
 hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt);
 
 /* Step 1 of the Markov chain (Hybrid METTS-Ancilla subsection; Bell pair

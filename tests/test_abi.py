@@ -92,3 +92,11 @@ def test_create_rejects_bad_options_without_gpu():
     assert lib.hmps_create(ctypes.byref(h), ctypes.byref(opt)) == hmps.HMPS_E_INVALID
     opt = hmps.hmps_options(0, None, None, 0, 1, 8, 32, 7, 0, 0, 0.0, None, None)
     assert lib.hmps_create(ctypes.byref(h), ctypes.byref(opt)) == hmps.HMPS_E_NOMEM
+    # chains run along a grid dimension of at most 65535 blocks
+    opt = hmps.hmps_options(0, None, None, 0, 65536, 8, 32, 7, 0, 0, 0.0, None,
+                            None)
+    assert lib.hmps_create(ctypes.byref(h), ctypes.byref(opt)) == hmps.HMPS_E_INVALID
+    opt = hmps.hmps_options(0, None, None, 0, 1, 8, 641, 7, 0, 0, 0.0, None, None)
+    assert lib.hmps_create(ctypes.byref(h), ctypes.byref(opt)) == hmps.HMPS_E_INVALID
+    opt = hmps.hmps_options(0, None, None, 0, 1, 8, 32, 7, 2, 0, 0.0, None, None)
+    assert lib.hmps_create(ctypes.byref(h), ctypes.byref(opt)) == hmps.HMPS_E_INVALID
