@@ -13,9 +13,10 @@ Test infrastructure only (see the package header).
   the thermal average with U = e^{-beta H/2} replaced by its Trotter
   product.
 
-Pins: the ED energies are checked against the closed form of a single bond
-and the high-temperature series; the Trotter product against tau^2
-convergence to ED.
+Pins: the ED energies are checked against the closed form of a single bond,
+the high-temperature series and a second diagonalisation of the 2x3 ladder
+written independently, sector by sector in total S^z; the Trotter product
+against tau^2 convergence to ED.
 """
 from __future__ import annotations
 

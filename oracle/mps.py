@@ -28,9 +28,13 @@ direction, tie rule of the truncation) are stated at each function.
 Parity: evolve + measure are pinned through the exhaustive hybrid sum
 (equal to the dense Trotter average, every cluster size, both bases), the
 single-bond closed form, the ancilla limit and the invariants (norm,
-right-orthonormality, <Q> = M_E, SU(2)); collapse through detailed balance
-by brute force, the beta = 0 transition table and a chi^2 test of sampled
-frequencies; truncation_rank through hand-made spectra.
+right-orthonormality, <Q> = M_E, SU(2)); the untruncated evolution also
+state by state against the update list applied to the full vector;
+apply_update on a single bond through the Schmidt profile of its input,
+gate inversion and the spin-sector closed form of ||G theta||^2; collapse
+through detailed balance by brute force, the beta = 0 transition table and
+a chi^2 test of sampled frequencies; truncation_rank through hand-made
+spectra.
 """
 from __future__ import annotations
 
