@@ -12,3 +12,12 @@ def pytest_configure(config):
     config.addinivalue_line(
         "markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long CPU test")
+
+
+def pytest_sessionstart(session):
+    # A checkout without the built library (it is not versioned) builds it
+    # once; an existing build is used as it is.
+    lib = os.path.join(ROOT, "paper_1910_09142_amd", "libhmps.so")
+    if not os.path.exists(lib):
+        from paper_1910_09142_amd import build
+        build.build(verbose=True)
