@@ -185,6 +185,26 @@ def test_beta_zero_and_chi_one():
     ctx.hmps_destroy()
 
 
+def test_hamiltonian_without_bonds():
+    # H = 0: the evolution is the identity, so the energy is 0, no gate
+    # adds to log w, <Q> is the environment's total S^z and an S^z collapse
+    # returns the labels it started from (sites 0 and 2 sampled, site 1
+    # purified by its ancilla)
+    print("case: no bonds, 3 sites, 2 chains", flush=True)
+    lat = hmps.Lattice(3, [], [0, 1, 2], [0, 1, 0])
+    ctx = hmps.Context(2, 4, 8, 0)
+    env = np.array([[0, 0], [2, 1]], np.uint8)
+    ctx.hmps_init_cluster_env(lat, 2, 5, env_state=env, basis=0)
+    ctx.hmps_evolve(1.0, 0.1, 8, 1e-12)
+    g = ctx.hmps_measure()
+    out = ctx.hmps_collapse_resample(0)
+    ctx.hmps_destroy()
+    assert np.all(g["energy"] == 0.0)
+    assert np.all(g["logw"] == 0.0)
+    assert np.abs(g["qn"] - np.array([2.0, -1.0])).max() < 1e-14
+    assert np.array_equal(out, env)
+
+
 def test_invalid_arguments_on_device():
     ctx, lat = gpu_ctx(3, 1, 32, 2)
     with pytest.raises(hmps.HmpsError):
