@@ -95,11 +95,13 @@ def init_state(lay: model.Layout, env_outcomes: dict, basis: int) -> MPS:
     return MPS(T, 0, 0.0)
 
 
-def initial_outcomes(lay: model.Layout, seed: int, chain: int) -> dict:
-    """Uniform random S^z index per environment site for sample 0."""
+def initial_outcomes(lay: model.Layout, seed: int, chain: int,
+                     sample: int = 0) -> dict:
+    """Uniform random S^z index per environment site for the first sample
+    of a chain (``sample`` = its index, 0 unless the chain is resumed)."""
     out = {}
     for p in lay.env_positions:
-        u = philox.uniform(seed, chain, 0, p, philox.PURPOSE_INIT)
+        u = philox.uniform(seed, chain, sample, p, philox.PURPOSE_INIT)
         out[p] = min(2, int(math.floor(3.0 * u)))
     return out
 
@@ -134,11 +136,19 @@ def truncation_rank(s: np.ndarray, chi_max: int, cutoff: float,
     """Number of singular values kept.
 
     k_eps is the smallest k >= 1 whose discarded tail sum_{j>=k} s_j^2 is at
-    most cutoff * sum_j s_j^2 (relative discarded weight, Results section);
-    k = min(k_eps, chi_max).  Tie rule: if the cut falls inside a run of
-    singular values whose consecutive relative gaps are <= TIE_TOL, the
-    whole run is discarded (the kept subspace is then unique); a run that
-    starts at the largest singular value is kept as cut.
+    most cutoff * sum_j s_j^2: the truncation error is the summed squares of
+    the discarded singular values over the sum of all squares, held at a
+    fixed target (Results section, third source of error).  The bond
+    dimension cap gives k = min(k_eps, chi_max).
+
+    Ties (reading of a point the paper leaves open): a run of singular
+    values whose consecutive relative gaps are <= TIE_TOL has no unique
+    split, so a cut never falls inside one.
+      * The target sets the cut (k_eps <= chi_max): the whole run is kept,
+        so the discarded weight stays within the target; if keeping it
+        would pass chi_max, the cap binds and the next rule applies.
+      * The cap binds: the whole run is dropped, unless it starts at the
+        largest singular value (then the cut stays where the cap put it).
     """
     r = len(s)
     w = s * s
@@ -159,14 +169,26 @@ def truncation_rank(s: np.ndarray, chi_max: int, cutoff: float,
         m1 = abs(tail[k_eps] - thr) / thr
         m2 = abs(tail[k_eps - 1] - thr) / thr
         stats.min_margin = min(stats.min_margin, m1, m2)
-    if k < r and s[k - 1] - s[k] <= TIE_TOL * s[k - 1]:
-        i = k - 1
-        while i > 0 and s[i - 1] - s[i] <= TIE_TOL * s[i - 1]:
-            i -= 1
-        if i > 0:
-            k = i
-            if stats is not None:
-                stats.ties += 1
+
+    def tied(j):          # s[j - 1] and s[j] belong to one run
+        return s[j - 1] - s[j] <= TIE_TOL * s[j - 1]
+
+    if k < r and tied(k):
+        moved = k
+        end = k
+        while end < r and tied(end):
+            end += 1                       # the run ends at index end - 1
+        if k_eps <= chi_max and end <= chi_max:
+            moved = end                    # keep the whole run
+        else:
+            start = k - 1
+            while start > 0 and tied(start):
+                start -= 1                 # the run starts at index start
+            if start > 0:
+                moved = start              # drop the whole run
+        if moved != k and stats is not None:
+            stats.ties += 1
+        k = moved
     return k
 
 

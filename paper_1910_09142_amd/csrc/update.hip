@@ -280,9 +280,12 @@ __global__ void k_mark_small_done(Batch b, UpdScratch s, UpdParams u,
 //   k = min(k_eps, chi_max), k_eps the smallest k >= 1 whose discarded
 //   tail sum_{j>=k} sigma_j^2 is <= cutoff * sum_j sigma_j^2 (relative
 //   discarded weight, Results section); values at or below SIGMA_FLOOR
-//   sigma_0 are numerically zero and always dropped; a cut inside a run
-//   of ties (relative gaps <= TIE_TOL) drops the whole run unless it
-//   starts at sigma_0.  ln sum sigma^2 = ln ||theta'||^2 goes into logw
+//   sigma_0 are numerically zero and always dropped.  No cut falls inside
+//   a run of ties (relative gaps <= TIE_TOL): when the target set the cut
+//   the whole run is kept (the discarded weight stays within the target),
+//   unless that passes chi_max; then, as when the cap sets the cut, the
+//   whole run is dropped unless it starts at sigma_0.
+//   ln sum sigma^2 = ln ||theta'||^2 goes into logw
 //   for a gate (the sampling weight is the product of these norms).
 // =====================================================================
 __global__ void __launch_bounds__(NT)
@@ -337,13 +340,26 @@ __global__ void __launch_bounds__(NT)
       else
         break;
     }
-    int k = k_eps < u.chi_max ? k_eps : u.chi_max;
-    if (k > kfloor) k = kfloor;
-    if (k < 1) k = 1;
-    if (k < N && key[k - 1] - key[k] <= TIE_TOL * key[k - 1]) {
-      int i = k - 1;
-      while (i > 0 && key[i - 1] - key[i] <= TIE_TOL * key[i - 1]) --i;
-      if (i > 0) k = i;
+    // the largest k allowed: the cap and the numerical floor
+    int kcap = u.chi_max < kfloor ? u.chi_max : kfloor;
+    if (kcap < 1) kcap = 1;
+    int k = k_eps < kcap ? k_eps : kcap;
+    auto tied = [&](int j) {
+      return key[j - 1] - key[j] <= TIE_TOL * key[j - 1];
+    };
+    if (k < N && tied(k)) {
+      // no cut inside a run of ties: keep the whole run when the target
+      // set the cut and the run fits under the cap, else drop it (unless
+      // it starts at sigma_0)
+      int end = k;
+      while (end < N && tied(end)) ++end;
+      if (k_eps <= kcap && end <= kcap) {
+        k = end;
+      } else {
+        int i = k - 1;
+        while (i > 0 && tied(i)) --i;
+        if (i > 0) k = i;
+      }
     }
     double kept = 0.0;
     for (int j = k - 1; j >= 0; --j) kept += key[j] * key[j];

@@ -180,6 +180,56 @@ def test_truncation_rank_cases():
     assert mps.truncation_rank(s3, 2, 0.0) == 2
 
 
+def test_truncation_tie_run_when_the_target_sets_the_cut():
+    # Results section, third source of error: the discarded weight is held
+    # at the target.  Spectrum with a three-fold run at indices 2..4; the
+    # target alone would cut after index 2, inside the run.
+    s = np.array([0.9, 0.3, 0.1, 0.1, 0.1 * (1 - 1e-12), 1e-3])
+    tot = float((s * s).sum())            # 0.930001
+    cut = 0.025 / tot                     # tail from 3 = 0.020001 < 0.025
+    assert mps.truncation_rank(s, 100, cut) == 5   # the whole run is kept
+    # discarded weight of that choice: only the last value, within target
+    assert float((s[5:] ** 2).sum()) <= cut * tot
+    # the run does not fit under the cap: the cap binds and the run is
+    # dropped, even though the target alone would keep 3
+    assert mps.truncation_rank(s, 4, cut) == 2
+    assert mps.truncation_rank(s, 3, cut) == 2
+    # exactly at the end of the run the cap admits it
+    assert mps.truncation_rank(s, 5, cut) == 5
+    # a target that cuts between runs is untouched by the tie rule
+    assert mps.truncation_rank(s, 100, 0.05 / tot) == 2
+    st = mps.Stats()
+    mps.truncation_rank(s, 100, cut, st)
+    assert st.ties == 1
+
+
+def test_truncation_never_cuts_a_run_and_keeps_the_target_when_uncapped():
+    # property over random spectra with planted runs of ties: with no
+    # binding cap the discarded weight never exceeds the target, and no
+    # cut (capped or not) falls between two tied values unless the run
+    # starts at the largest value
+    rng = np.random.default_rng(7)
+    for trial in range(400):
+        n = int(rng.integers(2, 40))
+        s = np.sort(rng.exponential(size=n))[::-1].copy()
+        for _ in range(int(rng.integers(0, 4))):
+            i = int(rng.integers(0, n - 1))
+            run = int(rng.integers(2, 5))
+            s[i:i + run] = s[i] * (1 - 1e-12 * np.arange(run)[: n - i])
+        s = np.sort(s)[::-1].copy()
+        tot = float((s * s).sum())
+        cut = float(10 ** rng.uniform(-6, -0.5))
+        k = mps.truncation_rank(s, n, cut)
+        assert 1 <= k <= n
+        assert float((s[k:] ** 2).sum()) <= cut * tot * (1 + 1e-12)
+        chi = int(rng.integers(1, n + 1))
+        k2 = mps.truncation_rank(s, chi, cut)
+        assert 1 <= k2 <= chi
+        if k2 < n and s[k2 - 1] - s[k2] <= mps.TIE_TOL * s[k2 - 1]:
+            # only a run that starts at sigma_0 may be cut
+            assert np.all(s[0] - s[:k2 + 1] <= mps.TIE_TOL * s[0] * (k2 + 1))
+
+
 # --------------------------------------------------------------------------
 # whole MPS path against the dense Trotter product (exhaustive sums)
 # --------------------------------------------------------------------------
