@@ -1,30 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the hybrid METTS-ancilla hot path on one MI355X.
 
-One step = one full sample of every chain of the batch: imaginary-time
-evolution to beta/2 (every Trotter gate and swap with its truncated SVD),
-measurement of every bond, projective collapse of the environment and
-re-initialisation (Markov chain steps 2-4 of Chen & Stoudenmire,
-arXiv:1910.09142).  The default workload is the 2x16 S=1 ladder with
-J_rung = 0.5, W = 2, beta = 5, tau = 0.05, chi_max = 256, cutoff 1e-10 in
-FP64 (one chain); inputs are synthetic (Philox product states).
+Default line: two-site gate applications per second at chi = 256, FP64,
+64 independent chains batched.  Every chain holds one MPS bond with chi_l =
+chi_m = chi_r = 256 (synthetic Haar factors, Schmidt values exp(-j/24));
+one step applies exp(-(tau/2) J S.S) (tau = 0.05, J = 1) to every chain:
+theta = T_k T_{k+1}, the gate, the log-weight update, and the truncated
+SVD of the 768 x 768 theta' back to chi_max = 256 at cutoff 1e-10, the
+bond swept back and forth (Ancilla Method subsection: a two-site gate
+followed by a truncated SVD; Results section: the cutoff).  Inputs are
+resident on the device before the timed region.
 
-Prints one JSON line.  `value` counts the two-site Trotter updates (gates
-and swaps; orthogonality-centre moves excluded) per second of the timed
-region, all chains together.
+Extra fields of the same line: the same workload on one chain, in mixed
+precision (FP32 theta and gate) with its speedup over FP64, a bounded
+samples-per-second run (one full Markov-chain sample of 64 chains of the
+2x8 ladder at beta = 1), the roofline of the dominant kernel and the FP64
+oracle on the host's cores.
 
-`--workload m1` measures single gate applications at chi = 256 instead:
-every chain holds one bond with chi_l = chi_m = chi_r = 256 (synthetic
-Haar factors, Schmidt values exp(-j/24)); one step applies exp(-(tau/2) J
-S.S) with tau = 0.05, J = 1 to every chain, with the truncated SVD back to
-chi_max = 256 at cutoff 1e-10, sweeping the bond back and forth.
+`--workload c1..c5` runs whole samples of a ladder workload instead (one
+step = one sample of every chain: evolution to beta/2, measurement,
+collapse), `--workload m1` the gate workload alone.
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
-import math
 import os
+import platform
 import sys
 import time
 
@@ -35,33 +38,63 @@ METRIC = ("two-site gate apps/sec at χ=256 (FP64 vs mixed, batched); "
           "METTS samples/sec")
 UNIT = "two-site gate applications/s"
 FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBPS = 8000.0
+DEFAULT_CHAINS = 64
+
+# Conservative rates used only to check that a command's planned work fits
+# the time the bench is given (half of what MI355X measured).
+PLAN_GATES_PER_S_BATCHED = 150.0    # chi = 256, 64 chains
+PLAN_GATES_PER_S_SINGLE = 12.0      # chi = 256, one chain
+PLAN_SAMPLE_SECONDS = 60.0          # one 2x8 beta = 1 sample of 64 chains
+PLAN_STARTUP_SECONDS = 150.0        # first torch import on a fresh box,
+                                    # inputs, library load
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default 1 sample; m1: 20 gates)")
-    ap.add_argument("--warmup", type=int, default=None,
-                    help="untimed steps (default 0; m1: 2)")
-    ap.add_argument("--workload", default="c3",
-                    choices=["c1", "c2", "c3", "c4", "c5", "m1"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="gate",
+                    choices=["gate", "m1", "c1", "c2", "c3", "c4", "c5"],
+                    help="gate (default): the chi = 256 gate workload with "
+                    "its extra fields; m1: that workload alone; c1..c5: "
+                    "whole samples of a ladder workload")
     ap.add_argument("--chains", type=int, default=None,
-                    help="override the number of chains of the workload")
+                    help="chains (default: 64 for the gate workload, the "
+                    "workload's own count for ladders)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"],
                     help="mixed: FP32 theta contraction and gate on the "
                     "matrix cores, FP64 SVD, truncation and observables")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="budget of the oracle baseline (0 disables it)")
-    args = ap.parse_args()
-    bond = args.workload == "m1"
-    if args.steps is None:
-        args.steps = 20 if bond else 1
-    if args.warmup is None:
-        args.warmup = 2 if bond else 0
+    ap.add_argument("--no-extras", action="store_true",
+                    help="gate workload: headline measurement only")
+    args = ap.parse_args(argv)
+    if args.steps < 1 or args.warmup < 0:
+        ap.error("--steps >= 1 and --warmup >= 0")
     return args
 
 
+def planned_seconds(args) -> float:
+    """Upper estimate of the wall time of a command, from conservative
+    rates: the bench must finish well inside the time it is given."""
+    if args.workload not in ("gate", "m1"):
+        return float("inf")    # whole ladder samples: minutes per step
+    n = args.steps + args.warmup
+    B = args.chains or DEFAULT_CHAINS
+    rate = PLAN_GATES_PER_S_SINGLE if B == 1 else PLAN_GATES_PER_S_BATCHED
+    t = PLAN_STARTUP_SECONDS + n * B / rate
+    if args.workload == "gate" and not args.no_extras:
+        t += n * B / PLAN_GATES_PER_S_BATCHED        # mixed, batched
+        t += n / PLAN_GATES_PER_S_SINGLE              # one chain
+        t += PLAN_SAMPLE_SECONDS
+    return t + args.cpu_seconds
+
+
+# ---------------------------------------------------------------------------
+# roofline
+# ---------------------------------------------------------------------------
 # Sources that make up the round kernel; a traffic figure measured with
 # hardware counters holds only for the code it was measured on.
 KERNEL_SOURCES = ("jacobi.hip", "device_common.h", "hmps_internal.h")
@@ -85,13 +118,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(wl):
+def measured_traffic(tag):
     """HBM bytes per round-kernel launch from the committed rocprofv3
     counter summary of this workload (FETCH_SIZE and WRITE_SIZE scaled by
     the copy-kernel calibration), or None when there is none or it was
     taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles",
-                        f"k_jacobi_round_traffic_{wl.name}.md")
+    path = os.path.join(ROOT, "profiles", f"k_jacobi_round_traffic_{tag}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -109,63 +141,10 @@ def measured_traffic(wl):
         return None
 
 
-def model_steps(wl):
-    """Trotter steps of one evolution to beta/2."""
-    return int(round(wl.beta / (2.0 * wl.tau)))
-
-
-def prefix_rate(marks, t0, n_updates, per_step):
-    """(steps, updates, updates/s) of the GPU over the fewest leading
-    Trotter steps of the timed sample that cover n_updates, from the
-    (steps done, time) marks of the progress callback; None without marks."""
-    if not marks or per_step <= 0:
-        return None
-    need = max(1, int(-(-n_updates // per_step)))
-    for done, t in marks:
-        if done >= need and t > t0:
-            ups = int(round(done * per_step))
-            return done, ups, ups / (t - t0)
-    return None
-
-
-def cpu_baseline(wl, seconds):
-    """The FP64 oracle on the same workload: chain 0, seed 0, sample 0,
-    Trotter updates in order until the time budget is spent."""
-    from oracle import model, mps
-    threads = oracle_threads()
-    lat = model.ladder(wl.L, wl.J_leg, wl.J_rung, W=wl.W)
-    lay = model.layout(lat)
-    sch = model.schedule(lat, lay)
-    M = model.trotter_steps(wl.beta, wl.tau)
-    gates = [model.gate(J, wl.tau / 2.0) for J in sch.couplings]
-    swap = model.swap_gate()
-    psi = mps.init_state(lay, mps.initial_outcomes(lay, wl.seed, 0), 0)
-    st = mps.Stats()
-    t0 = time.perf_counter()
-    n = 0
-    for u in model.evolve_updates(sch, M):
-        if u.op == model.OP_SWAP:
-            mps.apply_update(psi, u.k, swap, False, u.right, wl.chi_max,
-                             wl.cutoff, st)
-        else:
-            mps.apply_update(psi, u.k, gates[u.op], True, u.right,
-                             wl.chi_max, wl.cutoff, st)
-        n += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    total = M * len(sch.step)
-    return {"value": n / dt, "unit": UNIT, "cores": int(threads),
-            "kind": "oracle", "n_updates": n,
-            "sample": (f"first {n} of the {total} Trotter updates of sample 0 "
-                       f"(chain 0, seed {wl.seed}); chi reached "
-                       f"{st.max_chi} of {wl.chi_max}; the rest of the "
-                       "sample runs at larger chi, so this rate is an upper "
-                       "bound for the oracle")}
-
-
-def svd_roofline(wl, s0, s1, use_traffic):
-    """Roofline object of the round kernel over the timed region."""
+def svd_roofline(tag, s0, s1, use_traffic):
+    """Roofline object of the round kernel over the timed region: achieved
+    = Golub-Reinsch SVD flops of the updates (the algorithmic count) over
+    the HIP-event span of the rounds on the library's stream."""
     launches = s1.round_launches - s0.round_launches
     svd_s = s1.svd_seconds - s0.svd_seconds
     svd_f = s1.svd_flops - s0.svd_flops
@@ -175,116 +154,248 @@ def svd_roofline(wl, s0, s1, use_traffic):
         "bound": "mfma", "achieved": achieved,
         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS,
-        "traffic": measured_traffic(wl) if use_traffic else None,
+        "traffic": measured_traffic(tag) if use_traffic else None,
         "kernel": "k_jacobi_round",
         "launches": launches,
         "avg_launch_us": 1e6 * svd_s / launches if launches else None,
         "flops_per_launch": svd_f / launches if launches else None,
         "algo_bytes_per_launch": svd_b / launches if launches else None,
         "algo_hbm_GBps": svd_b / svd_s / 1e9 if svd_s > 0 else None,
-        "hbm_peak_GBps": 8000.0,
+        "hbm_peak_GBps": HBM_PEAK_GBPS,
     }
 
 
-def oracle_threads():
+# ---------------------------------------------------------------------------
+# host description and the oracle baselines
+# ---------------------------------------------------------------------------
+def host_info():
+    import numpy  # noqa: F401  (loads the BLAS threadpoolctl reports)
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas, threads = "unknown", os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
-        return int(max([p.get("num_threads", 1) for p in threadpool_info()]
-                       or [1]))
+        info = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if info:
+            blas = (f"{info[0].get('internal_api')} "
+                    f"{info[0].get('version')}").strip()
+            threads = int(info[0].get("num_threads", threads))
     except Exception:
-        return os.cpu_count() or 1
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(),
+            "blas": blas, "blas_threads": threads}
 
 
-def cpu_baseline_bond(wl, center, right, seconds):
+def oracle_bond_rate(wl, center, right, seconds, threads=None):
     """The FP64 oracle's two-site update on chain 0's bond, repeated with
-    the centre sweeping back and forth until the time budget is spent."""
+    the centre sweeping back and forth until the time budget is spent;
+    returns (applications per second, applications, seconds)."""
     import numpy as np
     from oracle import model, mps
     tensors = [np.ascontiguousarray(T.transpose(1, 0, 2))   # [a, s, b]
                for T in (center[0], right[0])]
     psi = mps.MPS(tensors, 0)
     g = model.gate(wl.J, wl.x)
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        mps.apply_update(psi, 0, g, True, n % 2 == 0, wl.chi_max, wl.cutoff)
-        n += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": UNIT, "cores": oracle_threads(),
+
+    def loop():
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            mps.apply_update(psi, 0, g, True, n % 2 == 0, wl.chi_max,
+                             wl.cutoff)
+            n += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        return n, time.perf_counter() - t0
+
+    if threads is None:
+        n, dt = loop()
+    else:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=threads):
+            n, dt = loop()
+    return n / dt, n, dt
+
+
+def cpu_baseline_bond(wl, center, right, seconds):
+    """The oracle on the gate workload: all BLAS threads for 2/3 of the
+    budget, then one thread (the paper's one-core protocol) for the rest."""
+    info = host_info()
+    v_all, n_all, dt_all = oracle_bond_rate(wl, center, right,
+                                            seconds * 2.0 / 3.0)
+    v_one, n_one, dt_one = oracle_bond_rate(wl, center, right,
+                                            seconds / 3.0, threads=1)
+    return {"value": v_all, "unit": UNIT, "cores": info["blas_threads"],
             "kind": "oracle",
-            "sample": (f"{n} gate applications on chain 0's bond (chi "
-                       f"{wl.chi} x {wl.chi} x {wl.chi}, the same input) in "
-                       f"{dt:.1f} s")}
+            "sample": (f"{n_all} gate applications on chain 0's bond (chi "
+                       f"{wl.chi} x {wl.chi} x {wl.chi}, the GPU's input) in "
+                       f"{dt_all:.1f} s on {info['blas_threads']} BLAS "
+                       f"threads; then {n_one} in {dt_one:.1f} s on one "
+                       "thread"),
+            "single_core_value": v_one,
+            **info}
 
 
-def main_bond(args):
-    """Single gate applications at chi = 256 (the m1 workload)."""
+# ---------------------------------------------------------------------------
+# gate workload
+# ---------------------------------------------------------------------------
+def gate_run(wl, center, right, precision, steps, warmup, label):
+    """Applies the gate steps + warmup times to every chain; returns the
+    rate over the timed steps and the stats around them."""
     import torch
-    from paper_1910_09142_amd import hmps, workloads
-    wl = workloads.M1
-    B = args.chains or 1
-    chi = wl.chi
-    center, right = workloads.bond_tensors(wl.seed, B, chi, chi, chi,
-                                           wl.decay)
-    precision = (hmps.PREC_MIXED_FP32 if args.precision == "mixed"
-                 else hmps.PREC_FP64)
-    ctx = hmps.Context(B, 2, chi, 1, precision=precision)
+    from paper_1910_09142_amd import hmps
+    B = center.shape[0]
+    ctx = hmps.Context(B, 2, wl.chi, 1, precision=precision)
     ctx.hmps_load_bond(center, right)
-    for i in range(args.warmup):
+    for _ in range(warmup):
         ctx.hmps_apply_gate(wl.J, wl.x, wl.chi_max, wl.cutoff)
-    print(f"warmup done ({args.warmup} gate applications)", file=sys.stderr,
-          flush=True)
     s0 = ctx.hmps_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         ctx.hmps_apply_gate(wl.J, wl.x, wl.chi_max, wl.cutoff)
-        if (i + 1) % 10 == 0:
-            print(f"gate application {i + 1}/{args.steps} "
-                  f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+        if (i + 1) % 10 == 0 or i + 1 == steps:
+            print(f"{label}: gate step {i + 1}/{steps} "
+                  f"({time.perf_counter() - t0:.2f} s)", file=sys.stderr,
                   flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     s1 = ctx.hmps_stats()
     chi_now = ctx.hmps_bond_dims()[:, 1]
+    logw = ctx.hmps_apply_gate(wl.J, wl.x, wl.chi_max, wl.cutoff,
+                               want_logw=True)
     ctx.hmps_destroy()
     gates = s1.gate_updates - s0.gate_updates
+    return {"rate": gates / elapsed, "elapsed": elapsed, "s0": s0, "s1": s1,
+            "chi_after": int(chi_now.min()), "logw": logw,
+            "sweeps_per_gate": (s1.jacobi_sweeps - s0.jacobi_sweeps)
+            / max(1, steps),
+            "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12}
+
+
+def sample_run(wl, B, precision):
+    """One full Markov-chain sample of B chains of a ladder workload:
+    evolution to beta/2, measurement, collapse (timed from resident
+    product states)."""
+    import torch
+    from paper_1910_09142_amd import hmps, workloads
+    n, bonds, order, mask = workloads.ladder_arrays(wl.L, wl.J_leg,
+                                                    wl.J_rung, wl.W)
+    lat = hmps.Lattice(n, bonds, order, mask)
+    ctx = hmps.Context(B, workloads.mps_length(wl.L, wl.W), wl.chi_max,
+                       len(bonds), precision=precision)
+    ctx.hmps_init_cluster_env(lat, B, wl.seed)
+    s0 = ctx.hmps_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.hmps_evolve(wl.beta, wl.tau, wl.chi_max, wl.cutoff)
+    m = ctx.hmps_measure()
+    ctx.hmps_collapse_resample(0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s1 = ctx.hmps_stats()
+    ctx.hmps_destroy()
+    ups = (s1.updates - s0.updates) - (s1.move_updates - s0.move_updates)
+    return {"workload": wl.name, "n_chains": B, "samples": B,
+            "seconds": elapsed, "value": B / elapsed,
+            "unit": "METTS samples/s",
+            "trotter_updates_per_s": ups / elapsed,
+            "hamiltonian_gates_per_s": (s1.gate_updates - s0.gate_updates)
+            / elapsed,
+            "max_chi": s1.max_chi,
+            "energy_mean": float(m["energy"].mean())}
+
+
+def gate_tag(wl, B):
+    return wl.name if B == 1 else f"{wl.name}_batch{B}"
+
+
+def main_gate(args, extras):
+    """Gate applications at chi = 256 (the headline line)."""
+    import numpy as np
+    from paper_1910_09142_amd import hmps, workloads
+    wl = workloads.M1
+    B = args.chains or DEFAULT_CHAINS
+    center, right = workloads.bond_tensors(wl.seed, B, wl.chi, wl.chi,
+                                           wl.chi, wl.decay)
+    prec = (hmps.PREC_MIXED_FP32 if args.precision == "mixed"
+            else hmps.PREC_FP64)
+    copy_probe()
+    print(f"inputs ready: {B} bonds at chi {wl.chi}", file=sys.stderr,
+          flush=True)
+    head = gate_run(wl, center, right, prec, args.steps, args.warmup,
+                    f"{args.precision} x{B}")
+    tag = gate_tag(wl, B)
     out = {
-        "metric": METRIC, "value": gates / elapsed, "unit": UNIT,
+        "metric": METRIC, "value": head["rate"], "unit": UNIT,
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": 1e3 * head["elapsed"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic (Philox-seeded Haar bond tensors)",
-        "config": {"workload": wl.name, "n_chains": B, "chi_l": chi,
-                   "chi_m": chi, "chi_r": chi, "J": wl.J, "x": wl.x,
+        "config": {"workload": tag, "n_chains": B, "chi_l": wl.chi,
+                   "chi_m": wl.chi, "chi_r": wl.chi, "J": wl.J, "x": wl.x,
                    "chi_max": wl.chi_max, "cutoff": wl.cutoff,
                    "schmidt_decay": wl.decay, "precision": args.precision},
-        "bond_dim_after": int(chi_now.min()),
-        "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12,
-        "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
-        "roofline": svd_roofline(wl, s0, s1, args.precision == "fp64"),
+        "bond_dim_after": head["chi_after"],
+        "algo_tflops": head["algo_tflops"],
+        "jacobi_sweeps_per_gate": head["sweeps_per_gate"],
+        "roofline": svd_roofline(tag, head["s0"], head["s1"],
+                                 args.precision == "fp64"),
     }
+    if extras:
+        one = gate_run(wl, center[:1], right[:1], prec, args.steps,
+                       args.warmup, f"{args.precision} x1")
+        out["single_chain"] = {
+            "value": one["rate"], "unit": UNIT,
+            "ms_per_gate": 1e3 / one["rate"],
+            "jacobi_sweeps_per_gate": one["sweeps_per_gate"],
+            "roofline": svd_roofline(gate_tag(wl, 1), one["s0"], one["s1"],
+                                     False)}
+        other = "mixed" if args.precision == "fp64" else "fp64"
+        oprec = (hmps.PREC_MIXED_FP32 if other == "mixed"
+                 else hmps.PREC_FP64)
+        alt = gate_run(wl, center, right, oprec, args.steps, args.warmup,
+                       f"{other} x{B}")
+        fp64, mixed = (head, alt) if other == "mixed" else (alt, head)
+        out["mixed"] = {
+            "value": mixed["rate"], "unit": UNIT, "n_chains": B,
+            "speedup_vs_fp64": mixed["rate"] / fp64["rate"],
+            "jacobi_sweeps_per_gate": mixed["sweeps_per_gate"],
+            "max_abs_logw_diff_vs_fp64": float(
+                np.abs(mixed["logw"] - fp64["logw"]).max())}
+        c2 = dataclasses.replace(workloads.C2, beta=1.0,
+                                 name="ladder2x8_W2_beta1_chi128")
+        out["samples_per_s"] = sample_run(c2, DEFAULT_CHAINS, prec)
+        print("sample run done", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline_bond(wl, center, right,
                                                 args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the chains are independent "
-              "Markov chains that shard over GPUs without communication, and "
-              "this benchmark does not run on more than one GPU",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "m1":
-        main_bond(args)
-        return
+def copy_probe():
+    """One device-to-device copy of 256 MiB: the calibration kernel of the
+    hardware byte counters in a profiled run of this command."""
+    import torch
+    a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+# ---------------------------------------------------------------------------
+# whole samples of a ladder workload
+# ---------------------------------------------------------------------------
+def main_ladder(args):
     import torch
     from paper_1910_09142_amd import hmps, workloads
 
@@ -294,14 +405,11 @@ def main():
                                                     wl.J_rung, wl.W)
     lat = hmps.Lattice(n, bonds, order, mask)
     t_start = time.perf_counter()
-    step_marks = []  # (Trotter steps done, time) of the first timed sample
 
     def progress(done, total):
-        # one line per Trotter step: evolutions at chi = 256 take minutes
-        now = time.perf_counter()
-        step_marks.append((done, now))
-        print(f"trotter step {done}/{total} ({now - t_start:.1f} s)",
-              file=sys.stderr, flush=True)
+        print(f"trotter step {done}/{total} "
+              f"({time.perf_counter() - t_start:.1f} s)", file=sys.stderr,
+              flush=True)
 
     precision = (hmps.PREC_MIXED_FP32 if args.precision == "mixed"
                  else hmps.PREC_FP64)
@@ -319,17 +427,12 @@ def main():
     for _ in range(args.warmup):
         one_sample(sample)
         sample += 1
-        print(f"warmup sample done", file=sys.stderr, flush=True)
     s0 = ctx.hmps_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     energies = []
-    timed_marks = None
     for _ in range(args.steps):
-        step_marks.clear()
         m = one_sample(sample)
-        if timed_marks is None:
-            timed_marks = list(step_marks)
         energies += m["energy"].tolist()
         sample += 1
         print(f"timed sample done ({time.perf_counter() - t0:.1f} s)",
@@ -337,46 +440,48 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     s1 = ctx.hmps_stats()
+    ctx.hmps_destroy()
     trotter_updates = ((s1.updates - s0.updates)
                        - (s1.move_updates - s0.move_updates))
     gates = s1.gate_updates - s0.gate_updates
-    value = trotter_updates / elapsed
     out = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
+        "metric": METRIC, "value": gates / elapsed, "unit": UNIT,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic (Philox-seeded product states, ladder Hamiltonian)",
-        "config": {"workload": wl.name, "n_chains": B, "L": wl.L, "W": wl.W,
+        "config": {"workload": wl.name if B == wl.n_chains
+                   else f"{wl.name}_chains{B}",
+                   "n_chains": B, "L": wl.L, "W": wl.W,
                    "J_leg": wl.J_leg, "J_rung": wl.J_rung, "beta": wl.beta,
                    "tau": wl.tau, "chi_max": wl.chi_max, "cutoff": wl.cutoff,
                    "samples_per_step": 1, "precision": args.precision},
         "samples_per_s": B * args.steps / elapsed,
-        "hamiltonian_gates_per_s": gates / elapsed,
+        "trotter_updates_per_s": trotter_updates / elapsed,
         "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12,
         "max_chi": s1.max_chi,
         "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
         "energy_mean": sum(energies) / len(energies),
-        "roofline": svd_roofline(
-            wl, s0, s1, args.precision == "fp64" and B == wl.n_chains),
+        "roofline": svd_roofline(wl.name, s0, s1,
+                                 args.precision == "fp64" and B == wl.n_chains),
     }
-    ctx.hmps_destroy()
-    if args.cpu_seconds > 0:
-        cb = cpu_baseline(wl, args.cpu_seconds)
-        # the oracle covers only the first updates of the sample (small chi):
-        # the GPU's rate over the same leading Trotter steps, for comparison
-        per_step = trotter_updates / max(1, args.steps) / max(
-            1, model_steps(wl))
-        g = (prefix_rate(timed_marks or [], t0, cb["n_updates"], per_step)
-             if B == 1 else None)
-        if g is not None:
-            cb["sample"] += (f"; the GPU ran the first {g[0]} Trotter steps "
-                             f"of the timed sample ({g[1]} updates) at "
-                             f"{g[2]:.1f} updates/s")
-        del cb["n_updates"]
-        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the chains are independent "
+              "Markov chains that shard over GPUs without communication, and "
+              "this benchmark does not run on more than one GPU",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("gate", "m1"):
+        main_gate(args, extras=args.workload == "gate" and not args.no_extras)
+    else:
+        main_ladder(args)
 
 
 if __name__ == "__main__":

@@ -56,6 +56,17 @@ typedef int32_t hmps_status;
  * are FP64 in both modes. */
 #define HMPS_PREC_FP64 0
 #define HMPS_PREC_MIXED_FP32 1
+/* Split-bf16 (three bf16 products per FP32 product) contractions are not
+ * built: hmps_create rejects this value with HMPS_E_INVALID.  The theta
+ * contraction is a small share of an update; the SVD sets the cost. */
+#define HMPS_PREC_MIXED_BF16X3 2
+
+/* Bits of the `what` mask of hmps_measure. */
+#define HMPS_MEASURE_ENERGY 1u /* energy (needs every bond correlator)   */
+#define HMPS_MEASURE_BONDS 2u  /* <S_i.S_j> of every Hamiltonian bond    */
+#define HMPS_MEASURE_LOGW 4u   /* log-weights (no device contraction)    */
+#define HMPS_MEASURE_QN 8u     /* <Q>, Q = sum_phys S^z - sum_anc S^z    */
+#define HMPS_MEASURE_ALL 15u
 
 typedef struct {
   int32_t device;          /* HIP device ordinal                          */
@@ -116,6 +127,9 @@ typedef struct {
   double svd_bytes;         /* algorithmic bytes of those rounds: each
                                vector read once per round, and written
                                once while its chain still rotates        */
+  int64_t center;           /* MPS position of the orthogonality centre  */
+  int64_t evolve_pos;       /* updates applied of an evolution run in
+                               parts by hmps_evolve_updates (0: none)    */
 } hmps_stats_t;
 
 /* Bytes of device workspace needed for the given capacities. */
@@ -138,10 +152,28 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt);
  * with Philox4x64-10 (key = (seed, 0), counter = (chain, 0, MPS position,
  * 0), label = floor(3 u), u = top 53 bits / 2^53).  Resets the sample
  * counter to 0 and every log-weight to 0.  E_INVALID for a malformed
- * lattice, a label > 2, or capacities exceeded. */
+ * lattice, a label > 2, or capacities exceeded.  Same as
+ * hmps_init_cluster_env_at with chain_offset = 0 and sample = 0. */
 hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
                                   int32_t n_chains, uint64_t seed,
                                   const uint8_t *env_state, int32_t basis);
+
+/* Step 1 for chains chain_offset .. chain_offset + n_chains - 1 of a
+ * larger ensemble, starting at sample `sample` (the Markov chains of the
+ * Hybrid METTS-Ancilla subsection are independent, so the ensemble splits
+ * over contexts or devices, and a chain resumes from the product state its
+ * last collapse produced).  Every Philox counter carries the global chain
+ * id chain_offset + c and the sample index: the initial draws use
+ * (chain_offset + c, sample, MPS position, 0) and the collapse of sample n
+ * uses (chain_offset + c, n, MPS position, 1).  So chains split over
+ * contexts with matching offsets, or resumed at sample n with the outcomes
+ * of sample n - 1 (in its basis), reproduce an uninterrupted run bit for
+ * bit.  E_INVALID as hmps_init_cluster_env, and for sample < 0 or an
+ * offset whose chain ids overflow. */
+hmps_status hmps_init_cluster_env_at(hmps_ctx *ctx, const hmps_lattice *lat,
+                                     int32_t n_chains, uint64_t seed,
+                                     uint64_t chain_offset, int64_t sample,
+                                     const uint8_t *env_state, int32_t basis);
 
 /* Step 2: apply (e^{-tau H})^M, M = beta/(2 tau) (Ancilla Method
  * subsection; M must be an integer to 1e-9, else E_INVALID), as a second-
@@ -156,21 +188,47 @@ hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
 hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
                         int32_t chi_max, double cutoff);
 
+/* Part of the evolution hmps_evolve(beta, tau, chi_max, cutoff) applies:
+ * its two-site updates first .. first + count - 1 (the list has M times
+ * the updates of one Trotter step, see hmps_schedule), each with the
+ * centre moves it needs.  Parts must follow each other (first = the
+ * number already applied, hmps_stats.evolve_pos) with the same
+ * parameters, else E_STATE / E_INVALID; the part that applies the last
+ * update also moves the centre to site 0, as hmps_evolve does.  For
+ * update-by-update comparison with a reference (teacher forcing).
+ * E_INVALID for a range outside [0, M * steplen] and as hmps_evolve. */
+hmps_status hmps_evolve_updates(hmps_ctx *ctx, double beta, double tau,
+                                int32_t chi_max, double cutoff, int64_t first,
+                                int64_t count);
+
+/* Result of the last two-site update of every chain (a Trotter gate, a
+ * swap or a centre move): rank[c] = singular values kept, sigma[c * cap +
+ * j] (j < min(rank[c], cap)) the kept singular values of theta' in
+ * descending order, before the kept ones are renormalised (theta' of a
+ * gate has unit norm; Results section: truncated SVD).  E_STATE if no
+ * update has run since the chains were created.  Synchronises. */
+hmps_status hmps_last_spectrum(hmps_ctx *ctx, int32_t cap, int32_t *rank,
+                               double *sigma);
+
 /* Step 3: per-chain Monte Carlo estimators <psi|A|psi> (Markov Chain
- * Sampling Algorithm, step 3).  Outputs (host, any may be NULL):
+ * Sampling Algorithm, step 3).  `what` is a mask of HMPS_MEASURE_* bits;
+ * an output is written when its bit is set and its pointer is not NULL,
+ * and only the contractions those outputs need run.  Outputs (host):
  *   energy  [n_chains]           sum_b J_b <S_i.S_j>
  *   bond_ss [n_chains * n_bonds] <S_i.S_j> per bond, in lattice order
  *   logw    [n_chains]           accumulated ln of squared gate norms
- *   qn      [n_chains]           <sum_phys S^z - sum_ancilla S^z>
- * Synchronises the stream. */
-hmps_status hmps_measure(hmps_ctx *ctx, double *energy, double *bond_ss,
-                         double *logw, double *qn);
+ *   qn      [n_chains]           <sum_phys S^z - sum_ancilla S^z> (an
+ *                                expectation value: an integer only for
+ *                                environments collapsed in S^z, so FP64)
+ * E_INVALID for unknown bits.  Synchronises the stream. */
+hmps_status hmps_measure(hmps_ctx *ctx, uint32_t what, double *energy,
+                         double *bond_ss, double *logw, double *qn);
 
 /* Step 4: collapse every environment site in MPS order by a projective
  * measurement in `basis` (0 = S^z, 1 = S^x), tracing the cluster sites;
  * outcome of a site = smallest label s with u < cumulative conditional
- * probability, u from Philox4x64-10 with counter (chain, sample, MPS
- * position, 1).  Then re-initialise every chain to the new product state
+ * probability, u from Philox4x64-10 with counter (global chain id, sample,
+ * MPS position, 1) (see hmps_init_cluster_env_at).  Then re-initialise every chain to the new product state
  * (in `basis`) with fresh Bell pairs and advance the sample counter.
  * env_out (host, may be NULL): n_chains x n_env labels.  Synchronises. */
 hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,

@@ -45,17 +45,19 @@ def run_sample(lat, lay, sch, M, tau, chi_max, cutoff, env, basis,
 def run_chain(lat: model.Lattice, beta: float, tau: float, chi_max: int,
               cutoff: float, n_samples: int, seed: int, chain: int = 0,
               env0: dict | None = None, basis0: int = 0,
-              record_spectra: bool = False) -> list:
-    """Samples 0..n_samples-1 of one Markov chain.  Each record holds the
-    initial product state, the estimators and the collapse outcomes."""
+              record_spectra: bool = False, first_sample: int = 0) -> list:
+    """Samples first_sample .. first_sample + n_samples - 1 of one Markov
+    chain (a chain resumes at first_sample from the product state env0 of
+    the previous collapse).  Each record holds the initial product state,
+    the estimators and the collapse outcomes."""
     lay = model.layout(lat)
     sch = model.schedule(lat, lay)
     M = model.trotter_steps(beta, tau)
     env = dict(env0) if env0 is not None else mps.initial_outcomes(
-        lay, seed, chain)
+        lay, seed, chain, first_sample)
     basis = basis0
     out = []
-    for n in range(n_samples):
+    for n in range(first_sample, first_sample + n_samples):
         st = mps.Stats()
         if record_spectra:
             st.spectra = []

@@ -230,8 +230,15 @@ struct hmps_ctx {
   Plan plan;
   int B = 0;
   uint64_t seed = 0;
+  uint64_t chain0 = 0;     // global id of chain 0 (Philox counters)
   int64_t sample = 0;
   int center = 0;
+  // an evolution applied in parts (hmps_evolve_updates): the next update
+  // of its list and the parameters it was started with
+  int64_t evo_pos = 0;
+  double evo_beta = 0.0, evo_tau = 0.0, evo_cutoff = 0.0;
+  int evo_chi = 0;
+  bool have_spectrum = false;  // d_sig / d_knew hold an update's result
   std::vector<int> h_chi;  // [B][len+1]
   hmps_stats_t stats{};
   bool sync_debug = false;  // HMPS_SYNC_DEBUG=1: check every launch
@@ -602,6 +609,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
     ctx->stats.svd_seconds += 1e-3 * ms;
     ctx->stats.svd_flops += svd_flops;
   }
+  ctx->have_spectrum = true;
   ctx->stats.algo_flops += flops;
   ctx->stats.updates += ctx->B;
   if (op >= 0) ctx->stats.gate_updates += ctx->B;
@@ -648,7 +656,7 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
       opt->max_bonds < 0 || opt->chi_cap > 640 ||
       (opt->precision != HMPS_PREC_FP64 &&
        opt->precision != HMPS_PREC_MIXED_FP32))
-    return HMPS_E_INVALID;
+    return HMPS_E_INVALID;  // HMPS_PREC_MIXED_BF16X3 included: not built
   const size_t need = hmps_workspace_bytes(opt->max_chains, opt->max_sites,
                                            opt->chi_cap, opt->max_bonds);
   if (!opt->workspace || opt->workspace_bytes < need) return HMPS_E_NOMEM;
@@ -714,9 +722,21 @@ const char *hmps_last_error(const hmps_ctx *ctx) {
 hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
                                   int32_t n_chains, uint64_t seed,
                                   const uint8_t *env_state, int32_t basis) {
+  return hmps_init_cluster_env_at(ctx, lat, n_chains, seed, 0, 0, env_state,
+                                  basis);
+}
+
+hmps_status hmps_init_cluster_env_at(hmps_ctx *ctx, const hmps_lattice *lat,
+                                     int32_t n_chains, uint64_t seed,
+                                     uint64_t chain_offset, int64_t sample,
+                                     const uint8_t *env_state, int32_t basis) {
   hmps_status st = check_usable(ctx, false);
   if (st) return st;
   DeviceGuard guard(ctx->opt.device);
+  if (sample < 0)
+    return fail(ctx, HMPS_E_INVALID, "sample must be >= 0");
+  if (chain_offset > UINT64_MAX - (uint64_t)std::max(n_chains, 0))
+    return fail(ctx, HMPS_E_INVALID, "chain_offset + n_chains overflows");
   Plan P;
   std::string why = validate_and_plan(lat, P);
   if (!why.empty()) return fail(ctx, HMPS_E_INVALID, why);
@@ -737,10 +757,12 @@ hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
     }
   } else {
     basis = 0;
+    // counter (global chain id, sample, MPS position, purpose 0)
     for (int c = 0; c < n_chains; ++c)
       for (int e = 0; e < P.n_env; ++e) {
-        const uint64_t x = philox0((uint64_t)c, 0, (uint64_t)P.env_pos[e], 0,
-                                   seed, 0);
+        const uint64_t x = philox0(chain_offset + (uint64_t)c,
+                                   (uint64_t)sample, (uint64_t)P.env_pos[e],
+                                   0, seed, 0);
         const double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);
         labels[(size_t)c * P.n_env + e] =
             (uint8_t)std::min(2, (int)std::floor(3.0 * u));
@@ -749,8 +771,11 @@ hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
   ctx->plan = P;
   ctx->B = n_chains;
   ctx->seed = seed;
-  ctx->sample = 0;
+  ctx->chain0 = chain_offset;
+  ctx->sample = sample;
   ctx->center = 0;
+  ctx->evo_pos = 0;
+  ctx->have_spectrum = false;
   ctx->ready = false;
   ctx->bond_loaded = false;
   std::memset(&ctx->stats, 0, sizeof(ctx->stats));
@@ -790,30 +815,41 @@ hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
   ctx->stats.n_chains = n_chains;
   ctx->stats.n_sites = P.len;
   ctx->stats.n_env = P.n_env;
+  ctx->stats.sample = sample;
   ctx->ready = true;
   return HMPS_OK;
 }
 
-hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
-                        int32_t chi_max, double cutoff) {
-  hmps_status st = check_usable(ctx, true);
-  if (st) return st;
-  DeviceGuard guard(ctx->opt.device);
+// Validates the parameters of an evolution and returns its number of
+// Trotter steps M = beta / (2 tau).
+static hmps_status evolve_steps(hmps_ctx *ctx, double beta, double tau,
+                                int32_t chi_max, double cutoff, int &M) {
   if (!(std::isfinite(beta) && beta >= 0.0))
     return fail(ctx, HMPS_E_INVALID, "beta must be finite and >= 0");
   if (chi_max < 1 || chi_max > ctx->opt.chi_cap)
     return fail(ctx, HMPS_E_INVALID, "chi_max outside [1, chi_cap]");
   if (!(cutoff >= 0.0) || !std::isfinite(cutoff))
     return fail(ctx, HMPS_E_INVALID, "cutoff must be finite and >= 0");
-  int M = 0;
+  M = 0;
   if (beta > 0.0) {
     if (!(tau > 0.0) || !std::isfinite(tau))
       return fail(ctx, HMPS_E_INVALID, "tau must be > 0");
     const double m = beta / (2.0 * tau);
+    if (!(m < 1e9)) return fail(ctx, HMPS_E_INVALID, "beta/(2 tau) too large");
     M = (int)std::llround(m);
     if (std::fabs(m - M) > 1e-9 * std::max(1.0, m) || M < 1)
       return fail(ctx, HMPS_E_INVALID, "beta/(2 tau) must be an integer");
   }
+  return HMPS_OK;
+}
+
+// Updates [first, first + count) of the update list of one evolution
+// (M Trotter steps of the schedule), with the centre moves they need; the
+// centre goes to site 0 once the last update of the list is done.
+static hmps_status evolve_part(hmps_ctx *ctx, double beta, double tau,
+                               int32_t chi_max, double cutoff, int M,
+                               int64_t first, int64_t count) {
+  hmps_status st = HMPS_OK;
   const auto t0 = std::chrono::steady_clock::now();
   const Plan &P = ctx->plan;
   const int ncoup = (int)P.couplings.size();
@@ -824,8 +860,12 @@ hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
   HIPCHK(hipMemcpyAsync(ctx->d_gates, g.data(), sizeof(double) * g.size(),
                         hipMemcpyHostToDevice, ctx->stream));
   const int steplen = (int)P.step_k.size();
-  const long total = (long)M * steplen;
-  for (long t = 0; t < total; ++t) {
+  const int64_t total = (int64_t)M * steplen;
+  ctx->evo_beta = beta;
+  ctx->evo_tau = tau;
+  ctx->evo_chi = chi_max;
+  ctx->evo_cutoff = cutoff;
+  for (int64_t t = first; t < first + count; ++t) {
     const int k = P.step_k[t % steplen], op = P.step_op[t % steplen];
     const int kn = (t + 1 < total) ? P.step_k[(t + 1) % steplen] : 0;
     if (ctx->center < k) {
@@ -838,11 +878,15 @@ hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
     st = do_update(ctx, k, op, right, chi_max, cutoff);
     if (st) return st;
     ctx->center = right ? k + 1 : k;
+    ctx->evo_pos = t + 1;
     if (ctx->opt.progress && (t + 1) % steplen == 0)
       ctx->opt.progress(ctx->opt.progress_user, (t + 1) / steplen, M);
   }
-  st = move_center(ctx, 0);
-  if (st) return st;
+  if (first + count == total) {
+    st = move_center(ctx, 0);
+    if (st) return st;
+    ctx->evo_pos = 0;
+  }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->stats.evolve_seconds +=
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0)
@@ -850,16 +894,94 @@ hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
   return HMPS_OK;
 }
 
-hmps_status hmps_measure(hmps_ctx *ctx, double *energy, double *bond_ss,
-                         double *logw, double *qn) {
+hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
+                        int32_t chi_max, double cutoff) {
   hmps_status st = check_usable(ctx, true);
   if (st) return st;
   DeviceGuard guard(ctx->opt.device);
+  int M = 0;
+  st = evolve_steps(ctx, beta, tau, chi_max, cutoff, M);
+  if (st) return st;
+  if (ctx->evo_pos != 0)
+    return fail(ctx, HMPS_E_STATE,
+                "an evolution applied in parts is not finished");
+  const int64_t total = (int64_t)M * (int64_t)ctx->plan.step_k.size();
+  return evolve_part(ctx, beta, tau, chi_max, cutoff, M, 0, total);
+}
+
+hmps_status hmps_evolve_updates(hmps_ctx *ctx, double beta, double tau,
+                                int32_t chi_max, double cutoff, int64_t first,
+                                int64_t count) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
+  int M = 0;
+  st = evolve_steps(ctx, beta, tau, chi_max, cutoff, M);
+  if (st) return st;
+  const int64_t total = (int64_t)M * (int64_t)ctx->plan.step_k.size();
+  if (first < 0 || count < 0 || first > total || count > total - first)
+    return fail(ctx, HMPS_E_INVALID, "update range outside the evolution");
+  if (first != ctx->evo_pos)
+    return fail(ctx, HMPS_E_STATE,
+                "updates must follow the last one applied (first = " +
+                    std::to_string(ctx->evo_pos) + ")");
+  if (first > 0 && (beta != ctx->evo_beta || tau != ctx->evo_tau ||
+                    chi_max != ctx->evo_chi || cutoff != ctx->evo_cutoff))
+    return fail(ctx, HMPS_E_INVALID,
+                "parameters differ from those the evolution started with");
+  return evolve_part(ctx, beta, tau, chi_max, cutoff, M, first, count);
+}
+
+hmps_status hmps_last_spectrum(hmps_ctx *ctx, int32_t cap, int32_t *rank,
+                               double *sigma) {
+  hmps_status st = check_usable(ctx, false);
+  if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
+  if (!ctx->have_spectrum)
+    return fail(ctx, HMPS_E_STATE, "no two-site update since initialisation");
+  if (!rank || cap < 0 || (cap > 0 && !sigma))
+    return fail(ctx, HMPS_E_INVALID, "bad output arrays");
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipMemcpyAsync(rank, ctx->d_knew, sizeof(int32_t) * ctx->B,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int c = 0; c < ctx->B; ++c) {
+    const int n = std::min(cap, (int)rank[c]);
+    if (n > 0)
+      HIPCHK(hipMemcpyAsync(sigma + (size_t)c * cap,
+                            ctx->d_sig + (size_t)c * ctx->n_cap,
+                            sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return HMPS_OK;
+}
+
+hmps_status hmps_measure(hmps_ctx *ctx, uint32_t what, double *energy,
+                         double *bond_ss, double *logw, double *qn) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
+  if (what & ~(uint32_t)HMPS_MEASURE_ALL)
+    return fail(ctx, HMPS_E_INVALID, "unknown bits in what");
+  if (!(what & HMPS_MEASURE_ENERGY)) energy = nullptr;
+  if (!(what & HMPS_MEASURE_BONDS)) bond_ss = nullptr;
+  if (!(what & HMPS_MEASURE_LOGW)) logw = nullptr;
+  if (!(what & HMPS_MEASURE_QN)) qn = nullptr;
+  const Plan &P = ctx->plan;
+  hipStream_t s = ctx->stream;
+  const size_t B = ctx->B;
+  // the log-weights need no contraction
+  if (!energy && !qn && !(bond_ss && P.n_bonds > 0)) {
+    if (logw)
+      HIPCHK(hipMemcpyAsync(logw, ctx->d_logw, sizeof(double) * B,
+                            hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HMPS_OK;
+  }
   if (ctx->center != 0) {
     st = move_center(ctx, 0);
     if (st) return st;
   }
-  const Plan &P = ctx->plan;
   Batch b = batch_of(ctx);
   MeasureArgs ma;
   ma.bond_p = ctx->d_bond_p;
@@ -874,13 +996,12 @@ hmps_status hmps_measure(hmps_ctx *ctx, double *energy, double *bond_ss,
   ma.chi2 = ctx->chi2;
   ma.norm = ctx->d_norm;
   ma.bond_ss = ctx->d_bond_ss;
-  hipStream_t s = ctx->stream;
   launch_measure_envs(b, ma, s);
-  for (int b0 = 0; b0 < P.n_bonds; b0 += ctx->slots)
-    launch_measure_bonds(b, ma, b0, std::min(ctx->slots, P.n_bonds - b0), s);
+  if (energy || bond_ss)
+    for (int b0 = 0; b0 < P.n_bonds; b0 += ctx->slots)
+      launch_measure_bonds(b, ma, b0, std::min(ctx->slots, P.n_bonds - b0), s);
   launch_measure_finish(b, ma, ctx->d_energy, ctx->d_qn, s);
   HIPCHK(hipGetLastError());
-  const size_t B = ctx->B;
   if (energy)
     HIPCHK(hipMemcpyAsync(energy, ctx->d_energy, sizeof(double) * B,
                           hipMemcpyDeviceToHost, s));
@@ -922,6 +1043,7 @@ hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
   ca.near = ctx->d_near;
   ca.basis = basis;
   ca.seed = ctx->seed;
+  ca.chain0 = ctx->chain0;
   ca.sample = ctx->sample;
   launch_collapse(b, ca, s);
   HIPCHK(hipGetLastError());
@@ -940,6 +1062,7 @@ hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
   HIPCHK(hipStreamSynchronize(s));
   init_host_chi(ctx);
   ctx->center = 0;
+  ctx->evo_pos = 0;
   ctx->sample += 1;
   ctx->stats.sample = ctx->sample;
   return HMPS_OK;
@@ -949,6 +1072,8 @@ hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out) {
   if (!ctx || !out) return HMPS_E_INVALID;
   DeviceGuard guard(ctx->opt.device);
   hmps_stats_t s = ctx->stats;
+  s.center = ctx->center;
+  s.evolve_pos = ctx->evo_pos;
   if ((ctx->ready || ctx->bond_loaded) && !ctx->poisoned) {
     std::vector<double> disc(ctx->B);
     std::vector<int32_t> sw(ctx->B);

@@ -131,6 +131,7 @@ struct CollapseArgs {
   int32_t *near;              // [B] draws within 1e-12 of a threshold
   int basis;
   uint64_t seed;
+  uint64_t chain0;            // global id of chain 0 of the batch
   int64_t sample;
 };
 void launch_collapse(const Batch &b, const CollapseArgs &a, hipStream_t st);

@@ -197,7 +197,9 @@ __global__ void __launch_bounds__(NT) k_collapse(Batch b, CollapseArgs a) {
       if (threadIdx.x == 0) {
         const double P = pr[0] + pr[1] + pr[2];
         const double cum0 = pr[0] / P, cum1 = (pr[0] + pr[1]) / P;
-        const uint64_t x = philox_word0((uint64_t)c, (uint64_t)a.sample,
+        // counter (global chain id, sample, MPS position, purpose 1)
+        const uint64_t x = philox_word0(a.chain0 + (uint64_t)c,
+                                        (uint64_t)a.sample,
                                         (uint64_t)k, 1ull, a.seed, 0ull);
         const double uu = (double)(x >> 11) * (1.0 / 9007199254740992.0);
         int sel = 2;

@@ -23,6 +23,12 @@ HMPS_E_STATE = 4
 HMPS_E_NUMERIC = 5
 PREC_FP64 = 0
 PREC_MIXED_FP32 = 1
+PREC_MIXED_BF16X3 = 2      # declared by the ABI, rejected by hmps_create
+MEASURE_ENERGY = 1
+MEASURE_BONDS = 2
+MEASURE_LOGW = 4
+MEASURE_QN = 8
+MEASURE_ALL = 15
 
 EXPORTS = [
     "hmps_workspace_bytes", "hmps_create", "hmps_init_cluster_env",
@@ -30,7 +36,8 @@ EXPORTS = [
     "hmps_bond_dims", "hmps_destroy", "hmps_last_error", "hmps_gate",
     "hmps_schedule", "hmps_svd_probe", "hmps_measure_pairs",
     "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
-    "hmps_apply_gate",
+    "hmps_apply_gate", "hmps_init_cluster_env_at", "hmps_evolve_updates",
+    "hmps_last_spectrum",
 ]
 
 
@@ -64,7 +71,8 @@ class hmps_stats_t(C.Structure):
                 ("sample", C.c_int64), ("discarded_weight", C.c_double),
                 ("evolve_seconds", C.c_double), ("algo_flops", C.c_double),
                 ("svd_flops", C.c_double), ("svd_seconds", C.c_double),
-                ("round_launches", C.c_int64), ("svd_bytes", C.c_double)]
+                ("round_launches", C.c_int64), ("svd_bytes", C.c_double),
+                ("center", C.c_int64), ("evolve_pos", C.c_int64)]
 
 
 _lib = None
@@ -87,9 +95,17 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.hmps_init_cluster_env.argtypes = [C.c_void_p, P(hmps_lattice),
                                           C.c_int32, C.c_uint64,
                                           P(C.c_uint8), C.c_int32]
+    lib.hmps_init_cluster_env_at.argtypes = [
+        C.c_void_p, P(hmps_lattice), C.c_int32, C.c_uint64, C.c_uint64,
+        C.c_int64, P(C.c_uint8), C.c_int32]
     lib.hmps_evolve.argtypes = [C.c_void_p, C.c_double, C.c_double,
                                 C.c_int32, C.c_double]
-    lib.hmps_measure.argtypes = [C.c_void_p] + [P(C.c_double)] * 4
+    lib.hmps_evolve_updates.argtypes = [C.c_void_p, C.c_double, C.c_double,
+                                        C.c_int32, C.c_double, C.c_int64,
+                                        C.c_int64]
+    lib.hmps_last_spectrum.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32),
+                                       P(C.c_double)]
+    lib.hmps_measure.argtypes = [C.c_void_p, C.c_uint32] + [P(C.c_double)] * 4
     lib.hmps_collapse_resample.argtypes = [C.c_void_p, C.c_int32,
                                            P(C.c_uint8)]
     lib.hmps_stats.argtypes = [C.c_void_p, P(hmps_stats_t)]
@@ -121,7 +137,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "hmps_bond_dims", "hmps_gate", "hmps_schedule",
                  "hmps_svd_probe", "hmps_measure_pairs",
                  "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
-                 "hmps_apply_gate"):
+                 "hmps_apply_gate", "hmps_init_cluster_env_at",
+                 "hmps_evolve_updates", "hmps_last_spectrum"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -233,15 +250,23 @@ class Context:
             raise HmpsError(st, f"{what}: {msg}")
 
     def hmps_init_cluster_env(self, lat: Lattice, n_chains: int, seed: int,
-                              env_state=None, basis: int = 0):
+                              env_state=None, basis: int = 0,
+                              chain_offset: int = 0, sample: int = 0):
+        """hmps_init_cluster_env, or hmps_init_cluster_env_at when a chain
+        offset or a start sample is given."""
         self._lat = lat
         es = None
         if env_state is not None:
             env_state = np.ascontiguousarray(env_state, dtype=np.uint8)
             es = _ptr(env_state, C.c_uint8)
-        self._check(self.lib.hmps_init_cluster_env(
-            self.h, C.byref(lat.c), n_chains, C.c_uint64(seed), es, basis),
-            "hmps_init_cluster_env")
+        if chain_offset == 0 and sample == 0:
+            st = self.lib.hmps_init_cluster_env(
+                self.h, C.byref(lat.c), n_chains, C.c_uint64(seed), es, basis)
+        else:
+            st = self.lib.hmps_init_cluster_env_at(
+                self.h, C.byref(lat.c), n_chains, C.c_uint64(seed),
+                C.c_uint64(chain_offset), C.c_int64(sample), es, basis)
+        self._check(st, "hmps_init_cluster_env")
         self.n_chains = n_chains
         self.n_bonds = lat.n_bonds
         s = self.hmps_stats()
@@ -252,14 +277,33 @@ class Context:
         self._check(self.lib.hmps_evolve(self.h, beta, tau, chi_max, cutoff),
                     "hmps_evolve")
 
-    def hmps_measure(self):
+    def hmps_evolve_updates(self, beta, tau, chi_max, cutoff, first, count):
+        self._check(self.lib.hmps_evolve_updates(
+            self.h, beta, tau, chi_max, cutoff, int(first), int(count)),
+            "hmps_evolve_updates")
+
+    def hmps_last_spectrum(self, cap):
+        """(rank[n_chains], sigma[n_chains, cap]) of the last update."""
+        rank = np.zeros(self.n_chains, np.int32)
+        sig = np.zeros((self.n_chains, max(cap, 1)), np.float64)
+        self._check(self.lib.hmps_last_spectrum(
+            self.h, int(cap), _ptr(rank, C.c_int32), _ptr(sig, C.c_double)),
+            "hmps_last_spectrum")
+        return rank, sig[:, :cap]
+
+    def hmps_measure(self, what=MEASURE_ALL):
+        """Outputs whose bit is not in `what` come back as None."""
         B, nb = self.n_chains, self.n_bonds
         e, lw, qn = np.zeros(B), np.zeros(B), np.zeros(B)
         ss = np.zeros((B, max(nb, 1)))
         self._check(self.lib.hmps_measure(
-            self.h, _ptr(e, C.c_double), _ptr(ss, C.c_double),
-            _ptr(lw, C.c_double), _ptr(qn, C.c_double)), "hmps_measure")
-        return {"energy": e, "bond_ss": ss[:, :nb], "logw": lw, "qn": qn}
+            self.h, C.c_uint32(what), _ptr(e, C.c_double),
+            _ptr(ss, C.c_double), _ptr(lw, C.c_double),
+            _ptr(qn, C.c_double)), "hmps_measure")
+        return {"energy": e if what & MEASURE_ENERGY else None,
+                "bond_ss": ss[:, :nb] if what & MEASURE_BONDS else None,
+                "logw": lw if what & MEASURE_LOGW else None,
+                "qn": qn if what & MEASURE_QN else None}
 
     def hmps_collapse_resample(self, basis: int):
         out = np.zeros((self.n_chains, max(self.n_env, 1)), np.uint8)

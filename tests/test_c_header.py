@@ -2,7 +2,8 @@
 as C++, through its extern "C" guard), and a C program must link against
 libhmps.so and call the entry points that need no GPU: hmps_gate (checked
 against the closed form of its trace), hmps_workspace_bytes, hmps_schedule
-on a two-site chain, hmps_create's argument checks and hmps_last_error."""
+on a two-site chain, hmps_create's argument checks (including the
+declared but unbuilt split-bf16 precision) and hmps_last_error."""
 import os
 import shutil
 import subprocess
@@ -62,6 +63,12 @@ int main(void) {
     opt.max_bonds = 7;
     CHECK(hmps_create(&ctx, &opt) == HMPS_E_NOMEM);   /* no workspace */
     CHECK(ctx == NULL);
+    opt.precision = HMPS_PREC_MIXED_BF16X3;           /* declared, not built */
+    CHECK(hmps_create(&ctx, &opt) == HMPS_E_INVALID);
+    CHECK(ctx == NULL);
+    opt.precision = HMPS_PREC_FP64;
+    CHECK((HMPS_MEASURE_ENERGY | HMPS_MEASURE_BONDS | HMPS_MEASURE_LOGW |
+           HMPS_MEASURE_QN) == HMPS_MEASURE_ALL);
     CHECK(strcmp(hmps_last_error(NULL), "null context") == 0);
     hmps_destroy(NULL);
   }

@@ -19,13 +19,14 @@ pytestmark = pytest.mark.gpu
 E_REL = 1e-10
 SS_ABS = 1e-10
 LOGW_ABS = 1e-9
-# Where the chi_max cap cuts through a dense singular spectrum, the result
-# depends on the last bits of each SVD: perturbing every theta of the 2x8
-# ladder at beta=1 by 2e-16 (relative) moves the oracle's own energy by
-# 1.3e-9 relative, and the oracle differs from itself run to run at that
-# level with a different BLAS thread count.  Those runs are compared at
-# 100x that sensitivity.
-CAP_REL = 1e-7
+# Where the chi_max cap cuts through a dense singular spectrum, a free-
+# running sample depends on the last bits of each SVD: perturbing every
+# theta of the 2x8 ladder at beta=1 by 2e-16 (relative) moves the oracle's
+# own energy by 1.3e-9 relative, and the GPU and the oracle were measured
+# 2.4e-9 apart on MI355X.  Free-running samples there are compared at about
+# 4x that; single updates from a shared state are compared to 1e-12 in
+# test_gpu_teacher_forced.py.
+CAP_REL = 1e-8
 
 
 def gpu_ctx(L, W, chi_cap, n_chains, precision=hmps.PREC_FP64, J_leg=1.0,
