@@ -70,6 +70,8 @@ def parse(argv=None):
                     help="budget of the oracle baseline (0 disables it)")
     ap.add_argument("--no-extras", action="store_true",
                     help="gate workload: headline measurement only")
+    ap.add_argument("--beta", type=float, default=None,
+                    help="ladder workloads: override beta")
     args = ap.parse_args(argv)
     if args.steps < 1 or args.warmup < 0:
         ap.error("--steps >= 1 and --warmup >= 0")
@@ -400,6 +402,9 @@ def main_ladder(args):
     from paper_1910_09142_amd import hmps, workloads
 
     wl = getattr(workloads, args.workload.upper())
+    if args.beta is not None:
+        wl = dataclasses.replace(wl, beta=args.beta,
+                                 name=f"{wl.name}_beta{args.beta:g}")
     B = args.chains or wl.n_chains
     n, bonds, order, mask = workloads.ladder_arrays(wl.L, wl.J_leg,
                                                     wl.J_rung, wl.W)

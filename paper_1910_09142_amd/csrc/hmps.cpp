@@ -256,11 +256,16 @@ struct hmps_ctx {
   // products on vector lanes, so beyond a few thousand entries the blocked
   // MFMA rounds win even at a single chain (at most SMALL_LDS).
   size_t small_max = 2048;
+  // Householder QR preconditioning of the blocked rounds (HMPS_QR=0 turns
+  // it off, for measurements): on the chi = 256 gate workload it cuts the
+  // sweeps per update from about 30 to about 14.
+  int precond = 1;
   bool skip_theta = false;  // hmps_svd_probe: theta' is placed by the host
   // device buffers (carved from the workspace)
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
   int n_cap = 0, slots = 0;
   double *d_sites = nullptr, *d_TH = nullptr, *d_X = nullptr,
+         *d_Y = nullptr, *d_qrT = nullptr, *d_norm2 = nullptr,
          *d_sig2 = nullptr, *d_sig = nullptr, *d_fac = nullptr,
          *d_logw = nullptr, *d_disc = nullptr, *d_gates = nullptr,
          *d_envs = nullptr, *d_wsz = nullptr, *d_bscr = nullptr,
@@ -317,6 +322,8 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_chi = cv.take<int32_t>(B * (max_sites + 1));
   t->d_TH = cv.take<double>(B * th_stride);
   t->d_X = cv.take<double>(B * th_stride);
+  t->d_Y = cv.take<double>(B * th_stride);
+  t->d_qrT = cv.take<double>(B * QB * QB);
   t->d_sig2 = cv.take<double>(B * n_cap);
   t->d_sig = cv.take<double>(B * n_cap);
   t->d_perm = cv.take<int32_t>(B * n_cap);
@@ -327,6 +334,7 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_sweeps = cv.take<int32_t>(B);
   t->d_near = cv.take<int32_t>(B);
   t->d_fac = cv.take<double>(B);
+  t->d_norm2 = cv.take<double>(B);
   t->d_logw = cv.take<double>(B);
   t->d_disc = cv.take<double>(B);
   t->d_norm = cv.take<double>(B);
@@ -396,6 +404,8 @@ UpdScratch scratch_of(hmps_ctx *ctx) {
   UpdScratch s;
   s.TH = ctx->d_TH;
   s.X = ctx->d_X;
+  s.Y = ctx->d_Y;
+  s.qrT = ctx->d_qrT;
   s.th_stride = ctx->th_stride;
   s.sig2 = ctx->d_sig2;
   s.perm = ctx->d_perm;
@@ -403,6 +413,7 @@ UpdScratch scratch_of(hmps_ctx *ctx) {
   s.n_cap = ctx->n_cap;
   s.knew = ctx->d_knew;
   s.fac = ctx->d_fac;
+  s.norm2 = ctx->d_norm2;
   s.logw = ctx->d_logw;
   s.discarded = ctx->d_disc;
   s.rot_cur = ctx->d_rot;
@@ -452,8 +463,8 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   // each chain's SVD runs in LDS when its theta' has at most small_max
   // entries, else on the blocked rounds; the rounds' grid is sized by the
   // blocked chains alone
-  int n_small = 0, n_blocked = 0;
-  int max_nb = 2, max_vlen = 1, max_nvec = 1;
+  int n_small = 0, n_blocked = 0, n_qr = 0;
+  int max_nb = 2, max_vlen = 1, max_nvec = 1, max_qr_n = 0;
   double flops = 0.0, svd_flops = 0.0;
   for (int c = 0; c < ctx->B; ++c) {
     const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
@@ -471,11 +482,16 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
     const int nvec = 3 * std::min(row[k], row[k + 2]);
     max_vlen = std::max(max_vlen, 3 * std::max(row[k], row[k + 2]));
     max_nvec = std::max(max_nvec, nvec);
-    if ((size_t)(3 * row[k]) * (3 * row[k + 2]) <= ctx->small_max) {
+    const int vlen = 3 * std::max(row[k], row[k + 2]);
+    if (small_path(vlen, nvec, ctx->small_max)) {
       ++n_small;
     } else {
       ++n_blocked;
       max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
+      if (qr_path(vlen, nvec, ctx->small_max, ctx->precond)) {
+        ++n_qr;
+        max_qr_n = std::max(max_qr_n, nvec);
+      }
     }
   }
   const bool is_move = (op == OP_IDENT);
@@ -490,7 +506,10 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   u.cutoff = is_move ? 0.0 : cutoff;
   u.tol = ctx->opt.jacobi_tol;
   u.max_sweeps = ctx->opt.max_sweeps;
-  u.mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32;
+  // centre moves are exact gauge changes: always FP64
+  u.mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32 && !is_move;
+  u.precond = ctx->precond;
+  u.small_max = ctx->small_max;
   u.inner_sweeps = ctx->inner_sweeps;
   u.skip = ctx->skip;
   u.cross_inner = ctx->cross_inner;
@@ -500,6 +519,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   bool timed_svd = false;
   if (!ctx->skip_theta) {
     launch_theta(b, s, u, max_chiL, max_chiR, st);
+    if (u.is_gate) launch_theta_norm(b, s, u, st);
     LAUNCHCHK(ctx);
   }
   if (n_small > 0) {
@@ -508,6 +528,16 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   }
   if (n_blocked > 0) {
     launch_pad(b, s, u, st);
+    if (n_qr > 0) {
+      // theta' = Q R panel by panel, then R^T into the vector buffer
+      const int panels = (max_qr_n + QB - 1) / QB;
+      for (int p = 0; p < panels; ++p) {
+        launch_qr_panel(b, s, u, p, st);
+        launch_qr_update(b, s, u, p, panels - 1 - p, st);
+      }
+      launch_qr_to_vectors(b, s, u, max_qr_n, st);
+      LAUNCHCHK(ctx);
+    }
     bool converged = false;
     // Sweep s is enqueued before the host waits for the rotation count of
     // sweep s-1, so the read-back overlaps the next sweep; a sweep enqueued
@@ -536,9 +566,12 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       const int nvec = 3 * std::min(row[k], row[k + 2]);
       const int len = 3 * std::max(row[k], row[k + 2]);
       const int nb = n_blocks_even(nvec, JB);
-      const bool small = (size_t)(3 * row[k]) * (3 * row[k + 2]) <= ctx->small_max;
+      const bool small = small_path(len, nvec, ctx->small_max);
+      // the QR path rotates vectors of length nvec
+      const int vlen =
+          qr_path(len, nvec, ctx->small_max, ctx->precond) ? nvec : len;
       round_bytes[c] =
-          small ? 0.0 : (double)(nb - 1) * nb * JB * vector_stride(len) * 8.0;
+          small ? 0.0 : (double)(nb - 1) * nb * JB * vector_stride(vlen) * 8.0;
     }
     HIPCHK(hipEventRecord(ctx->svd_ev[0], st));
     hmps_status est = enqueue_sweep(0);
@@ -678,6 +711,7 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
   if (const char *e = std::getenv("HMPS_INNER")) ctx->inner_sweeps = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("HMPS_SKIP")) ctx->skip = std::min(1e-26, std::atof(e));
   if (const char *e = std::getenv("HMPS_CROSS")) ctx->cross_inner = e[0] == '1';
+  if (const char *e = std::getenv("HMPS_QR")) ctx->precond = e[0] != '0';
   if (const char *e = std::getenv("HMPS_SMALL_MAX"))
     ctx->small_max = std::min<size_t>(SMALL_LDS, std::strtoull(e, nullptr, 10));
   int current = -1;
@@ -1248,15 +1282,18 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
   HIPCHK(hipMemsetAsync(ctx->d_disc, 0, sizeof(double), s));
   HIPCHK(hipMemsetAsync(ctx->d_logw, 0, sizeof(double), s));
   // theta' in the vector layout of the SVD: the min(m, n) vectors of length
-  // max(m, n), stride vector_stride, column-major, zero padding rows
+  // max(m, n), stride vector_stride, column-major, zero padding rows, the
+  // vector index interleaved (3 bond index + s)
   const bool trans = n > m;
   const int len = trans ? n : m, nvec = trans ? m : n,
             ld = vector_stride(len);
   std::vector<double> h((size_t)ld * nvec, 0.0);
   for (int r = 0; r < m; ++r)
-    for (int c = 0; c < n; ++c)
-      h[trans ? (size_t)r * ld + c : (size_t)c * ld + r] =
-          theta[(size_t)r * n + c];
+    for (int c = 0; c < n; ++c) {
+      const size_t vr = 3 * (size_t)(r % chi_l) + r / chi_l;
+      const size_t vc = 3 * (size_t)(c % chi_r) + c / chi_r;
+      h[trans ? vr * ld + c : vc * ld + r] = theta[(size_t)r * n + c];
+    }
   HIPCHK(hipMemcpyAsync(ctx->d_TH, h.data(), sizeof(double) * h.size(),
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ctx->d_X, h.data(), sizeof(double) * h.size(),

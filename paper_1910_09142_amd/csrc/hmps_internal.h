@@ -32,6 +32,25 @@ constexpr double SIGMA_FLOOR = 1e-13;
 // Relative gap below which neighbouring singular values tie.
 constexpr double TIE_TOL = 1e-8;
 
+// Householder QR preconditioning of the blocked Jacobi SVD: panel width,
+// and the longest vectors whose 16-column panel fits in one workgroup's
+// LDS (QB * QR_MAX_L doubles).
+constexpr int QB = 16;
+constexpr int QR_MAX_L = 1152;
+
+// The per-chain path of an update's SVD: the in-LDS Jacobi for L * N <=
+// small_max, else the blocked rounds -- on R^T of theta' = Q R when the
+// preconditioning is on and the vectors fit a QR panel, else on theta'
+// itself.  The choice depends on the chain's own dimensions only, so a
+// chain takes the same path alone and in a batch.
+__host__ __device__ inline bool small_path(int L, int N, size_t small_max) {
+  return (size_t)L * N <= small_max;
+}
+__host__ __device__ inline bool qr_path(int L, int N, size_t small_max,
+                                        int precond) {
+  return precond && !small_path(L, N, small_max) && L <= QR_MAX_L;
+}
+
 // Device view of one batch of chains.  Site p of chain c is the row-major
 // tensor T[s][l][r] (s < 3, l < chi[c][p], r < chi[c][p+1]) stored at
 // sites + (c * nsites + p) * site_cap.
@@ -49,6 +68,8 @@ struct Batch {
 struct UpdScratch {
   double *TH;         // [B][th_stride]
   double *X;          // [B][th_stride]
+  double *Y;          // [B][th_stride] R^T of the QR path (the vectors)
+  double *qrT;        // [B][QB * QB] compact-WY factor of the last panel
   size_t th_stride;
   double *sig2;       // [B][n_cap] squared column norms after convergence
   int32_t *perm;      // [B][n_cap] kept columns, largest singular value first
@@ -56,6 +77,7 @@ struct UpdScratch {
   int n_cap;
   int32_t *knew;      // [B]
   double *fac;        // [B] 1/||kept||
+  double *norm2;      // [B] ||theta'||^2 of the update (FP64)
   double *logw;       // [B]
   double *discarded;  // [B] accumulated relative discarded weight
   int32_t *rot_cur;   // [B] rotations in the current sweep
@@ -77,6 +99,8 @@ struct UpdParams {
   int inner_sweeps;   // cap on the inner Jacobi sweeps of a block pair
   double skip;        // relative squared norm below which a vector is zero
   int cross_inner;    // inner rotations across the two blocks only (rounds > 0)
+  int precond;        // QR preconditioning of the blocked path
+  size_t small_max;   // largest L * N of the in-LDS SVD path
 };
 
 // ---- launchers (update.hip, jacobi.hip, observe.hip) -----------------------------------------
@@ -84,6 +108,8 @@ void launch_theta(const Batch &b, const UpdScratch &s, const UpdParams &u,
                   int max_chiL, int max_chiR, hipStream_t st);
 void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,
                 hipStream_t st);
+void launch_theta_norm(const Batch &b, const UpdScratch &s,
+                       const UpdParams &u, hipStream_t st);
 void launch_jacobi_small(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, hipStream_t st);
 void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
@@ -95,6 +121,14 @@ void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
                      hipStream_t st);
 void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
                       int max_L, int max_N, int max_k, hipStream_t st);
+// QR preconditioning (qr.hip): panel p of every QR-path chain, the update
+// of its trailing columns (max_tiles 16-column tiles), and R^T into Y.
+void launch_qr_panel(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                     int p, hipStream_t st);
+void launch_qr_update(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                      int p, int max_tiles, hipStream_t st);
+void launch_qr_to_vectors(const Batch &b, const UpdScratch &s,
+                          const UpdParams &u, int max_N, hipStream_t st);
 
 struct MeasureArgs {
   const int32_t *bond_p, *bond_q;  // [n_bonds] MPS positions, p < q

@@ -2,8 +2,9 @@
 // (the SVD that restores the MPS form after every two-site gate;
 // Chen & Stoudenmire, arXiv:1910.09142, Results section).
 //
-// The N vectors (columns of the L x N vector matrix X, stride ld = L
-// rounded up to 16, column-major) are split into NB (even) blocks of
+// The N vectors (columns of the L x N vector matrix X -- or, on the QR
+// path, of the N x N matrix R^T in Y -- stride ld = L rounded up to 16,
+// column-major) are split into NB (even) blocks of
 // JB = 16 vectors.  A sweep has NB-1 rounds; in a round the blocks are
 // paired by the circle method and one workgroup of eight wavefronts handles
 // one block pair of one chain:
@@ -150,13 +151,16 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   if (s.done[c]) return;
   const int32_t *chi = chi_row(b, c);
   const int m = 3 * chi[u.k], n = 3 * chi[u.k + 2];
-  const int L = m > n ? m : n, N = m > n ? n : m;
+  const int Lt = m > n ? m : n, N = m > n ? n : m;
+  // the QR path rotates the N columns of R^T (length N) in Y
+  const bool qr = qr_path(Lt, N, u.small_max, u.precond);
+  const int L = qr ? N : Lt;
   const int NB = n_blocks_even(N, JB);
   if (r >= NB - 1 || pi >= NB / 2) return;
   const int ld = vec_ld(L);
   int bi, bj;
   rr_pair(r, pi, NB, bi, bj);
-  double *X = s.X + (size_t)c * s.th_stride;
+  double *X = (qr ? s.Y : s.X) + (size_t)c * s.th_stride;
   auto colidx = [&](int t) { return t < JB ? bi * JB + t : bj * JB + t - JB; };
 
   // G is symmetric and only its upper triangle (i <= j) is kept.  It is

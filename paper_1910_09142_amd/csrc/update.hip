@@ -16,7 +16,11 @@
 // min(m, n) vectors of length L = max(m, n): the columns of theta' when
 // n <= m, its rows when n > m ("transposed").  More vectors than their
 // length could never all become orthogonal.  X and TH hold the L x N
-// vector matrix column-major (vector j at offset j*L).
+// vector matrix column-major (vector j at offset j*L).  Vectors are
+// ordered bond index first, 3 c + s2 (or 3 a + s1): the bond's basis
+// comes from the previous truncations sorted by Schmidt value, so this
+// order grades the vectors by norm, which is what the unpivoted QR of the
+// preconditioned path needs.  Elements along a vector keep s-major order.
 #include "device_common.h"
 #include "small_path.h"
 
@@ -27,7 +31,22 @@ using namespace dev;
 struct Dims {
   int chiL, chiM, chiR, m, n, L, N, trans;
   int ld;  // vector stride in X and TH: L rounded up to a multiple of 16
+  // the side of theta' whose index is the vector index (rows when trans,
+  // columns otherwise) is interleaved, 3 (bond index) + s
+  int il_rows, il_cols;
 };
+
+// A chain on the QR path rotates R^T (N vectors of length N, in Y): its
+// converged vectors lie on the other side of theta' than those of the
+// plain path (columns of M^T, see qr.hip), so the write-back swaps sides.
+__device__ __forceinline__ bool on_qr(const Dims &d, const UpdParams &u) {
+  return qr_path(d.L, d.N, u.small_max, u.precond);
+}
+__device__ __forceinline__ Dims vector_side(const Dims &d, bool qr) {
+  Dims e = d;
+  if (qr) e.trans = !d.trans;
+  return e;
+}
 
 __device__ __forceinline__ Dims dims_of(const Batch &b, int c, int k) {
   const int32_t *chi = chi_row(b, c);
@@ -41,6 +60,8 @@ __device__ __forceinline__ Dims dims_of(const Batch &b, int c, int k) {
   d.L = d.trans ? d.n : d.m;
   d.N = d.trans ? d.m : d.n;
   d.ld = vec_ld(d.L);
+  d.il_rows = d.trans;
+  d.il_cols = !d.trans;
   return d;
 }
 
@@ -159,19 +180,43 @@ __global__ void __launch_bounds__(NT) k_theta(Batch b, UpdScratch s, UpdParams u
         T v = 0;
 #pragma unroll
         for (int t = 0; t < 9; ++t) v += G[(s1 * 3 + s2) * 9 + t] * th[t];
-        const size_t row = (size_t)s1 * chiL + ai, col = (size_t)s2 * chiR + ci;
-        const size_t off = d.trans ? row * d.ld + col : col * d.ld + row;
+        // the vector index interleaved (3 bond + s), the element index not
+        const size_t off =
+            d.trans ? (size_t)(3 * ai + s1) * d.ld + (size_t)s2 * chiR + ci
+                    : (size_t)(3 * ci + s2) * d.ld + (size_t)s1 * chiL + ai;
         TH[off] = (double)v;
         X[off] = (double)v;
       }
   }
 }
 
-// Zero what the blocked Jacobi path reads beyond theta': the padding rows
-// L..ld-1 of every vector and the padding vectors N..npad-1.
+// ||theta'||^2 of every chain in FP64, summed over theta' as stored (before
+// any rotation) in a fixed order: the gate's log-weight increment ln
+// ||theta'||^2 (the sampling weight is the product of the squared norms of
+// the evolution, Hybrid METTS-Ancilla subsection).
+__global__ void __launch_bounds__(NT) k_theta_norm(Batch b, UpdScratch s,
+                                                   UpdParams u) {
+  const int c = blockIdx.x;
+  const Dims d = dims_of(b, c, u.k);
+  const double *TH = s.TH + (size_t)c * s.th_stride;
+  __shared__ double red[NT / 64];
+  double v = 0.0;
+  for (int q = 0; q < d.N; ++q)
+    for (int l = threadIdx.x; l < d.L; l += NT) {
+      const double x = TH[(size_t)q * d.ld + l];
+      v = fma(x, x, v);
+    }
+  v = wg_sum(v, red);
+  if (threadIdx.x == 0) s.norm2[c] = v;
+}
+
+// Zero what the blocked paths read beyond theta': the padding rows
+// L..ld-1 of every vector and, for the plain rounds, the padding vectors
+// N..npad-1 (the QR path writes its own vectors, padding included).
 __global__ void __launch_bounds__(NT) k_pad(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.y;
   const Dims d = dims_of(b, c, u.k);
+  const bool qr = on_qr(d, u);
   const int npad = n_blocks_even(d.N, JB) * JB;
   double *X = s.X + (size_t)c * s.th_stride;
   const int tail = d.ld - d.L;
@@ -179,6 +224,7 @@ __global__ void __launch_bounds__(NT) k_pad(Batch b, UpdScratch s, UpdParams u) 
     for (int i = blockIdx.x * NT + threadIdx.x; i < d.N * tail;
          i += gridDim.x * NT)
       X[(size_t)(i / tail) * d.ld + d.L + i % tail] = 0.0;
+  if (qr) return;
   const size_t cnt = (size_t)(npad - d.N) * d.ld;
   double *P = X + (size_t)d.N * d.ld;
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < cnt;
@@ -285,8 +331,8 @@ __global__ void k_mark_small_done(Batch b, UpdScratch s, UpdParams u,
 //   the whole run is kept (the discarded weight stays within the target),
 //   unless that passes chi_max; then, as when the cap sets the cut, the
 //   whole run is dropped unless it starts at sigma_0.
-//   ln sum sigma^2 = ln ||theta'||^2 goes into logw
-//   for a gate (the sampling weight is the product of these norms).
+//   ln ||theta'||^2 (k_theta_norm) goes into logw for a gate (the sampling
+//   weight is the product of these norms).
 // =====================================================================
 __global__ void __launch_bounds__(NT)
     k_truncate(Batch b, UpdScratch s, UpdParams u) {
@@ -365,7 +411,7 @@ __global__ void __launch_bounds__(NT)
     for (int j = k - 1; j >= 0; --j) kept += key[j] * key[j];
     if (!(total > 0.0) || !isfinite(total) || !(kept > 0.0)) s.err[c] = 2;
     s.fac[c] = 1.0 / sqrt(kept);
-    if (u.is_gate) s.logw[c] += log(total);
+    if (u.is_gate) s.logw[c] += log(s.norm2[c]);
     s.discarded[c] += (total - kept) / total;
     s.knew[c] = k;
     kk_s = k;
@@ -391,32 +437,40 @@ __global__ void __launch_bounds__(NT)
 // (columns (s2,c)).  With fac = 1/||kept||, right = 1 gives T_k = U,
 // T_{k+1} = fac Sigma V^T; right = 0 gives T_k = fac U Sigma, T_{k+1} = V^T.
 // =====================================================================
+// Element i of a row-side factor (site k, T[s1][a][j]) and element q of a
+// column-side factor (site k+1, T[s2][j][c]); il: the index is interleaved.
+__device__ __forceinline__ void store_row(const Batch &b, int c, int k,
+                                          const Dims &d, int knew, int i,
+                                          int j, double v) {
+  const int s1 = d.il_rows ? i % 3 : i / d.chiL;
+  const int a = d.il_rows ? i / 3 : i - s1 * d.chiL;
+  site_ptr(b, c, k)[(size_t)s1 * d.chiL * knew + (size_t)a * knew + j] = v;
+}
+__device__ __forceinline__ void store_col(const Batch &b, int c, int k,
+                                          const Dims &d, int knew, int q,
+                                          int j, double v) {
+  const int s2 = d.il_cols ? q % 3 : q / d.chiR;
+  const int cc = d.il_cols ? q / 3 : q - s2 * d.chiR;
+  site_ptr(b, c, k + 1)[(size_t)s2 * knew * d.chiR + (size_t)j * d.chiR + cc] =
+      v;
+}
 __device__ __forceinline__ void store_vector_side(const Batch &b, int c,
                                                   int k, const Dims &d,
                                                   int knew, int l, int j,
                                                   double v) {
-  if (!d.trans) {
-    const int s1 = l / d.chiL, a = l - s1 * d.chiL;
-    site_ptr(b, c, k)[(size_t)s1 * d.chiL * knew + (size_t)a * knew + j] = v;
-  } else {
-    const int s2 = l / d.chiR, cc = l - s2 * d.chiR;
-    site_ptr(b, c, k + 1)[(size_t)s2 * knew * d.chiR + (size_t)j * d.chiR +
-                          cc] = v;
-  }
+  if (!d.trans)
+    store_row(b, c, k, d, knew, l, j, v);
+  else
+    store_col(b, c, k, d, knew, l, j, v);
 }
-
 __device__ __forceinline__ void store_other_side(const Batch &b, int c,
                                                  int k, const Dims &d,
                                                  int knew, int q, int j,
                                                  double v) {
-  if (!d.trans) {
-    const int s2 = q / d.chiR, cc = q - s2 * d.chiR;
-    site_ptr(b, c, k + 1)[(size_t)s2 * knew * d.chiR + (size_t)j * d.chiR +
-                          cc] = v;
-  } else {
-    const int s1 = q / d.chiL, a = q - s1 * d.chiL;
-    site_ptr(b, c, k)[(size_t)s1 * d.chiL * knew + (size_t)a * knew + j] = v;
-  }
+  if (!d.trans)
+    store_col(b, c, k, d, knew, q, j, v);
+  else
+    store_row(b, c, k, d, knew, q, j, v);
 }
 
 // Dims as they were before the truncation: chi[k+1] now holds knew, but
@@ -425,51 +479,203 @@ __global__ void __launch_bounds__(NT)
     k_writeback_direct(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.y;
   const Dims d = dims_of(b, c, u.k);
+  const bool qr = on_qr(d, u);
+  const Dims e = vector_side(d, qr);
+  const int vlen = qr ? d.N : d.L, vld = qr ? vec_ld(d.N) : d.ld;
   const int k = s.knew[c];
   const int t = blockIdx.x * NT + threadIdx.x;
-  if (t >= d.L * k) return;
-  const int l = t % d.L, j = t / d.L;
+  if (t >= vlen * k) return;
+  const int l = t % vlen, j = t / vlen;
   const int col = s.perm[(size_t)c * s.n_cap + j];
-  const bool vec_center = (d.trans != 0) == (u.right != 0);
+  const bool vec_center = (e.trans != 0) == (u.right != 0);
   const double f =
       vec_center ? s.fac[c] : 1.0 / s.sig[(size_t)c * s.n_cap + j];
-  const double v = s.X[(size_t)c * s.th_stride + (size_t)col * d.ld + l] * f;
-  store_vector_side(b, c, u.k, d, k, l, j, v);
+  const double *V = (qr ? s.Y : s.X) + (size_t)c * s.th_stride;
+  store_vector_side(b, c, u.k, e, k, l, j, V[(size_t)col * vld + l] * f);
 }
 
+// The other side.  With X_j = sigma_j x_j the converged vectors (x_j unit
+// singular vectors on the vector side) and M the vector matrix of the path
+// (theta' or its transpose as stored in TH), the unit singular vectors on
+// the other side are p_j = op(M) X_j / sigma_j^2: op(M) = M^T on the plain
+// path (X_j of length L, p_j of length N), op(M) = M on the QR path (X_j
+// = Y_j of length N, p_j of length L).  The projections are orthonormal
+// only to about eps sigma_0 / sigma_j, so they are corrected before they
+// are stored, to first order in E (G = P^T P = I + E) along the Cholesky
+// factor of G taken in the order of decreasing sigma: p_j <- p_j (1 - E_jj
+// / 2) - sum_{i<j} p_i E_ij.  Column j is made orthonormal against the
+// columns of larger singular value and never feeds back into them, so the
+// large rounding error of a tiny-sigma projection stays in that column
+// (where the state weighs it by sigma_j).
+//   k_other_project  P into a free buffer (Y on the plain path, X on the QR
+//                    path), column j at j * ldP, zero rows P_len .. ldP-1
+//   k_other_gram     G = P^T P into TH (free once P is formed), row-major
+//                    with stride round16(k), zero beyond k
+//   k_other_store    P (3 I - G) / 2, scaled, into the site tensor
+// All three on the FP64 matrix cores, one 16 x 16 tile per wavefront.
+struct Other {
+  int qr, len, ldP, k, ldG;
+  double *P;
+  double *G;
+};
+
+__device__ __forceinline__ Other other_of(const Dims &d, const UpdParams &u,
+                                          const UpdScratch &s, int c) {
+  Other o;
+  o.qr = on_qr(d, u);
+  o.len = o.qr ? d.L : d.N;
+  o.ldP = vec_ld(o.len);
+  o.k = s.knew[c];
+  o.ldG = (o.k + 15) & ~15;
+  o.P = (o.qr ? s.X : s.Y) + (size_t)c * s.th_stride;
+  o.G = s.TH + (size_t)c * s.th_stride;
+  return o;
+}
+
+// P tile (rows r0 .. r0+15, vectors j0 .. j0+15) per wavefront.
 __global__ void __launch_bounds__(NT)
-    k_writeback_gemm(Batch b, UpdScratch s, UpdParams u) {
+    k_other_project(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.z;
   const Dims d = dims_of(b, c, u.k);
-  const int k = s.knew[c];
-  const int q0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
-  if (q0 >= d.N || j0 >= k) return;
-  const int L = d.L;
-  const double *X = s.X + (size_t)c * s.th_stride;
-  const double *TH = s.TH + (size_t)c * s.th_stride;
+  const Other o = other_of(d, u, s, c);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = blockIdx.x * 64 + 16 * w, j0 = blockIdx.y * 16;
+  if (r0 >= o.ldP || j0 >= o.k) return;
+  const double *M = s.TH + (size_t)c * s.th_stride;
   const int32_t *perm = s.perm + (size_t)c * s.n_cap;
-  __shared__ double As[16][17];
-  __shared__ double Bs[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int pj = (j0 + ty < k) ? perm[j0 + ty] : -1;
-  double acc = 0.0;
-  for (int i0 = 0; i0 < L; i0 += 16) {
-    As[ty][tx] =
-        (pj >= 0 && i0 + tx < L) ? X[(size_t)pj * d.ld + i0 + tx] : 0.0;
-    Bs[tx][ty] = (q0 + ty < d.N && i0 + tx < L)
-                     ? TH[(size_t)(q0 + ty) * d.ld + i0 + tx]
-                     : 0.0;
-    __syncthreads();
+  const bool jok = j0 + li < o.k;
+  const int pj = perm[jok ? j0 + li : j0];
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  if (o.qr) {
+    // D[l][j] = sum_q M[l][q] Y[q][pj]: lane (li, lk) takes row r0 + li of
+    // M (single coalesced loads per q) and q = q0 + 4 lk .. + 3 of Y_pj
+    const int ldN = vec_ld(d.N);
+    const double *yv = s.Y + (size_t)c * s.th_stride + (size_t)pj * ldN;
+    const bool lok = r0 + li < d.L;
+    const double *mrow = M + (lok ? r0 + li : 0);
+    for (int q0 = 0; q0 < d.N; q0 += 16) {
+      const int qb = q0 + 4 * lk;
+      const v4d yq = *reinterpret_cast<const v4d *>(yv + qb);
+      double mv[4];
 #pragma unroll
-    for (int ii = 0; ii < 16; ++ii) acc += As[ty][ii] * Bs[ii][tx];
-    __syncthreads();
+      for (int q = 0; q < 4; ++q) {
+        const int qq = min(qb + q, d.N - 1);
+        const double x = mrow[(size_t)qq * d.ld];
+        mv[q] = (lok && qb + q < d.N) ? x : 0.0;
+      }
+      acc = mfma_f64(mv[0], jok ? yq.x : 0.0, acc);
+      acc = mfma_f64(mv[1], jok ? yq.y : 0.0, acc);
+      acc = mfma_f64(mv[2], jok ? yq.z : 0.0, acc);
+      acc = mfma_f64(mv[3], jok ? yq.w : 0.0, acc);
+    }
+  } else {
+    // D[q][j] = sum_l M[l][q] X[l][pj]: both operands as aligned 32-byte
+    // loads of four consecutive l (rows L .. ld-1 of X are zero)
+    const double *xv = s.X + (size_t)c * s.th_stride + (size_t)pj * d.ld;
+    const bool qok = r0 + li < d.N;
+    const double *mcol = M + (size_t)(qok ? r0 + li : 0) * d.ld;
+    for (int l0 = 0; l0 < d.L; l0 += 16) {
+      const int lb = l0 + 4 * lk;
+      const v4d xq = *reinterpret_cast<const v4d *>(xv + lb);
+      const v4d mq = *reinterpret_cast<const v4d *>(mcol + lb);
+      // rows L .. ld-1 of TH are not written by the update: mask them
+      const bool l0ok = lb < d.L, l1ok = lb + 1 < d.L, l2ok = lb + 2 < d.L,
+                 l3ok = lb + 3 < d.L;
+      acc = mfma_f64(qok && l0ok ? mq.x : 0.0, jok ? xq.x : 0.0, acc);
+      acc = mfma_f64(qok && l1ok ? mq.y : 0.0, jok ? xq.y : 0.0, acc);
+      acc = mfma_f64(qok && l2ok ? mq.z : 0.0, jok ? xq.z : 0.0, acc);
+      acc = mfma_f64(qok && l3ok ? mq.w : 0.0, jok ? xq.w : 0.0, acc);
+    }
   }
-  const int j = j0 + ty, q = q0 + tx;
-  if (j < k && q < d.N) {
-    const double sg = s.sig[(size_t)c * s.n_cap + j];
-    const bool vec_center = (d.trans != 0) == (u.right != 0);
-    const double f = vec_center ? 1.0 / (sg * sg) : s.fac[c] / sg;
-    store_other_side(b, c, u.k, d, k, q, j, f * acc);
+  if (!jok) return;
+  const double sg = s.sig[(size_t)c * s.n_cap + j0 + li];
+  const double inv = 1.0 / (sg * sg);
+  // D[i][j] (row r0 + i, vector j0 + j) in lane j + 16 (i % 4), element i/4
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + lk + 4 * q;
+    o.P[(size_t)(j0 + li) * o.ldP + r] = r < o.len ? acc[q] * inv : 0.0;
+  }
+}
+
+// G tile (j1 .. j1+15, j2 .. j2+15) per wavefront; contraction over the
+// rows of P (zero beyond len) as aligned 32-byte loads.
+__global__ void __launch_bounds__(NT)
+    k_other_gram(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.z;
+  const Dims d = dims_of(b, c, u.k);
+  const Other o = other_of(d, u, s, c);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int j1 = blockIdx.x * 64 + 16 * w, j2 = blockIdx.y * 16;
+  if (j1 >= o.ldG || j2 >= o.ldG) return;
+  const bool aok = j1 + li < o.k, bok = j2 + li < o.k;
+  const double *pa = o.P + (size_t)(aok ? j1 + li : 0) * o.ldP;
+  const double *pb = o.P + (size_t)(bok ? j2 + li : 0) * o.ldP;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 0; r0 < o.ldP; r0 += 16) {
+    const int rb = r0 + 4 * lk;
+    const v4d a = *reinterpret_cast<const v4d *>(pa + rb);
+    const v4d bb = *reinterpret_cast<const v4d *>(pb + rb);
+    acc = mfma_f64(aok ? a.x : 0.0, bok ? bb.x : 0.0, acc);
+    acc = mfma_f64(aok ? a.y : 0.0, bok ? bb.y : 0.0, acc);
+    acc = mfma_f64(aok ? a.z : 0.0, bok ? bb.z : 0.0, acc);
+    acc = mfma_f64(aok ? a.w : 0.0, bok ? bb.w : 0.0, acc);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    o.G[(size_t)(j1 + lk + 4 * q) * o.ldG + j2 + li] = acc[q];
+}
+
+// out[r][j] = P[r][j] (3 - G[j][j]) / 2 - sum_{i<j} P[r][i] G[i][j], times
+// 1 for an isometry or fac sigma_j for the centre; G is symmetric, so lane
+// (li, lk) loads G[j0 + li][i0 + 4 lk .. + 3] as one aligned 32-byte load.
+__global__ void __launch_bounds__(NT)
+    k_other_store(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.z;
+  const Dims d = dims_of(b, c, u.k);
+  const Other o = other_of(d, u, s, c);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int r0 = blockIdx.x * 64 + 16 * w, j0 = blockIdx.y * 16;
+  if (r0 >= o.len || j0 >= o.k) return;
+  const bool jok = j0 + li < o.k;
+  const double *grow = o.G + (size_t)(jok ? j0 + li : 0) * o.ldG;
+  const double *prow = o.P + r0 + li;  // row r0 + li of every column
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int i0 = 0; i0 < o.ldG; i0 += 16) {
+    const int ib = i0 + 4 * lk;
+    const v4d g = *reinterpret_cast<const v4d *>(grow + ib);
+    double pv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int ii = min(ib + q, o.k - 1);
+      const double x = prow[(size_t)ii * o.ldP];
+      pv[q] = ib + q < o.k ? x : 0.0;
+    }
+    // only i < j (the strictly upper part of E)
+    const int jj = j0 + li;
+    acc = mfma_f64(pv[0], jok && ib < jj ? g.x : 0.0, acc);
+    acc = mfma_f64(pv[1], jok && ib + 1 < jj ? g.y : 0.0, acc);
+    acc = mfma_f64(pv[2], jok && ib + 2 < jj ? g.z : 0.0, acc);
+    acc = mfma_f64(pv[3], jok && ib + 3 < jj ? g.w : 0.0, acc);
+  }
+  if (!jok) return;
+  const int j = j0 + li;
+  const double gjj = o.G[(size_t)j * o.ldG + j];
+  const Dims e = vector_side(d, o.qr);
+  const bool vec_center = (e.trans != 0) == (u.right != 0);
+  const double f =
+      vec_center ? 1.0 : s.fac[c] * s.sig[(size_t)c * s.n_cap + j];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + lk + 4 * q;
+    if (r < o.len) {
+      const double pr = o.P[(size_t)j * o.ldP + r];
+      store_other_side(b, c, u.k, e, o.k, r, j,
+                       f * (pr * (1.5 - 0.5 * gjj) - acc[q]));
+    }
   }
 }
 
@@ -483,6 +689,11 @@ void launch_theta(const Batch &b, const UpdScratch &s, const UpdParams &u,
     hipLaunchKernelGGL(k_theta<float>, grid, dim3(NT), 0, st, b, s, u);
   else
     hipLaunchKernelGGL(k_theta<double>, grid, dim3(NT), 0, st, b, s, u);
+}
+
+void launch_theta_norm(const Batch &b, const UpdScratch &s,
+                       const UpdParams &u, hipStream_t st) {
+  hipLaunchKernelGGL(k_theta_norm, dim3(b.B), dim3(NT), 0, st, b, s, u);
 }
 
 void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,
@@ -516,11 +727,18 @@ void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
 
 void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
                       int max_L, int max_N, int max_k, hipStream_t st) {
+  (void)max_N;
   const int nd = (max_L * max_k + NT - 1) / NT;
   hipLaunchKernelGGL(k_writeback_direct, dim3(nd, b.B), dim3(NT), 0, st, b, s,
                      u);
-  dim3 g2((max_N + 15) / 16, (max_k + 15) / 16, b.B);
-  hipLaunchKernelGGL(k_writeback_gemm, g2, dim3(NT), 0, st, b, s, u);
+  // the other side has at most max_L rows (L on the QR path, N <= L on
+  // the plain path), padded to 16
+  const int rows = (max_L + 15) & ~15, kk = (max_k + 15) & ~15;
+  dim3 gp((rows + 63) / 64, kk / 16, b.B);
+  hipLaunchKernelGGL(k_other_project, gp, dim3(NT), 0, st, b, s, u);
+  dim3 gg((kk + 63) / 64, kk / 16, b.B);
+  hipLaunchKernelGGL(k_other_gram, gg, dim3(NT), 0, st, b, s, u);
+  hipLaunchKernelGGL(k_other_store, gp, dim3(NT), 0, st, b, s, u);
 }
 
 }  // namespace hmps

@@ -11,15 +11,13 @@ and a ragged tail).
 
 Compared (gauge-invariant, FP64): bond dimensions exactly; the two-site
 state T_0 T_1 after each application to 1e-10 relative (Frobenius), the
-log-weights to 1e-10 absolute, i.e. the weights exp(log w) to 1e-10
-relative (the Jacobi rotations preserve ||theta'||^2 only to rounding per
-rotation: 1.8e-12 after the ~46k rotations per vector of a 1536 x 1536
-theta'); the factor left of the centre
-left-orthonormal, the one right of it right-orthonormal.  One of the two
-factors is the normalised Jacobi vectors, the other the projections
-theta'^T u_j / sigma_j, whose orthonormality error grows like
-eps sqrt(len) sigma_0 / sigma_k (len = max(m, n)); the bound is
-max(1e-12, 2 eps sqrt(len) sigma_0 / sigma_k) over the kept spectrum.
+log-weight of the first application to 1e-12 absolute (ln ||theta'||^2 is
+summed from theta' itself in FP64, before the SVD; later applications
+start from states that already differ at the 1e-13 level, so they are held
+at 1e-10); the factor left of the centre left-orthonormal and the one
+right of it right-orthonormal, both to 1e-12 (one factor is the
+normalised Jacobi vectors, the other their projections through theta',
+corrected to orthonormality).
 Mixed mode (FP32 theta and gate): the state to 5e-6 relative, log-weights
 to 1e-6.
 """
@@ -54,7 +52,7 @@ def oracle_state(psi):
 
 def run_case(chi_l, chi_m, chi_r, n_chains, chi_max, cutoff, n_apply,
              precision=hmps.PREC_FP64, J=1.0, x=0.025, seed=3,
-             tol_state=1e-10, tol_logw=1e-10):
+             tol_state=1e-10, tol_logw=1e-12):
     print(f"case: bond {chi_l}x{chi_m}x{chi_r}, {n_chains} chains, "
           f"chi_max {chi_max}, precision {precision}", flush=True)
     center, right = workloads.bond_tensors(seed, n_chains, chi_l, chi_m,
@@ -80,7 +78,8 @@ def run_case(chi_l, chi_m, chi_r, n_chains, chi_max, cutoff, n_apply,
             got = state(T0, T1)
             err = np.linalg.norm(got - want) / np.linalg.norm(want)
             assert err < tol_state, (it, c, err)
-            assert abs(logw[c] - psis[c].logw) < tol_logw, (it, c)
+            tl = tol_logw if it == 0 else max(tol_logw, 1e-10)
+            assert abs(logw[c] - psis[c].logw) < tl, (it, c)
             k = T0.shape[2]
             if go_right:   # T0 left-orthonormal: rows (a, s)
                 U = T0.transpose(1, 0, 2).reshape(-1, k)
@@ -88,9 +87,7 @@ def run_case(chi_l, chi_m, chi_r, n_chains, chi_max, cutoff, n_apply,
             else:          # T1 right-orthonormal: columns (s, c)
                 V = T1.transpose(1, 0, 2).reshape(k, -1)
                 iso = V @ V.T
-            length = 3 * max(chi_l, chi_r)
-            tol_iso = max(1e-12, 2 * EPS * np.sqrt(length) * S[0] / S[-1])
-            assert np.abs(iso - np.eye(k)).max() < tol_iso, (it, c)
+            assert np.abs(iso - np.eye(k)).max() < 1e-12, (it, c)
     ctx.hmps_destroy()
 
 

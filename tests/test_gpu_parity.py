@@ -24,9 +24,16 @@ LOGW_ABS = 1e-9
 # theta of the 2x8 ladder at beta=1 by 2e-16 (relative) moves the oracle's
 # own energy by 1.3e-9 relative, and the GPU and the oracle were measured
 # 2.4e-9 apart on MI355X.  Free-running samples there are compared at about
-# 4x that; single updates from a shared state are compared to 1e-12 in
-# test_gpu_teacher_forced.py.
+# 4x that, and the per-bond correlators (measured 8.1e-8 apart: the bond
+# errors partly cancel in the energy) at 3x theirs; single updates from a
+# shared state are compared to 1e-12 in test_gpu_teacher_forced.py.
 CAP_REL = 1e-8
+# <Q> is conserved exactly; where the cap cuts between near-degenerate
+# Schmidt values of different Q sectors the oracle's LAPACK vectors mix
+# them slightly (its <Q> was measured 1.8e-9 from the exact integer, the
+# GPU's 7e-13)
+CAP = {"e_rel": CAP_REL, "ss": 2.5e-7, "logw": 1e-6, "qn": 6e-9}
+TIGHT = {"e_rel": E_REL, "ss": SS_ABS, "logw": LOGW_ABS, "qn": 1e-10}
 
 
 def gpu_ctx(L, W, chi_cap, n_chains, precision=hmps.PREC_FP64, J_leg=1.0,
@@ -53,18 +60,21 @@ def run_gpu_chain(L, W, beta, tau, chi, cut, n_samples, seed, J_rung=1.0,
     return out
 
 
-def compare_sample(g, r, c=0, rel=E_REL):
+def compare_sample(g, r, c=0, tol=None):
+    tol = tol or TIGHT
     e = r["energy"]
-    print(f"  E gpu={g['energy'][c]:.15f} oracle={e:.15f}", flush=True)
-    scale = rel / E_REL
-    assert abs(g["energy"][c] - e) <= rel * abs(e)
-    assert np.abs(g["bond_ss"][c] - np.array(r["bond_ss"])).max() <= SS_ABS * scale
-    assert abs(g["logw"][c] - r["logw"]) <= LOGW_ABS * scale
-    assert abs(g["qn"][c] - r["qn"]) <= 1e-10 * scale
+    dss = np.abs(g["bond_ss"][c] - np.array(r["bond_ss"])).max()
+    print(f"  E gpu={g['energy'][c]:.15f} oracle={e:.15f} "
+          f"dE/E={abs(g['energy'][c] - e) / abs(e):.2e} dSS={dss:.2e} "
+          f"dlogw={abs(g['logw'][c] - r['logw']):.2e}", flush=True)
+    assert abs(g["energy"][c] - e) <= tol["e_rel"] * abs(e)
+    assert dss <= tol["ss"]
+    assert abs(g["logw"][c] - r["logw"]) <= tol["logw"]
+    assert abs(g["qn"][c] - r["qn"]) <= tol["qn"]
     if r["basis"] == 0:
         # <Q> is the environment's total S^z exactly (U(1) conservation)
         me = sum(1 - v for v in r["env"].values())
-        assert abs(g["qn"][c] - me) <= 1e-10 * scale
+        assert abs(g["qn"][c] - me) <= tol["qn"]
 
 
 def test_c1_chain_parity():
@@ -132,9 +142,9 @@ def test_batch_is_bit_identical_to_single_chains():
         assert g1["logw"][0] == gb["logw"][c]
 
 
-@pytest.mark.parametrize("beta,n_samples,rel", [(0.5, 2, E_REL),
-                                                (1.0, 1, CAP_REL)])
-def test_c2_ladder_parity(beta, n_samples, rel):
+@pytest.mark.parametrize("beta,n_samples,tol", [(0.5, 2, TIGHT),
+                                                (1.0, 1, CAP)])
+def test_c2_ladder_parity(beta, n_samples, tol):
     # 2x8 ladder, W=2, tau=0.05, chi_max=128, cutoff 1e-12 (large-matrix
     # Jacobi path: theta reaches 384 x 384)
     L, W, tau, chi, cut = 8, 2, 0.05, 128, 1e-12
@@ -145,7 +155,7 @@ def test_c2_ladder_parity(beta, n_samples, rel):
     lay = model.layout(model.ladder(L, 1.0, 1.0, W=W))
     for n in range(n_samples):
         assert ref[n]["stats"].min_margin > 1e-8
-        compare_sample(gpu[n], ref[n], rel=rel)
+        compare_sample(gpu[n], ref[n], tol=tol)
         want = [ref[n]["outcomes"][p] for p in lay.env_positions]
         assert list(gpu[n]["outcomes"][0]) == want or ref[n]["near"] > 0
 

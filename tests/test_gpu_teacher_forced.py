@@ -18,7 +18,8 @@ from the GPU's own state (read back through hmps_read_site):
 3. at the end the oracle measures the GPU's state (Markov chain step 3).
 
 Tolerances (FP64): spectra 1e-12 relative to sigma_0, log-weight
-increments 1e-12, measurement of one state 1e-10.  Mixed precision (FP32
+increments 1e-12 (beyond the rounding of the accumulated sum), the
+free-running window 1e-10, measurement of one state 1e-10.  Mixed precision (FP32
 theta and gate): the per-observable bounds in MIXED below, three times the
 largest deviations measured on the 2x16 ladder at chi_max = 256.
 """
@@ -34,9 +35,11 @@ pytestmark = pytest.mark.gpu
 
 FP64 = {"spectrum": 1e-12, "logw": 1e-12, "theta": 1e-9,
         "free_energy_rel": 1e-10, "free_ss": 1e-10}
-# mixed precision, frozen at 3x the largest deviation measured on MI355X
-MIXED = {"spectrum": 1e-6, "logw": 1e-6, "theta": 1e-5,
-         "free_energy_rel": 1e-6, "free_ss": 5e-6}
+# mixed precision, frozen at 3x the largest deviations measured on MI355X
+# on this window (spectrum 7.6e-8, log w 1.3e-7, T_k T_k+1 7.7e-8, energy
+# after the free-running window 4.6e-8 relative, <S.S> 3.2e-7)
+MIXED = {"spectrum": 2.5e-7, "logw": 4e-7, "theta": 2.5e-7,
+         "free_energy_rel": 1.5e-7, "free_ss": 1e-6}
 MEASURE_E_REL = 1e-10
 MEASURE_SS = 1e-10
 
@@ -97,6 +100,7 @@ def run_window(L, W, J_rung, beta, tau, chi, cut, t0, free, forced,
                   gpu_logw(ctx))
     worst = {"spectrum": 0.0, "logw": 0.0, "theta": 0.0}
     ranks = []
+    n_theta = 0
     for t in range(t1, t1 + forced):
         u = ups[t]
         op, g = op_of(u)
@@ -116,10 +120,16 @@ def run_window(L, W, J_rung, beta, tau, chi, cut, t0, free, forced,
         kk = min(k, len(S))
         worst["spectrum"] = max(worst["spectrum"],
                                 float(np.abs(gs[:kk] - S[:kk]).max() / S[0]))
-        worst["logw"] = max(worst["logw"], abs((lw - psi.logw)
-                                               - (oref.logw - psi.logw)))
+        # increments of a log-weight of size |psi.logw|: both sides round
+        # the sum to its ulp, which is taken out of the comparison
+        ulp = 4 * np.spacing(max(1.0, abs(psi.logw)))
+        worst["logw"] = max(worst["logw"], max(0.0, abs(lw - oref.logw) - ulp))
         Tn = read_state(ctx, range(lo, hi + 1))
-        if k == len(S):
+        # T_k T_{k+1} is invariant under the gauge of bond (k, k+1) only:
+        # after centre moves the oracle's QR and the GPU leave its outer
+        # bonds in different bases
+        if k == len(S) and psi.center in (u.k, u.k + 1):
+            n_theta += 1
             a = np.einsum("asb,btc->astc", Tn[u.k], Tn[u.k + 1])
             b = np.einsum("asb,btc->astc", oref.tensors[u.k],
                           oref.tensors[u.k + 1])
@@ -130,6 +140,7 @@ def run_window(L, W, J_rung, beta, tau, chi, cut, t0, free, forced,
         psi.logw = lw
     out.update(worst)
     out["rank_range"] = (min(ranks), max(ranks))
+    out["theta_compared"] = n_theta
 
     # 3. the oracle measures the GPU's state
     T = read_state(ctx, range(lay.length))
@@ -149,6 +160,7 @@ def check(out, tol):
     assert out["measure_ss"] <= MEASURE_SS
     for key in ("spectrum", "logw", "theta", "free_energy_rel", "free_ss"):
         assert out[key] <= tol[key], (key, out[key], tol[key])
+    assert out["theta_compared"] >= 10
 
 
 # 2x8 ladder, W=2, tau=0.05, chi_max=128, cutoff 1e-12: windows in the

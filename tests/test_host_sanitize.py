@@ -12,8 +12,10 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PKG = os.path.join(ROOT, "paper_1910_09142_amd")
-KERNEL_OBJS = [os.path.join(PKG, "_build", n)
-               for n in ("update.o", "jacobi.o", "observe.o")]
+# every kernel object of the regular build (the sources besides hmps.cpp)
+from paper_1910_09142_amd import build as _build  # noqa: E402
+KERNEL_OBJS = [os.path.join(PKG, "_build", os.path.splitext(n)[0] + ".o")
+               for n in _build.SOURCES if n.endswith(".hip")]
 
 
 def test_host_code_is_clean_under_sanitizers(tmp_path):
