@@ -326,6 +326,38 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
                            double cutoff, double *sigma, int32_t *rank,
                            double *left, double *right);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * truncated SVD of hmps_svd_probe without a context, on caller-owned
+ * device arrays, every intermediate in one file-scope device array of the
+ * library (4.4 MiB per device, held until the process ends).  It allocates
+ * nothing: no device memory, no events, no pinned memory.
+ *   device, stream: the HIP device ordinal and a hipStream_t on it (NULL
+ *     = the null stream); work is enqueued on the stream.
+ *   theta: device array, m x n row-major (m = 3 chi_l, n = 3 chi_r),
+ *     1 <= chi_l, chi_r <= 128 (the array's capacity; larger sizes return
+ *     HMPS_E_INVALID).
+ *   chi_max >= 1, 0 <= cutoff < 1: as hmps_svd_probe.
+ *   Outputs, as hmps_svd_probe: *rank (host) = k, valid on return;
+ *     sigma (device, >= min(m, n) doubles): the k kept singular values;
+ *     left (device, >= 3 chi_l min(m, n)): U as T[s1][a][j]; right
+ *     (device, >= 3 min(m, n) chi_r): Sigma V^T / ||Sigma_kept|| as
+ *     T[s2][j][c]; these are written on `stream` after the call returns.
+ * It runs the kernels of hmps_svd_probe on a context with chi_cap = 128
+ * and default options (max_sweeps 100), with the Jacobi sweeps as a fixed
+ * launch sequence; results equal that entry point's.  Every call on a
+ * device shares the device's array and leaves its contents there: calls
+ * that overlap on one device (other streams or threads) race.  Returns
+ * HMPS_E_INVALID for bad arguments, HMPS_E_DEVICE for a failed HIP call,
+ * HMPS_E_NUMERIC if the SVD does not converge.  Synchronises the stream
+ * once (to read the status and rank). */
+hmps_status hmps_svd_probe_noalloc(int32_t device, void *stream,
+                                   int32_t chi_l, int32_t chi_r,
+                                   const double *theta, int32_t chi_max,
+                                   double cutoff, double *sigma,
+                                   int32_t *rank, double *left,
+                                   double *right);
+
 /* Destroy a context (NULL is accepted).  Does not free the workspace. */
 void hmps_destroy(hmps_ctx *ctx);
 

@@ -37,7 +37,7 @@ EXPORTS = [
     "hmps_schedule", "hmps_svd_probe", "hmps_measure_pairs",
     "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
     "hmps_apply_gate", "hmps_init_cluster_env_at", "hmps_evolve_updates",
-    "hmps_last_spectrum",
+    "hmps_last_spectrum", "hmps_svd_probe_noalloc",
 ]
 
 
@@ -124,6 +124,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         P(C.c_double), P(C.c_double)]
     lib.hmps_apply_gate.argtypes = [C.c_void_p, C.c_double, C.c_double,
                                     C.c_int32, C.c_double, P(C.c_double)]
+    lib.hmps_svd_probe_noalloc.argtypes = [
+        C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+        C.c_double, C.c_void_p, P(C.c_int32), C.c_void_p, C.c_void_p]
+    lib.hmps_svd_probe_noalloc.restype = C.c_int32
     lib.hmps_destroy.argtypes = [C.c_void_p]
     lib.hmps_destroy.restype = None
     lib.hmps_last_error.argtypes = [C.c_void_p]
