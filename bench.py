@@ -72,6 +72,11 @@ def parse(argv=None):
                     help="gate workload: headline measurement only")
     ap.add_argument("--beta", type=float, default=None,
                     help="ladder workloads: override beta")
+    ap.add_argument("--window", default=None, metavar="START:COUNT",
+                    help="ladder workloads: time Trotter steps START .. "
+                    "START+COUNT-1 of the first evolution only (the steps "
+                    "before run untimed); reports the bond-dimension "
+                    "histogram at the end of the window")
     args = ap.parse_args(argv)
     if args.steps < 1 or args.warmup < 0:
         ap.error("--steps >= 1 and --warmup >= 0")
@@ -397,6 +402,65 @@ def copy_probe():
 # ---------------------------------------------------------------------------
 # whole samples of a ladder workload
 # ---------------------------------------------------------------------------
+def main_window(args, wl, B, ctx):
+    """Trotter steps START .. START+COUNT-1 of the first evolution of B
+    chains, timed; the bond dimensions of every chain afterwards."""
+    import numpy as np
+    import torch
+    from paper_1910_09142_amd import hmps
+    start, count = (int(x) for x in args.window.split(":"))
+    n, steps = hmps.hmps_schedule(ctx._lat)
+    per = len(steps)
+    M = int(round(wl.beta / (2.0 * wl.tau)))
+    if start < 0 or count < 1 or start + count > M:
+        raise SystemExit(f"--window outside the {M} Trotter steps")
+    ctx.hmps_evolve_updates(wl.beta, wl.tau, wl.chi_max, wl.cutoff, 0,
+                            start * per)
+    s0 = ctx.hmps_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(count):
+        ctx.hmps_evolve_updates(wl.beta, wl.tau, wl.chi_max, wl.cutoff,
+                                (start + i) * per, per)
+        print(f"window step {start + i + 1} ({time.perf_counter() - t0:.1f} s)",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s1 = ctx.hmps_stats()
+    chi = ctx.hmps_bond_dims()
+    # bonds inside the chain (the two open ends have dimension 1)
+    inner = chi[:, 1:-1].ravel()
+    edges = [1, 2, 4, 8, 16, 32, 64, 128, 192, 256, 384, 512, 1 << 30]
+    hist = {f"{edges[i]}-{edges[i + 1] - 1}": int(((inner >= edges[i]) &
+                                                   (inner < edges[i + 1])).sum())
+            for i in range(len(edges) - 1)
+            if ((inner >= edges[i]) & (inner < edges[i + 1])).any()}
+    ups = s1.updates - s0.updates - (s1.move_updates - s0.move_updates)
+    gates = s1.gate_updates - s0.gate_updates
+    out = {
+        "metric": METRIC, "value": gates / elapsed, "unit": UNIT,
+        "n_gpus": 1, "steps": count, "warmup": start,
+        "ms_per_step": 1e3 * elapsed / count, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic (Philox-seeded product states, ladder Hamiltonian)",
+        "config": {"workload": f"{wl.name}_chains{B}_steps{start}-"
+                   f"{start + count - 1}", "n_chains": B, "L": wl.L,
+                   "W": wl.W, "J_leg": wl.J_leg, "J_rung": wl.J_rung,
+                   "beta": wl.beta, "tau": wl.tau, "chi_max": wl.chi_max,
+                   "cutoff": wl.cutoff, "trotter_steps": [start, start + count],
+                   "precision": args.precision},
+        "trotter_updates_per_s": ups / elapsed,
+        "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12,
+        "chi_histogram_after": hist,
+        "chi_mean_after": float(inner.mean()),
+        "max_chi": int(inner.max()),
+        "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
+        "roofline": svd_roofline(wl.name, s0, s1, False),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main_ladder(args):
     import torch
     from paper_1910_09142_amd import hmps, workloads
@@ -421,6 +485,10 @@ def main_ladder(args):
     ctx = hmps.Context(B, workloads.mps_length(wl.L, wl.W), wl.chi_max,
                        len(bonds), precision=precision, progress=progress)
     ctx.hmps_init_cluster_env(lat, B, wl.seed)
+    if args.window:
+        main_window(args, wl, B, ctx)
+        ctx.hmps_destroy()
+        return
 
     def one_sample(idx):
         ctx.hmps_evolve(wl.beta, wl.tau, wl.chi_max, wl.cutoff)
