@@ -284,6 +284,8 @@ def gate_run(wl, center, right, precision, steps, warmup, label):
             "chi_after": int(chi_now.min()), "logw": logw,
             "sweeps_per_gate": (s1.jacobi_sweeps - s0.jacobi_sweeps)
             / max(1, steps),
+            "sweeps32_per_gate": (s1.jacobi_sweeps_fp32 - s0.jacobi_sweeps_fp32)
+            / max(1, steps),
             "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12}
 
 
@@ -376,6 +378,7 @@ def main_gate(args, extras):
             "value": mixed["rate"], "unit": UNIT, "n_chains": B,
             "speedup_vs_fp64": mixed["rate"] / fp64["rate"],
             "jacobi_sweeps_per_gate": mixed["sweeps_per_gate"],
+            "fp32_sweeps_per_gate": mixed["sweeps32_per_gate"],
             "max_abs_logw_diff_vs_fp64": float(
                 np.abs(mixed["logw"] - fp64["logw"]).max())}
         c2 = dataclasses.replace(workloads.C2, beta=1.0,

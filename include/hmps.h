@@ -50,10 +50,15 @@ typedef int32_t hmps_status;
 #define HMPS_E_STATE 4   /* call out of order (e.g. evolve before init) */
 #define HMPS_E_NUMERIC 5 /* SVD did not converge, NaN/Inf, zero norm    */
 
-/* Precision of the theta contraction and the gate (FP64, or FP32 on the
- * matrix cores with FP32 accumulation from FP64 site tensors rounded on
- * load).  The SVD, truncation, norms, observables and all accumulations
- * are FP64 in both modes. */
+/* Precision of an update (Trotter gate or swap; centre moves are always
+ * FP64).  HMPS_PREC_FP64: every step in FP64.  HMPS_PREC_MIXED_FP32: the
+ * theta contraction and the gate in FP32 on the matrix cores (FP32
+ * accumulation, FP64 site tensors rounded on load); for updates whose SVD
+ * takes the QR-preconditioned blocked path, the Jacobi sweeps run in FP32
+ * on the FP64 R factor rounded to FP32, and a Rayleigh-Ritz step in FP64
+ * on the chi_max + 64 (rounded to 32) largest resulting vectors gives the
+ * kept singular triplets.  Truncation, ||theta'||^2, the log-weight,
+ * norms, observables and all accumulations are FP64 in both modes. */
 #define HMPS_PREC_FP64 0
 #define HMPS_PREC_MIXED_FP32 1
 /* Split-bf16 (three bf16 products per FP32 product) contractions are not
@@ -130,6 +135,8 @@ typedef struct {
   int64_t center;           /* MPS position of the orthogonality centre  */
   int64_t evolve_pos;       /* updates applied of an evolution run in
                                parts by hmps_evolve_updates (0: none)    */
+  int64_t jacobi_sweeps_fp32; /* of jacobi_sweeps, the FP32 sweeps of the
+                               mixed-precision SVD                        */
 } hmps_stats_t;
 
 /* Bytes of device workspace needed for the given capacities. */

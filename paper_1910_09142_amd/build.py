@@ -14,8 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhmps.so")
-SOURCES = ["update.hip", "jacobi.hip", "qr.hip", "observe.hip", "noalloc.hip",
-           "hmps.cpp"]
+SOURCES = ["update.hip", "jacobi.hip", "qr.hip", "rr.hip", "observe.hip",
+           "noalloc.hip", "hmps.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -27,6 +27,9 @@ using namespace hmps;
 namespace {
 
 constexpr int OP_SWAP = -1;
+// sweeps of the FP32 stage of the mixed path (it stops earlier once no
+// pair needs a rotation at the FP32 tolerance)
+constexpr int RR_FP32_SWEEPS = 40;
 constexpr int OP_IDENT = -2;
 constexpr size_t ALIGN = 256;
 
@@ -265,7 +268,7 @@ struct hmps_ctx {
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
   int n_cap = 0, slots = 0;
   double *d_sites = nullptr, *d_TH = nullptr, *d_X = nullptr,
-         *d_Y = nullptr, *d_qrT = nullptr, *d_norm2 = nullptr,
+         *d_Y = nullptr, *d_Z = nullptr, *d_qrT = nullptr, *d_norm2 = nullptr,
          *d_sig2 = nullptr, *d_sig = nullptr, *d_fac = nullptr,
          *d_logw = nullptr, *d_disc = nullptr, *d_gates = nullptr,
          *d_envs = nullptr, *d_wsz = nullptr, *d_bscr = nullptr,
@@ -276,6 +279,7 @@ struct hmps_ctx {
           *d_rot = nullptr, *d_done = nullptr, *d_err = nullptr,
           *d_pair_p = nullptr, *d_pair_q = nullptr,
           *d_sweeps = nullptr, *d_near = nullptr, *d_bond_p = nullptr,
+          *d_rrk = nullptr,
           *d_bond_q = nullptr, *d_is_cluster = nullptr,
           *d_is_ancilla = nullptr, *d_env_index = nullptr;
   uint8_t *d_labels = nullptr, *d_outcomes = nullptr;
@@ -323,6 +327,7 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_TH = cv.take<double>(B * th_stride);
   t->d_X = cv.take<double>(B * th_stride);
   t->d_Y = cv.take<double>(B * th_stride);
+  t->d_Z = cv.take<double>(B * th_stride);
   t->d_qrT = cv.take<double>(B * QB * QB);
   t->d_sig2 = cv.take<double>(B * n_cap);
   t->d_sig = cv.take<double>(B * n_cap);
@@ -332,9 +337,10 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_rot = cv.take<int32_t>(B);
   t->d_done = cv.take<int32_t>(B);
   t->d_sweeps = cv.take<int32_t>(B);
+  t->d_rrk = cv.take<int32_t>(B);
   t->d_near = cv.take<int32_t>(B);
   t->d_fac = cv.take<double>(B);
-  t->d_norm2 = cv.take<double>(B);
+  t->d_norm2 = cv.take<double>(B * NORM_SPLIT);
   t->d_logw = cv.take<double>(B);
   t->d_disc = cv.take<double>(B);
   t->d_norm = cv.take<double>(B);
@@ -405,6 +411,7 @@ UpdScratch scratch_of(hmps_ctx *ctx) {
   s.TH = ctx->d_TH;
   s.X = ctx->d_X;
   s.Y = ctx->d_Y;
+  s.Z = ctx->d_Z;
   s.qrT = ctx->d_qrT;
   s.th_stride = ctx->th_stride;
   s.sig2 = ctx->d_sig2;
@@ -420,6 +427,7 @@ UpdScratch scratch_of(hmps_ctx *ctx) {
   s.done = ctx->d_done;
   s.err = ctx->d_err;
   s.sweeps = ctx->d_sweeps;
+  s.rrk = ctx->d_rrk;
   return s;
 }
 
@@ -463,9 +471,13 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   // each chain's SVD runs in LDS when its theta' has at most small_max
   // entries, else on the blocked rounds; the rounds' grid is sized by the
   // blocked chains alone
-  int n_small = 0, n_blocked = 0, n_qr = 0;
-  int max_nb = 2, max_vlen = 1, max_nvec = 1, max_qr_n = 0;
+  int n_small = 0, n_blocked = 0, n_qr = 0, n_rr = 0;
+  int max_nb = 2, max_nb32 = 2, max_vlen = 1, max_nvec = 1, max_qr_n = 0;
+  int max_rr_n = 0, max_rr_l = 0;
   double flops = 0.0, svd_flops = 0.0;
+  const bool is_move = (op == OP_IDENT);
+  // centre moves are exact gauge changes: always FP64
+  const int mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32 && !is_move;
   for (int c = 0; c < ctx->B; ++c) {
     const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
     {
@@ -483,18 +495,28 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
     max_vlen = std::max(max_vlen, 3 * std::max(row[k], row[k + 2]));
     max_nvec = std::max(max_nvec, nvec);
     const int vlen = 3 * std::max(row[k], row[k + 2]);
-    if (small_path(vlen, nvec, ctx->small_max)) {
+    const int path = svd_path(vlen, nvec, ctx->small_max, ctx->precond, mixed);
+    if (path == PATH_SMALL) {
       ++n_small;
     } else {
       ++n_blocked;
-      max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
-      if (qr_path(vlen, nvec, ctx->small_max, ctx->precond)) {
+      if (path == PATH_RR) {
+        // FP32 rounds on all nvec vectors, FP64 rounds on the Ritz basis
+        ++n_rr;
+        max_rr_n = std::max(max_rr_n, nvec);
+        max_rr_l = std::max(max_rr_l, vlen);
+        max_nb32 = std::max(max_nb32, n_blocks_even(nvec, JB));
+        max_nb = std::max(max_nb,
+                          n_blocks_even(rr_vectors(nvec, chi_max), JB));
+      } else {
+        max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
+      }
+      if (path >= PATH_QR) {
         ++n_qr;
         max_qr_n = std::max(max_qr_n, nvec);
       }
     }
   }
-  const bool is_move = (op == OP_IDENT);
   UpdParams u;
   u.k = k;
   const int ncoup = (int)ctx->plan.couplings.size();
@@ -506,8 +528,13 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   u.cutoff = is_move ? 0.0 : cutoff;
   u.tol = ctx->opt.jacobi_tol;
   u.max_sweeps = ctx->opt.max_sweeps;
-  // centre moves are exact gauge changes: always FP64
-  u.mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32 && !is_move;
+  u.mixed = mixed;
+  u.tol32 = 8.0 * std::sqrt(3.0 * ctx->opt.chi_cap) * 1.1920929e-7;
+  // vectors below 1e-12 sigma_0 are left unrotated in FP32 and out of the
+  // Ritz basis (the numerically null part of a rank-deficient theta');
+  // every other pair is rotated to the FP32 tolerance relative to its own
+  // norms, so the basis vectors are orthogonal to about tol32
+  u.skip32 = 1e-24;
   u.precond = ctx->precond;
   u.small_max = ctx->small_max;
   u.inner_sweeps = ctx->inner_sweeps;
@@ -519,7 +546,8 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   bool timed_svd = false;
   if (!ctx->skip_theta) {
     launch_theta(b, s, u, max_chiL, max_chiR, st);
-    if (u.is_gate) launch_theta_norm(b, s, u, st);
+    // ||theta'||^2: the gate's log-weight, the mixed path's unresolved tail
+    if (u.is_gate || mixed) launch_theta_norm(b, s, u, st);
     LAUNCHCHK(ctx);
   }
   if (n_small > 0) {
@@ -538,63 +566,102 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       launch_qr_to_vectors(b, s, u, max_qr_n, st);
       LAUNCHCHK(ctx);
     }
-    bool converged = false;
     // Sweep s is enqueued before the host waits for the rotation count of
     // sweep s-1, so the read-back overlaps the next sweep; a sweep enqueued
-    // after convergence finds every chain done and exits at once.
-    auto enqueue_sweep = [&](int sweep) -> hmps_status {
-      launch_jacobi_sweep_begin(s, ctx->B, sweep, st);
-      if (sweep == 0 && n_small > 0)
-        launch_mark_small_done(b, s, u, ctx->small_max, st);
-      for (int r = 0; r < max_nb - 1; ++r)
-        launch_jacobi_round(b, s, u, r, max_nb / 2, st);
-      ctx->stats.jacobi_sweeps += 1;
-      ctx->stats.round_launches += max_nb - 1;
-      int32_t *slot = ctx->h_stage + (size_t)(2 + (sweep & 1)) * ctx->opt.max_chains;
-      HIPCHK(hipMemcpyAsync(slot, ctx->d_rot, sizeof(int32_t) * ctx->B,
-                            hipMemcpyDeviceToHost, st));
-      HIPCHK(hipEventRecord(ctx->sweep_ev[sweep & 1], st));
+    // after convergence finds every chain done and exits at once.  f32:
+    // the FP32 rounds of the mixed path (only its chains take part).
+    auto run_sweeps = [&](bool f32, int nb_max, int cap,
+                          bool &converged) -> hmps_status {
+      converged = false;
+      auto enqueue_sweep = [&](int sweep) -> hmps_status {
+        launch_jacobi_sweep_begin(s, ctx->B, sweep, st);
+        if (sweep == 0 && n_small > 0)
+          launch_mark_small_done(b, s, u, ctx->small_max, st);
+        for (int r = 0; r < nb_max - 1; ++r) {
+          if (f32)
+            launch_jacobi_round32(b, s, u, r, nb_max / 2, st);
+          else
+            launch_jacobi_round(b, s, u, r, nb_max / 2, st);
+        }
+        ctx->stats.jacobi_sweeps += 1;
+        if (f32) ctx->stats.jacobi_sweeps_fp32 += 1;
+        ctx->stats.round_launches += nb_max - 1;
+        int32_t *slot =
+            ctx->h_stage + (size_t)(2 + (sweep & 1)) * ctx->opt.max_chains;
+        HIPCHK(hipMemcpyAsync(slot, ctx->d_rot, sizeof(int32_t) * ctx->B,
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(ctx->sweep_ev[sweep & 1], st));
+        return HMPS_OK;
+      };
+      // algorithmic bytes of the rounds: in every round a chain's block
+      // pairs are read once and, in a sweep where the chain still rotates,
+      // written once (its last, checking sweep only reads them)
+      std::vector<double> round_bytes(ctx->B);
+      std::vector<uint8_t> active(ctx->B, 1);
+      for (int c = 0; c < ctx->B; ++c) {
+        const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
+        const int nvec = 3 * std::min(row[k], row[k + 2]);
+        const int len = 3 * std::max(row[k], row[k + 2]);
+        const int path =
+            svd_path(len, nvec, ctx->small_max, ctx->precond, mixed);
+        int vlen = len, nv = nvec;
+        double esz = 8.0;
+        if (f32) {
+          vlen = nvec;
+          esz = 4.0;
+        } else if (path == PATH_QR) {
+          vlen = nvec;  // R^T
+        } else if (path == PATH_RR) {
+          nv = rr_vectors(nvec, chi_max);
+        }
+        const int nb = n_blocks_even(nv, JB);
+        const bool part = f32 ? path == PATH_RR : path != PATH_SMALL;
+        round_bytes[c] =
+            part ? (double)(nb - 1) * nb * JB * vector_stride(vlen) * esz : 0.0;
+      }
+      hmps_status est = enqueue_sweep(0);
+      if (est) return est;
+      for (int sweep = 1; sweep <= cap; ++sweep) {
+        if (sweep < cap) {
+          est = enqueue_sweep(sweep);
+          if (est) return est;
+        }
+        const int prev = (sweep - 1) & 1;
+        HIPCHK(hipEventSynchronize(ctx->sweep_ev[prev]));
+        const int32_t *slot =
+            ctx->h_stage + (size_t)(2 + prev) * ctx->opt.max_chains;
+        bool any = false;
+        for (int c = 0; c < ctx->B; ++c) {
+          if (active[c])
+            ctx->stats.svd_bytes += round_bytes[c] * (slot[c] != 0 ? 2.0 : 1.0);
+          active[c] = slot[c] != 0;
+          any |= slot[c] != 0;
+        }
+        if (!any) {
+          converged = true;
+          break;
+        }
+      }
+      // a sweep enqueued beyond convergence may still be in flight: the
+      // next loop resets the flags it reads only after it (stream order)
       return HMPS_OK;
     };
-    // algorithmic bytes of the rounds: in every round a chain's block pairs
-    // are read once and, in a sweep where the chain still rotates, written
-    // once (its last, checking sweep only reads them)
-    std::vector<double> round_bytes(ctx->B);
-    std::vector<uint8_t> active(ctx->B, 1);
-    for (int c = 0; c < ctx->B; ++c) {
-      const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
-      const int nvec = 3 * std::min(row[k], row[k + 2]);
-      const int len = 3 * std::max(row[k], row[k + 2]);
-      const int nb = n_blocks_even(nvec, JB);
-      const bool small = small_path(len, nvec, ctx->small_max);
-      // the QR path rotates vectors of length nvec
-      const int vlen =
-          qr_path(len, nvec, ctx->small_max, ctx->precond) ? nvec : len;
-      round_bytes[c] =
-          small ? 0.0 : (double)(nb - 1) * nb * JB * vector_stride(vlen) * 8.0;
-    }
     HIPCHK(hipEventRecord(ctx->svd_ev[0], st));
-    hmps_status est = enqueue_sweep(0);
-    if (est) return est;
-    for (int sweep = 1; sweep <= ctx->opt.max_sweeps; ++sweep) {
-      if (sweep < ctx->opt.max_sweeps) {
-        est = enqueue_sweep(sweep);
-        if (est) return est;
-      }
-      const int prev = (sweep - 1) & 1;
-      HIPCHK(hipEventSynchronize(ctx->sweep_ev[prev]));
-      const int32_t *slot = ctx->h_stage + (size_t)(2 + prev) * ctx->opt.max_chains;
-      bool any = false;
-      for (int c = 0; c < ctx->B; ++c) {
-        if (active[c])
-          ctx->stats.svd_bytes += round_bytes[c] * (slot[c] != 0 ? 2.0 : 1.0);
-        active[c] = slot[c] != 0;
-        any |= slot[c] != 0;
-      }
-      if (!any) {
-        converged = true;
-        break;
-      }
+    bool converged = false;
+    if (n_rr > 0) {
+      // mixed path: FP32 rounds on R^T (their convergence to the FP32
+      // tolerance is not required: the FP64 Ritz step takes whatever basis
+      // they reach), then the FP64 Ritz basis and theta' W
+      launch_rr_to32(b, s, u, st);
+      hmps_status est = run_sweeps(true, max_nb32, RR_FP32_SWEEPS, converged);
+      if (est) return est;
+      launch_rr_stage2(b, s, u, max_rr_n, max_rr_l, st);
+      LAUNCHCHK(ctx);
+    }
+    {
+      hmps_status est = run_sweeps(false, max_nb, ctx->opt.max_sweeps,
+                                   converged);
+      if (est) return est;
     }
     if (!converged)
       return fail(ctx, HMPS_E_NUMERIC,

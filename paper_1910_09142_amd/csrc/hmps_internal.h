@@ -32,6 +32,9 @@ constexpr double SIGMA_FLOOR = 1e-13;
 // Relative gap below which neighbouring singular values tie.
 constexpr double TIE_TOL = 1e-8;
 
+// Workgroups per chain summing ||theta'||^2.
+constexpr int NORM_SPLIT = 16;
+
 // Householder QR preconditioning of the blocked Jacobi SVD: panel width,
 // and the longest vectors whose 16-column panel fits in one workgroup's
 // LDS (QB * QR_MAX_L doubles).
@@ -49,6 +52,25 @@ __host__ __device__ inline bool small_path(int L, int N, size_t small_max) {
 __host__ __device__ inline bool qr_path(int L, int N, size_t small_max,
                                         int precond) {
   return precond && !small_path(L, N, small_max) && L <= QR_MAX_L;
+}
+// Paths of a chain's SVD.  PATH_RR (mixed precision, on chains that take
+// the QR): Jacobi rounds on an FP32 copy of R^T, then the rr_vectors
+// largest of its converged vectors, orthonormalised in FP64, give the basis
+// W of a Rayleigh-Ritz step: FP64 rounds on the columns of theta' W.
+enum { PATH_SMALL = 0, PATH_PLAIN = 1, PATH_QR = 2, PATH_RR = 3 };
+__host__ __device__ inline int svd_path(int L, int N, size_t small_max,
+                                        int precond, int mixed) {
+  if (small_path(L, N, small_max)) return PATH_SMALL;
+  if (qr_path(L, N, small_max, precond)) return mixed ? PATH_RR : PATH_QR;
+  return PATH_PLAIN;
+}
+// Largest Ritz basis: chi_max plus 64 (at least 64 vectors beyond the
+// cut), rounded to 32, at most N.  The basis holds only the vectors the
+// FP32 stage resolves (squared norm above skip32 times the largest, which
+// it rotates against every other): the chain's size is rrk <= this.
+__host__ __device__ inline int rr_vectors(int N, int chi_max) {
+  const int k = (chi_max + 64 + 31) / 32 * 32;
+  return k < N ? k : N;
 }
 
 // Device view of one batch of chains.  Site p of chain c is the row-major
@@ -70,6 +92,7 @@ struct UpdScratch {
   double *X;          // [B][th_stride]
   double *Y;          // [B][th_stride] R^T of the QR path (the vectors)
   double *qrT;        // [B][QB * QB] compact-WY factor of the last panel
+  double *Z;          // [B][th_stride] Gram of the mixed path's basis
   size_t th_stride;
   double *sig2;       // [B][n_cap] squared column norms after convergence
   int32_t *perm;      // [B][n_cap] kept columns, largest singular value first
@@ -77,13 +100,14 @@ struct UpdScratch {
   int n_cap;
   int32_t *knew;      // [B]
   double *fac;        // [B] 1/||kept||
-  double *norm2;      // [B] ||theta'||^2 of the update (FP64)
+  double *norm2;      // [B][NORM_SPLIT] partial sums of ||theta'||^2 (FP64)
   double *logw;       // [B]
   double *discarded;  // [B] accumulated relative discarded weight
   int32_t *rot_cur;   // [B] rotations in the current sweep
   int32_t *done;      // [B] Jacobi converged
   int32_t *err;       // [B] nonzero: numerical failure
   int32_t *sweeps;    // [B] Jacobi sweeps done by the in-LDS path
+  int32_t *rrk;       // [B] Ritz basis size of the mixed path (<= rr_vectors)
 };
 
 struct UpdParams {
@@ -94,10 +118,12 @@ struct UpdParams {
   int chi_max;
   double cutoff;
   double tol;         // Jacobi relative orthogonality tolerance
+  double tol32;       // the same for the FP32 rounds of the mixed path
   int max_sweeps;
   int mixed;          // FP32 contraction
   int inner_sweeps;   // cap on the inner Jacobi sweeps of a block pair
   double skip;        // relative squared norm below which a vector is zero
+  double skip32;      // the same for the FP32 rounds
   int cross_inner;    // inner rotations across the two blocks only (rounds > 0)
   int precond;        // QR preconditioning of the blocked path
   size_t small_max;   // largest L * N of the in-LDS SVD path
@@ -117,6 +143,9 @@ void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
 void launch_jacobi_round(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, int round, int max_pairs,
                          hipStream_t st);
+void launch_jacobi_round32(const Batch &b, const UpdScratch &s,
+                           const UpdParams &u, int round, int max_pairs,
+                           hipStream_t st);
 void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
                      hipStream_t st);
 void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
@@ -129,6 +158,12 @@ void launch_qr_update(const Batch &b, const UpdScratch &s, const UpdParams &u,
                       int p, int max_tiles, hipStream_t st);
 void launch_qr_to_vectors(const Batch &b, const UpdScratch &s,
                           const UpdParams &u, int max_N, hipStream_t st);
+// Mixed path (rr.hip): R^T to FP32 before the FP32 rounds; after them the
+// FP64 Ritz basis W and theta' W into X for the FP64 rounds.
+void launch_rr_to32(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                    hipStream_t st);
+void launch_rr_stage2(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                      int max_N, int max_L, hipStream_t st);
 
 struct MeasureArgs {
   const int32_t *bond_p, *bond_q;  // [n_bonds] MPS positions, p < q

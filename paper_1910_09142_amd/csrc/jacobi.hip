@@ -145,22 +145,57 @@ constexpr int NWAVE = RT / 64;
 constexpr int NSLOT = 4;               // partial Gram sets summed in LDS
 static_assert(P2 == 32 && RT == 512, "tiling assumes 16-wide blocks");
 
+// Storage precision of the rounds: FP64 (every path), or FP32 (the first
+// stage of the mixed-precision path).  The Gram products and the rotation
+// run on the matrix cores in the storage precision; the Gram is summed,
+// tested and diagonalised in FP64 in both.
+typedef float v4f __attribute__((ext_vector_type(4)));
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+  typedef v4d V;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return mfma_f64(a, b, c);
+  }
+  // row of the 16 x 16 product held by lane group lk in element e
+  // (FP64: lane j + 16 (i % 4) holds D[i][j] in element i / 4)
+  static __device__ __forceinline__ int drow(int lk, int e) { return lk + 4 * e; }
+};
+template <> struct Prec<float> {
+  typedef v4f V;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // FP32: lane j + 16 (i / 4) holds D[i][j] in element i % 4
+  static __device__ __forceinline__ int drow(int lk, int e) { return 4 * lk + e; }
+};
+
+template <typename T>
 __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     k_jacobi_round(Batch b, UpdScratch s, UpdParams u, int r) {
+  typedef Prec<T> PR;
+  typedef typename PR::V V;
+  constexpr bool F32 = sizeof(T) == 4;
   const int c = blockIdx.y, pi = blockIdx.x;
   if (s.done[c]) return;
   const int32_t *chi = chi_row(b, c);
   const int m = 3 * chi[u.k], n = 3 * chi[u.k + 2];
   const int Lt = m > n ? m : n, N = m > n ? n : m;
-  // the QR path rotates the N columns of R^T (length N) in Y
-  const bool qr = qr_path(Lt, N, u.small_max, u.precond);
-  const int L = qr ? N : Lt;
-  const int NB = n_blocks_even(N, JB);
+  const int path = svd_path(Lt, N, u.small_max, u.precond, u.mixed);
+  // the vector matrix of the chain's path: R^T (length N) in Y on the QR
+  // path; on the mixed path its FP32 copy in X (first stage), then the
+  // rrk columns of theta' W in X (second stage); theta' in X else
+  if (F32 && path != PATH_RR) return;
+  const int L = (F32 || path == PATH_QR) ? N : Lt;
+  const int nvec = (!F32 && path == PATH_RR) ? s.rrk[c] : N;
+  const int NB = n_blocks_even(nvec, JB);
   if (r >= NB - 1 || pi >= NB / 2) return;
   const int ld = vec_ld(L);
   int bi, bj;
   rr_pair(r, pi, NB, bi, bj);
-  double *X = (qr ? s.Y : s.X) + (size_t)c * s.th_stride;
+  T *X = reinterpret_cast<T *>((!F32 && path == PATH_QR) ? s.Y : s.X) +
+         (size_t)c * (F32 ? 2 : 1) * s.th_stride;
+  const double tol = F32 ? u.tol32 : u.tol;
+  const double skip = F32 ? u.skip32 : u.skip;
   auto colidx = [&](int t) { return t < JB ? bi * JB + t : bj * JB + t - JB; };
 
   // G is symmetric and only its upper triangle (i <= j) is kept.  It is
@@ -212,35 +247,35 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   }
   {
     constexpr int CSTEP = 16 * NWAVE;
-    v4d acc[NTILE];
+    V acc[NTILE];
 #pragma unroll
-    for (int t = 0; t < NTILE; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
-    const double *xa = X + (size_t)colidx(li) * ld + 4 * lk;
-    const double *xb = X + (size_t)colidx(JB + li) * ld + 4 * lk;
-    auto load = [&](const double *x, int e0) -> v4d {
-      return *reinterpret_cast<const v4d *>(x + e0);
+    for (int t = 0; t < NTILE; ++t) acc[t] = V{0, 0, 0, 0};
+    const T *xa = X + (size_t)colidx(li) * ld + 4 * lk;
+    const T *xb = X + (size_t)colidx(JB + li) * ld + 4 * lk;
+    auto load = [&](const T *x, int e0) -> V {
+      return *reinterpret_cast<const V *>(x + e0);
     };
-    auto gram4 = [&](const v4d &a, const v4d &b) {
-      acc[0] = mfma_f64(a.x, a.x, acc[0]);
-      acc[1] = mfma_f64(a.x, b.x, acc[1]);
-      acc[2] = mfma_f64(b.x, b.x, acc[2]);
-      acc[0] = mfma_f64(a.y, a.y, acc[0]);
-      acc[1] = mfma_f64(a.y, b.y, acc[1]);
-      acc[2] = mfma_f64(b.y, b.y, acc[2]);
-      acc[0] = mfma_f64(a.z, a.z, acc[0]);
-      acc[1] = mfma_f64(a.z, b.z, acc[1]);
-      acc[2] = mfma_f64(b.z, b.z, acc[2]);
-      acc[0] = mfma_f64(a.w, a.w, acc[0]);
-      acc[1] = mfma_f64(a.w, b.w, acc[1]);
-      acc[2] = mfma_f64(b.w, b.w, acc[2]);
+    auto gram4 = [&](const V &a, const V &b) {
+      acc[0] = PR::mma(a.x, a.x, acc[0]);
+      acc[1] = PR::mma(a.x, b.x, acc[1]);
+      acc[2] = PR::mma(b.x, b.x, acc[2]);
+      acc[0] = PR::mma(a.y, a.y, acc[0]);
+      acc[1] = PR::mma(a.y, b.y, acc[1]);
+      acc[2] = PR::mma(b.y, b.y, acc[2]);
+      acc[0] = PR::mma(a.z, a.z, acc[0]);
+      acc[1] = PR::mma(a.z, b.z, acc[1]);
+      acc[2] = PR::mma(b.z, b.z, acc[2]);
+      acc[0] = PR::mma(a.w, a.w, acc[0]);
+      acc[1] = PR::mma(a.w, b.w, acc[1]);
+      acc[2] = PR::mma(b.w, b.w, acc[2]);
     };
     // two register buffers, unrolled by two: the next chunk's loads are
     // issued before this chunk's products (the compiler barrier keeps them
     // there) and no register copy forces an early wait
     const int elast = ld - 16;
     int e0 = 16 * w;
-    v4d a0 = load(xa, min(e0, elast)), b0 = load(xb, min(e0, elast));
-    v4d a1, b1;
+    V a0 = load(xa, min(e0, elast)), b0 = load(xb, min(e0, elast));
+    V a1, b1;
     while (e0 < L) {
       const int e1 = min(e0 + CSTEP, elast);
       a1 = load(xa, e1);
@@ -265,8 +300,8 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
         for (int t = 0; t < NTILE; ++t)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            double *dst = part + t * 256 + (lk + 4 * q) * 16 + li;
-            *dst = step == 0 ? acc[t][q] : *dst + acc[t][q];
+            double *dst = part + t * 256 + PR::drow(lk, q) * 16 + li;
+            *dst = step == 0 ? (double)acc[t][q] : *dst + (double)acc[t][q];
           }
       }
       __syncthreads();
@@ -286,7 +321,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   __syncthreads();
 
   // ---- 2. convergence test; Q = I; angles of the first rotation round -----
-  const double tol_in = fmax(0.125 * u.tol, 4e-16);
+  const double tol_in = fmax(0.125 * tol, 4e-16);
   int needs = 0;
   for (int idx = tid; idx < P2 * P2; idx += RT) {
     const int i = idx / P2, j = idx % P2;
@@ -294,7 +329,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     // block are tested (and rotated) in the first round of every sweep, and
     // a sweep without any rotation leaves them as tested there
     if (i < j && (!cross || (i < NPAIR && j >= NPAIR)) &&
-        pair_needs_rotation(G[0][i][i], G[0][j][j], G[0][i][j], u.tol, u.skip))
+        pair_needs_rotation(G[0][i][i], G[0][j][j], G[0][i][j], tol, skip))
       needs = 1;
     Q[i][j] = (i == j) ? 1.0 : 0.0;
   }
@@ -302,7 +337,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     int p, q;
     inner_pair(cross, 0, tid, P2, p, q);
     double cr = 1.0, sr = 0.0;
-    if (pair_rotation(G[0][p][p], G[0][q][q], G[0][p][q], tol_in, u.skip, cr,
+    if (pair_rotation(G[0][p][p], G[0][q][q], G[0][p][q], tol_in, skip, cr,
                       sr))
       flag[0] = 1;
     csn[0][tid] = make_double2(cr, sr);
@@ -310,7 +345,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   if (__syncthreads_or(needs) == 0) {
     if (tid < P2) {
       const int col = colidx(tid);
-      if (col < N) s.sig2[(size_t)c * s.n_cap + col] = G[0][tid][tid];
+      if (col < nvec) s.sig2[(size_t)c * s.n_cap + col] = G[0][tid][tid];
     }
     return;
   }
@@ -378,7 +413,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
           apq = rb ? (ra ? nv[3] : nv[2]) : (ra ? nv[1] : nv[0]);
         }
         double cr = 1.0, sr = 0.0;
-        const bool rot = pair_rotation(app, aqq, apq, tol_in, u.skip, cr, sr);
+        const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
         // the angle belongs to the next sweep when rn wraps to 0
         if (rot) flag[(isw + (rn == 0)) & 1] = 1;
         csn[nxt][tid] = make_double2(cr, sr);
@@ -428,29 +463,36 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   int coff[KB];
 #pragma unroll
   for (int kk = 0; kk < KB; ++kk) coff[kk] = colidx(4 * kk + lk) * ld;
-  double cur[KB], nxt[KB];
+  // output vectors of lane group lk: PR::drow(lk, q) of each block
+  int soff[KB];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    soff[q] = colidx(PR::drow(lk, q)) * ld;
+    soff[4 + q] = colidx(JB + PR::drow(lk, q)) * ld;
+  }
+  T cur[KB], nxt[KB];
   // rows L..ld-1 are zero and stay zero under the rotation, and every
   // 16-row chunk lies inside ld: loads and stores need no bounds tests
-  auto load_chunk = [&](int e0, double *v) {
+  auto load_chunk = [&](int e0, T *v) {
     const int e = e0 + li;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) v[kk] = X[coff[kk] + e];
   };
   constexpr int CSTEP = 16 * NWAVE;
-  auto rotate16 = [&](int e0, const double *v) {
-    v4d d0 = {0.0, 0.0, 0.0, 0.0}, d1 = d0;
+  auto rotate16 = [&](int e0, const T *v) {
+    V d0 = {0, 0, 0, 0}, d1 = d0;
 #pragma unroll
     for (int kk = 0; kk < KB; ++kk) {
-      d0 = mfma_f64(Q[4 * kk + lk][li], v[kk], d0);
-      d1 = mfma_f64(Q[4 * kk + lk][16 + li], v[kk], d1);
+      d0 = PR::mma((T)Q[4 * kk + lk][li], v[kk], d0);
+      d1 = PR::mma((T)Q[4 * kk + lk][16 + li], v[kk], d1);
     }
-    // D[i][j] (vector 16 t + i, row e0 + j) sits in lane j + 16 (i % 4),
-    // element i / 4: vector 16 t + lk + 4 q = 4 (4 t + q) + lk
+    // D[i][j] (vector 16 t + i, row e0 + j) sits in lane j and element q
+    // with i = PR::drow(lk, q)
     const int e = e0 + li;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      X[coff[q] + e] = d0[q];
-      X[coff[4 + q] + e] = d1[q];
+      X[soff[q] + e] = d0[q];
+      X[soff[4 + q] + e] = d1[q];
     }
   };
   // two register buffers, unrolled by two, as in the Gram loop
@@ -480,8 +522,15 @@ void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
 void launch_jacobi_round(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, int round, int max_pairs,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_round, dim3(max_pairs, b.B), dim3(RT), 0, st, b,
-                     s, u, round);
+  hipLaunchKernelGGL(k_jacobi_round<double>, dim3(max_pairs, b.B), dim3(RT), 0,
+                     st, b, s, u, round);
+}
+
+void launch_jacobi_round32(const Batch &b, const UpdScratch &s,
+                           const UpdParams &u, int round, int max_pairs,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_round<float>, dim3(max_pairs, b.B), dim3(RT), 0,
+                     st, b, s, u, round);
 }
 
 }  // namespace hmps

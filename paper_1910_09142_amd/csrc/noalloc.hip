@@ -32,8 +32,9 @@ constexpr size_t OFF_SITES = OFF_Y + na_al(NA_STRIDE);
 constexpr size_t OFF_SIG2 = OFF_SITES + na_al(2 * NA_SITE);
 constexpr size_t OFF_SIG = OFF_SIG2 + na_al(NA_NCAP);
 constexpr size_t OFF_QRT = OFF_SIG + na_al(NA_NCAP);
-constexpr size_t OFF_F = OFF_QRT + na_al(QB * QB);  // fac norm2 logw disc
-constexpr size_t OFF_I = OFF_F + na_al(4);           // int32 area
+// fac, norm2[NORM_SPLIT], logw, disc
+constexpr size_t OFF_F = OFF_QRT + na_al(QB * QB);
+constexpr size_t OFF_I = OFF_F + na_al(3 + NORM_SPLIT);  // int32 area
 // int32 area (in int32 units from OFF_I): chi[3], knew, err, rot, done,
 // sweeps, perm[NA_NCAP]
 constexpr size_t I_CHI = 0, I_KNEW = 4, I_ERR = 5, I_ROT = 6, I_DONE = 7,
@@ -80,7 +81,7 @@ __global__ void k_na_setup(const double *theta, int chi_l, int chi_r,
     iv[I_ROT] = 0;
     iv[I_DONE] = 0;
     iv[I_SWEEPS] = 0;
-    for (int i = 0; i < 4; ++i) base[OFF_F + i] = 0.0;
+    for (int i = 0; i < 3 + NORM_SPLIT; ++i) base[OFF_F + i] = 0.0;
   }
 }
 
@@ -139,6 +140,7 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   s.X = base + OFF_X;
   s.Y = base + OFF_Y;
   s.qrT = base + OFF_QRT;
+  s.Z = nullptr;  // the mixed path is never taken here
   s.th_stride = NA_STRIDE;
   s.sig2 = base + OFF_SIG2;
   s.perm = iv + I_PERM;
@@ -147,12 +149,13 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   s.knew = iv + I_KNEW;
   s.fac = base + OFF_F;
   s.norm2 = base + OFF_F + 1;
-  s.logw = base + OFF_F + 2;
-  s.discarded = base + OFF_F + 3;
+  s.logw = base + OFF_F + 1 + NORM_SPLIT;
+  s.discarded = base + OFF_F + 2 + NORM_SPLIT;
   s.rot_cur = iv + I_ROT;
   s.done = iv + I_DONE;
   s.err = iv + I_ERR;
   s.sweeps = iv + I_SWEEPS;
+  s.rrk = nullptr;  // the mixed path is never taken here
   // the parameters of hmps_svd_probe on a context with chi_cap = NA_CHI
   // and default options
   UpdParams u;
@@ -163,6 +166,8 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   u.chi_max = chi_max;
   u.cutoff = cutoff;
   u.tol = 8.0 * std::sqrt(3.0 * NA_CHI) * 2.220446e-16;
+  u.tol32 = 0.0;  // FP32 rounds are never launched here
+  u.skip32 = 0.0;
   u.max_sweeps = 100;
   u.mixed = 0;
   u.inner_sweeps = 1;

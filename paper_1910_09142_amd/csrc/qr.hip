@@ -121,7 +121,6 @@ __global__ void __launch_bounds__(PT) k_qr_panel(Batch b, UpdScratch s,
   __shared__ double red[64];
   __shared__ double dots[QB];
   __shared__ double T[QB][QB];
-  __shared__ double tau_s[QB];
   const int tid = threadIdx.x;
   for (int t = 0; t < QB; ++t)
     for (int r = tid; r < rows; r += PT)
@@ -171,16 +170,14 @@ __global__ void __launch_bounds__(PT) k_qr_panel(Batch b, UpdScratch s,
       const double vr = r == t ? 1.0 : col[r];
       for (int q = t + 1; q < w; ++q) P[q * rows + r] -= tau * vr * dots[q];
     }
-    // T column t from the dots with the earlier reflectors
-    if (tid == 0) {
-      tau_s[t] = tau;
-      for (int i = 0; i < t; ++i) {
-        double x = 0.0;
-        for (int q = i; q < t; ++q) x += T[i][q] * dots[q];
-        T[i][t] = -tau * x;
-      }
-      T[t][t] = tau;
+    // T column t from the dots with the earlier reflectors, row i by
+    // thread i (each reads its own row of T, columns < t)
+    if (tid < t) {
+      double x = 0.0;
+      for (int q = tid; q < t; ++q) x += T[tid][q] * dots[q];
+      T[tid][t] = -tau * x;
     }
+    if (tid == 0) T[t][t] = tau;
     __syncthreads();
   }
   for (int t = 0; t < w; ++t)

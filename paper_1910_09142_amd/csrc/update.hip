@@ -39,8 +39,13 @@ struct Dims {
 // A chain on the QR path rotates R^T (N vectors of length N, in Y): its
 // converged vectors lie on the other side of theta' than those of the
 // plain path (columns of M^T, see qr.hip), so the write-back swaps sides.
+__device__ __forceinline__ int path_of(const Dims &d, const UpdParams &u) {
+  return svd_path(d.L, d.N, u.small_max, u.precond, u.mixed);
+}
+// the write-back of the mixed path is that of the plain path (its vectors
+// are columns of theta' W, of length L, in X)
 __device__ __forceinline__ bool on_qr(const Dims &d, const UpdParams &u) {
-  return qr_path(d.L, d.N, u.small_max, u.precond);
+  return path_of(d, u) == PATH_QR;
 }
 __device__ __forceinline__ Dims vector_side(const Dims &d, bool qr) {
   Dims e = d;
@@ -194,20 +199,22 @@ __global__ void __launch_bounds__(NT) k_theta(Batch b, UpdScratch s, UpdParams u
 // any rotation) in a fixed order: the gate's log-weight increment ln
 // ||theta'||^2 (the sampling weight is the product of the squared norms of
 // the evolution, Hybrid METTS-Ancilla subsection).
+// Workgroup x of a chain sums the vectors q = x (mod NORM_SPLIT); the
+// partial sums are added in a fixed order by k_truncate.
 __global__ void __launch_bounds__(NT) k_theta_norm(Batch b, UpdScratch s,
                                                    UpdParams u) {
-  const int c = blockIdx.x;
+  const int c = blockIdx.y;
   const Dims d = dims_of(b, c, u.k);
   const double *TH = s.TH + (size_t)c * s.th_stride;
   __shared__ double red[NT / 64];
   double v = 0.0;
-  for (int q = 0; q < d.N; ++q)
+  for (int q = blockIdx.x; q < d.N; q += NORM_SPLIT)
     for (int l = threadIdx.x; l < d.L; l += NT) {
       const double x = TH[(size_t)q * d.ld + l];
       v = fma(x, x, v);
     }
   v = wg_sum(v, red);
-  if (threadIdx.x == 0) s.norm2[c] = v;
+  if (threadIdx.x == 0) s.norm2[(size_t)c * NORM_SPLIT + blockIdx.x] = v;
 }
 
 // Zero what the blocked paths read beyond theta': the padding rows
@@ -216,7 +223,7 @@ __global__ void __launch_bounds__(NT) k_theta_norm(Batch b, UpdScratch s,
 __global__ void __launch_bounds__(NT) k_pad(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.y;
   const Dims d = dims_of(b, c, u.k);
-  const bool qr = on_qr(d, u);
+  const bool qr = path_of(d, u) >= PATH_QR;
   const int npad = n_blocks_even(d.N, JB) * JB;
   double *X = s.X + (size_t)c * s.th_stride;
   const int tail = d.ld - d.L;
@@ -338,7 +345,10 @@ __global__ void __launch_bounds__(NT)
     k_truncate(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.x;
   const Dims d = dims_of(b, c, u.k);
-  const int N = d.N;
+  // the mixed path resolves only the rr_vectors largest singular values;
+  // the rest of ||theta'||^2 is the unresolved tail
+  const bool rr = path_of(d, u) == PATH_RR;
+  const int N = rr ? s.rrk[c] : d.N;
   __shared__ double key[2048];
   __shared__ int idx[2048];
   __shared__ int kk_s;
@@ -374,11 +384,17 @@ __global__ void __launch_bounds__(NT)
   if (tid == 0) {
     double total = 0.0;
     for (int j = N - 1; j >= 0; --j) total += key[j] * key[j];
+    double n2 = 0.0;  // ||theta'||^2 in FP64, summed from theta'
+    if (u.is_gate || rr)
+      for (int x = 0; x < NORM_SPLIT; ++x)
+        n2 += s.norm2[(size_t)c * NORM_SPLIT + x];
+    const double unres = rr ? fmax(n2 - total, 0.0) : 0.0;
+    total += unres;
     int kfloor = 0;
     while (kfloor < N && key[kfloor] > SIGMA_FLOOR * key[0]) ++kfloor;
     const double thr = u.cutoff * total;
     int k_eps = N;
-    double tail = 0.0;
+    double tail = unres;
     for (int k = N; k >= 1; --k) {
       if (k < N) tail += key[k] * key[k];
       if (tail <= thr)
@@ -411,7 +427,7 @@ __global__ void __launch_bounds__(NT)
     for (int j = k - 1; j >= 0; --j) kept += key[j] * key[j];
     if (!(total > 0.0) || !isfinite(total) || !(kept > 0.0)) s.err[c] = 2;
     s.fac[c] = 1.0 / sqrt(kept);
-    if (u.is_gate) s.logw[c] += log(s.norm2[c]);
+    if (u.is_gate) s.logw[c] += log(n2);
     s.discarded[c] += (total - kept) / total;
     s.knew[c] = k;
     kk_s = k;
@@ -693,7 +709,8 @@ void launch_theta(const Batch &b, const UpdScratch &s, const UpdParams &u,
 
 void launch_theta_norm(const Batch &b, const UpdScratch &s,
                        const UpdParams &u, hipStream_t st) {
-  hipLaunchKernelGGL(k_theta_norm, dim3(b.B), dim3(NT), 0, st, b, s, u);
+  hipLaunchKernelGGL(k_theta_norm, dim3(NORM_SPLIT, b.B), dim3(NT), 0, st, b,
+                     s, u);
 }
 
 void launch_pad(const Batch &b, const UpdScratch &s, const UpdParams &u,

@@ -1,5 +1,6 @@
-"""Mixed precision (FP32 theta contraction and gate on the matrix cores,
-FP64 SVD, truncation, norms and observables) against the FP64 oracle.
+"""Mixed precision (FP32 theta contraction and gate on the matrix cores; on
+the QR path an FP32 Jacobi stage and an FP64 Rayleigh-Ritz step; FP64
+truncation, norms and observables) against the FP64 oracle.
 
 Chains in the two precisions diverge once a collapse probability differs in
 its last bits, so they are compared teacher-forced: from the same initial

@@ -35,10 +35,12 @@ pytestmark = pytest.mark.gpu
 
 FP64 = {"spectrum": 1e-12, "logw": 1e-12, "theta": 1e-9,
         "free_energy_rel": 1e-10, "free_ss": 1e-10}
-# mixed precision, frozen at 3x the largest deviations measured on MI355X
-# on this window (spectrum 7.6e-8, log w 1.3e-7, T_k T_k+1 7.7e-8, energy
-# after the free-running window 4.6e-8 relative, <S.S> 3.2e-7)
-MIXED = {"spectrum": 2.5e-7, "logw": 4e-7, "theta": 2.5e-7,
+# mixed precision (FP32 theta and gate; FP32 Jacobi stage and FP64 Ritz
+# step of the SVD), frozen at 3x the largest deviations measured on MI355X
+# on this window over both designs of the mixed SVD (spectrum 7.6e-8, log w
+# 1.4e-7, T_k T_k+1 8.4e-8, energy after the free-running window 4.6e-8
+# relative, <S.S> 3.2e-7)
+MIXED = {"spectrum": 2.5e-7, "logw": 4.5e-7, "theta": 2.6e-7,
          "free_energy_rel": 1.5e-7, "free_ss": 1e-6}
 MEASURE_E_REL = 1e-10
 MEASURE_SS = 1e-10
@@ -114,7 +116,9 @@ def run_window(L, W, J_rung, beta, tau, chi, cut, t0, free, forced,
         gs = sig[0, :k] / math.sqrt(float(np.sum(sig[0, :k] ** 2)))
         lw = gpu_logw(ctx)
         # a cut within 1e-12 of the cutoff threshold may land either way
-        if ost.min_margin > 1e-12:
+        # (mixed precision: within the relative accuracy of its Ritz values)
+        margin = 1e-12 if precision == hmps.PREC_FP64 else 1e-3
+        if ost.min_margin > margin:
             assert k == len(S), (t, k, len(S))
         ranks.append(k)
         kk = min(k, len(S))
