@@ -337,7 +337,7 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
  * capture, tight serving loops, harnesses that forbid allocation): the
  * truncated SVD of hmps_svd_probe without a context, on caller-owned
  * device arrays, every intermediate in one file-scope device array of the
- * library (4.4 MiB per device, held until the process ends).  It allocates
+ * library (5.4 MiB per device, held until the process ends).  It allocates
  * nothing: no device memory, no events, no pinned memory.
  *   device, stream: the HIP device ordinal and a hipStream_t on it (NULL
  *     = the null stream); work is enqueued on the stream.

@@ -259,14 +259,15 @@ struct hmps_ctx {
   // products on vector lanes, so beyond a few thousand entries the blocked
   // MFMA rounds win even at a single chain (at most SMALL_LDS).
   size_t small_max = 2048;
-  // Householder QR preconditioning of the blocked rounds (HMPS_QR=0 turns
-  // it off, for measurements): on the chi = 256 gate workload it cuts the
-  // sweeps per update from about 30 to about 14.
-  int precond = 1;
+  // Householder QR preconditioning of the blocked rounds: 0 none, 1 one QR,
+  // 2 two (FP64 chains; HMPS_QR=0/1/2, for measurements).  On the chi =
+  // 256 gate workload one QR cuts the sweeps per update from about 30 to
+  // about 14.
+  int precond = 2;
   bool skip_theta = false;  // hmps_svd_probe: theta' is placed by the host
   // device buffers (carved from the workspace)
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
-  int n_cap = 0, slots = 0;
+  int n_cap = 0, slots = 0, qr_panels = 0;
   double *d_sites = nullptr, *d_TH = nullptr, *d_X = nullptr,
          *d_Y = nullptr, *d_Z = nullptr, *d_qrT = nullptr, *d_norm2 = nullptr,
          *d_sig2 = nullptr, *d_sig = nullptr, *d_fac = nullptr,
@@ -328,7 +329,9 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_X = cv.take<double>(B * th_stride);
   t->d_Y = cv.take<double>(B * th_stride);
   t->d_Z = cv.take<double>(B * th_stride);
-  t->d_qrT = cv.take<double>(B * QB * QB);
+  // T factors of every panel of both QR stages
+  t->qr_panels = (mc + QB - 1) / QB;
+  t->d_qrT = cv.take<double>(B * 2 * t->qr_panels * QB * QB);
   t->d_sig2 = cv.take<double>(B * n_cap);
   t->d_sig = cv.take<double>(B * n_cap);
   t->d_perm = cv.take<int32_t>(B * n_cap);
@@ -413,6 +416,7 @@ UpdScratch scratch_of(hmps_ctx *ctx) {
   s.Y = ctx->d_Y;
   s.Z = ctx->d_Z;
   s.qrT = ctx->d_qrT;
+  s.qr_panels = ctx->qr_panels;
   s.th_stride = ctx->th_stride;
   s.sig2 = ctx->d_sig2;
   s.perm = ctx->d_perm;
@@ -471,9 +475,9 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   // each chain's SVD runs in LDS when its theta' has at most small_max
   // entries, else on the blocked rounds; the rounds' grid is sized by the
   // blocked chains alone
-  int n_small = 0, n_blocked = 0, n_qr = 0, n_rr = 0;
+  int n_small = 0, n_blocked = 0, n_qr = 0, n_rr = 0, n_qr2 = 0;
   int max_nb = 2, max_nb32 = 2, max_vlen = 1, max_nvec = 1, max_qr_n = 0;
-  int max_rr_n = 0, max_rr_l = 0;
+  int max_rr_n = 0, max_rr_l = 0, max_qr2_n = 0;
   double flops = 0.0, svd_flops = 0.0;
   const bool is_move = (op == OP_IDENT);
   // centre moves are exact gauge changes: always FP64
@@ -511,9 +515,13 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       } else {
         max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
       }
-      if (path >= PATH_QR) {
+      if (path_has_qr(path)) {
         ++n_qr;
         max_qr_n = std::max(max_qr_n, nvec);
+      }
+      if (path == PATH_QR2) {
+        ++n_qr2;
+        max_qr2_n = std::max(max_qr2_n, nvec);
       }
     }
   }
@@ -557,13 +565,16 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   if (n_blocked > 0) {
     launch_pad(b, s, u, st);
     if (n_qr > 0) {
-      // theta' = Q R panel by panel, then R^T into the vector buffer
+      // theta' = Q R panel by panel, then R^T into the vector buffer; on
+      // the two-QR path R^T = Q2 R2 the same way, and R2^T into Z
       const int panels = (max_qr_n + QB - 1) / QB;
-      for (int p = 0; p < panels; ++p) {
-        launch_qr_panel(b, s, u, p, st);
-        launch_qr_update(b, s, u, p, panels - 1 - p, st);
+      for (int stage = 0; stage < (n_qr2 > 0 ? 2 : 1); ++stage) {
+        for (int p = 0; p < panels; ++p) {
+          launch_qr_panel(b, s, u, stage, p, st);
+          launch_qr_update(b, s, u, stage, p, panels - 1 - p, st);
+        }
+        launch_qr_to_vectors(b, s, u, stage, max_qr_n, st);
       }
-      launch_qr_to_vectors(b, s, u, max_qr_n, st);
       LAUNCHCHK(ctx);
     }
     // Sweep s is enqueued before the host waits for the rotation count of
@@ -609,8 +620,8 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
         if (f32) {
           vlen = nvec;
           esz = 4.0;
-        } else if (path == PATH_QR) {
-          vlen = nvec;  // R^T
+        } else if (path == PATH_QR || path == PATH_QR2) {
+          vlen = nvec;  // R^T or R2^T
         } else if (path == PATH_RR) {
           nv = rr_vectors(nvec, chi_max);
         }
@@ -672,7 +683,8 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   launch_truncate(b, s, u, st);
   LAUNCHCHK(ctx);
   const int kmax = std::max(1, std::min(u.chi_max, max_nvec));
-  launch_writeback(b, s, u, max_vlen, max_nvec, kmax, st);
+  launch_writeback(b, s, u, max_vlen, max_nvec, kmax,
+                   (max_qr2_n + QB - 1) / QB, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_knew, sizeof(int32_t) * ctx->B,
                         hipMemcpyDeviceToHost, st));
@@ -778,7 +790,8 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
   if (const char *e = std::getenv("HMPS_INNER")) ctx->inner_sweeps = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("HMPS_SKIP")) ctx->skip = std::min(1e-26, std::atof(e));
   if (const char *e = std::getenv("HMPS_CROSS")) ctx->cross_inner = e[0] == '1';
-  if (const char *e = std::getenv("HMPS_QR")) ctx->precond = e[0] != '0';
+  if (const char *e = std::getenv("HMPS_QR"))
+    ctx->precond = std::max(0, std::min(2, std::atoi(e)));
   if (const char *e = std::getenv("HMPS_SMALL_MAX"))
     ctx->small_max = std::min<size_t>(SMALL_LDS, std::strtoull(e, nullptr, 10));
   int current = -1;

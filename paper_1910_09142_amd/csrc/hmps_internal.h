@@ -53,16 +53,29 @@ __host__ __device__ inline bool qr_path(int L, int N, size_t small_max,
                                         int precond) {
   return precond && !small_path(L, N, small_max) && L <= QR_MAX_L;
 }
-// Paths of a chain's SVD.  PATH_RR (mixed precision, on chains that take
-// the QR): Jacobi rounds on an FP32 copy of R^T, then the rr_vectors
-// largest of its converged vectors, orthonormalised in FP64, give the basis
-// W of a Rayleigh-Ritz step: FP64 rounds on the columns of theta' W.
-enum { PATH_SMALL = 0, PATH_PLAIN = 1, PATH_QR = 2, PATH_RR = 3 };
+// Paths of a chain's SVD.
+//   PATH_QR   Jacobi rounds on R^T of theta' = Q R (precond >= 1).
+//   PATH_QR2  (precond >= 2, FP64) a second QR, R^T = Q2 R2, and the rounds
+//             on R2^T: its columns are closer still to orthogonal, so fewer
+//             sweeps are needed.  R2^T = (Q^T U) Sigma (Q2^T V)^T, so the
+//             converged vectors are the left singular vectors in the basis
+//             of Q; both factors then follow by projection (see update.hip).
+//   PATH_RR   (mixed precision, on chains that take the QR) Jacobi rounds
+//             on an FP32 copy of R^T, then the rr_vectors largest of its
+//             converged vectors, orthonormalised in FP64, give the basis W
+//             of a Rayleigh-Ritz step: FP64 rounds on the columns of
+//             theta' W.
+enum { PATH_SMALL = 0, PATH_PLAIN = 1, PATH_QR = 2, PATH_RR = 3, PATH_QR2 = 4 };
 __host__ __device__ inline int svd_path(int L, int N, size_t small_max,
                                         int precond, int mixed) {
   if (small_path(L, N, small_max)) return PATH_SMALL;
-  if (qr_path(L, N, small_max, precond)) return mixed ? PATH_RR : PATH_QR;
+  if (qr_path(L, N, small_max, precond))
+    return mixed ? PATH_RR : (precond >= 2 ? PATH_QR2 : PATH_QR);
   return PATH_PLAIN;
+}
+// The paths whose first step is theta' = Q R.
+__host__ __device__ inline bool path_has_qr(int path) {
+  return path == PATH_QR || path == PATH_RR || path == PATH_QR2;
 }
 // Largest Ritz basis: chi_max plus 64 (at least 64 vectors beyond the
 // cut), rounded to 32, at most N.  The basis holds only the vectors the
@@ -91,8 +104,12 @@ struct UpdScratch {
   double *TH;         // [B][th_stride]
   double *X;          // [B][th_stride]
   double *Y;          // [B][th_stride] R^T of the QR path (the vectors)
-  double *qrT;        // [B][QB * QB] compact-WY factor of the last panel
-  double *Z;          // [B][th_stride] Gram of the mixed path's basis
+  double *qrT;        // [B][2][qr_panels][QB * QB] compact-WY factors of
+                      // every panel of both QR stages
+  int qr_panels;      // panels per stage: ceil(3 chi_cap / QB)
+  double *Z;          // [B][th_stride] R2^T of PATH_QR2 (its vectors),
+                      // Gram of the mixed path's basis, Grams of the
+                      // write-back
   size_t th_stride;
   double *sig2;       // [B][n_cap] squared column norms after convergence
   int32_t *perm;      // [B][n_cap] kept columns, largest singular value first
@@ -110,6 +127,12 @@ struct UpdScratch {
   int32_t *rrk;       // [B] Ritz basis size of the mixed path (<= rr_vectors)
 };
 
+// T factor of panel p of QR stage `stage` of chain c.
+__host__ __device__ inline double *qrT_slot(const UpdScratch &s, int c,
+                                            int stage, int p) {
+  return s.qrT + ((size_t)(2 * c + stage) * s.qr_panels + p) * QB * QB;
+}
+
 struct UpdParams {
   int k;              // left site of the update
   const double *gate; // 81 doubles on the device (row-major (s1 s2),(t1 t2))
@@ -125,7 +148,8 @@ struct UpdParams {
   double skip;        // relative squared norm below which a vector is zero
   double skip32;      // the same for the FP32 rounds
   int cross_inner;    // inner rotations across the two blocks only (rounds > 0)
-  int precond;        // QR preconditioning of the blocked path
+  int precond;        // QR preconditioning of the blocked path: 0 none,
+                      // 1 one QR, 2 two (FP64)
   size_t small_max;   // largest L * N of the in-LDS SVD path
 };
 
@@ -148,16 +172,27 @@ void launch_jacobi_round32(const Batch &b, const UpdScratch &s,
                            hipStream_t st);
 void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
                      hipStream_t st);
+// qr2_panels: panels of the largest PATH_QR2 chain (0: none)
 void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                      int max_L, int max_N, int max_k, hipStream_t st);
-// QR preconditioning (qr.hip): panel p of every QR-path chain, the update
-// of its trailing columns (max_tiles 16-column tiles), and R^T into Y.
+                      int max_L, int max_N, int max_k, int qr2_panels,
+                      hipStream_t st);
+// QR preconditioning (qr.hip).  Stage 0: theta' = Q R on every chain
+// whose path starts with a QR (the vector matrix in X), R^T into Y.
+// Stage 1: R^T = Q2 R2 on the PATH_QR2 chains (in Y), R2^T into Z.  Panel
+// p, the update of its trailing columns (max_tiles 16-column tiles), and
+// the transposed factor into the vector buffer.
 void launch_qr_panel(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                     int p, hipStream_t st);
+                     int stage, int p, hipStream_t st);
 void launch_qr_update(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                      int p, int max_tiles, hipStream_t st);
+                      int stage, int p, int max_tiles, hipStream_t st);
 void launch_qr_to_vectors(const Batch &b, const UpdScratch &s,
-                          const UpdParams &u, int max_N, hipStream_t st);
+                          const UpdParams &u, int stage, int max_N,
+                          hipStream_t st);
+// The first QR's block reflector of panel p applied to the k unit vectors
+// held in TH of every PATH_QR2 chain (max_tiles 16-column tiles): panels
+// from last to first give Q u~ (the left factor on the two-QR path).
+void launch_qr_apply(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                     int p, int max_tiles, hipStream_t st);
 // Mixed path (rr.hip): R^T to FP32 before the FP32 rounds; after them the
 // FP64 Ritz basis W and theta' W into X for the FP64 rounds.
 void launch_rr_to32(const Batch &b, const UpdScratch &s, const UpdParams &u,

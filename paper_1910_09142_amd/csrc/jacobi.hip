@@ -3,8 +3,8 @@
 // Chen & Stoudenmire, arXiv:1910.09142, Results section).
 //
 // The N vectors (columns of the L x N vector matrix X -- or, on the QR
-// path, of the N x N matrix R^T in Y -- stride ld = L rounded up to 16,
-// column-major) are split into NB (even) blocks of
+// paths, of the N x N matrix R^T in Y or R2^T in Z -- stride ld = L
+// rounded up to 16, column-major) are split into NB (even) blocks of
 // JB = 16 vectors.  A sweep has NB-1 rounds; in a round the blocks are
 // paired by the circle method and one workgroup of eight wavefronts handles
 // one block pair of one chain:
@@ -182,18 +182,21 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   const int Lt = m > n ? m : n, N = m > n ? n : m;
   const int path = svd_path(Lt, N, u.small_max, u.precond, u.mixed);
   // the vector matrix of the chain's path: R^T (length N) in Y on the QR
-  // path; on the mixed path its FP32 copy in X (first stage), then the
-  // rrk columns of theta' W in X (second stage); theta' in X else
+  // path, R2^T (length N) in Z on the two-QR path; on the mixed path the
+  // FP32 copy of R^T in X (first stage), then the rrk columns of theta' W
+  // in X (second stage); theta' in X else
   if (F32 && path != PATH_RR) return;
-  const int L = (F32 || path == PATH_QR) ? N : Lt;
+  const int L = (F32 || path == PATH_QR || path == PATH_QR2) ? N : Lt;
   const int nvec = (!F32 && path == PATH_RR) ? s.rrk[c] : N;
   const int NB = n_blocks_even(nvec, JB);
   if (r >= NB - 1 || pi >= NB / 2) return;
   const int ld = vec_ld(L);
   int bi, bj;
   rr_pair(r, pi, NB, bi, bj);
-  T *X = reinterpret_cast<T *>((!F32 && path == PATH_QR) ? s.Y : s.X) +
-         (size_t)c * (F32 ? 2 : 1) * s.th_stride;
+  double *base = F32 ? s.X
+                     : (path == PATH_QR ? s.Y
+                                        : (path == PATH_QR2 ? s.Z : s.X));
+  T *X = reinterpret_cast<T *>(base) + (size_t)c * (F32 ? 2 : 1) * s.th_stride;
   const double tol = F32 ? u.tol32 : u.tol;
   const double skip = F32 ? u.skip32 : u.skip;
   auto colidx = [&](int t) { return t < JB ? bi * JB + t : bj * JB + t - JB; };

@@ -24,16 +24,18 @@ constexpr int NA_NCAP = (NA_MC + 2 * JB - 1) / (2 * JB) * (2 * JB);
 constexpr size_t NA_STRIDE = (size_t)((NA_MC + 15) & ~15) * NA_NCAP;
 constexpr size_t NA_SITE = (size_t)3 * NA_CHI * NA_CHI;
 constexpr size_t na_al(size_t doubles) { return (doubles + 31) / 32 * 32; }
+constexpr int NA_QRP = (NA_MC + QB - 1) / QB;  // QR panels per stage
 // layout in doubles, every piece 256-byte aligned
 constexpr size_t OFF_TH = 0;
 constexpr size_t OFF_X = OFF_TH + na_al(NA_STRIDE);
 constexpr size_t OFF_Y = OFF_X + na_al(NA_STRIDE);
-constexpr size_t OFF_SITES = OFF_Y + na_al(NA_STRIDE);
+constexpr size_t OFF_Z = OFF_Y + na_al(NA_STRIDE);
+constexpr size_t OFF_SITES = OFF_Z + na_al(NA_STRIDE);
 constexpr size_t OFF_SIG2 = OFF_SITES + na_al(2 * NA_SITE);
 constexpr size_t OFF_SIG = OFF_SIG2 + na_al(NA_NCAP);
 constexpr size_t OFF_QRT = OFF_SIG + na_al(NA_NCAP);
 // fac, norm2[NORM_SPLIT], logw, disc
-constexpr size_t OFF_F = OFF_QRT + na_al(QB * QB);
+constexpr size_t OFF_F = OFF_QRT + na_al(2 * NA_QRP * QB * QB);
 constexpr size_t OFF_I = OFF_F + na_al(3 + NORM_SPLIT);  // int32 area
 // int32 area (in int32 units from OFF_I): chi[3], knew, err, rot, done,
 // sweeps, perm[NA_NCAP]
@@ -41,7 +43,7 @@ constexpr size_t I_CHI = 0, I_KNEW = 4, I_ERR = 5, I_ROT = 6, I_DONE = 7,
                  I_SWEEPS = 8, I_PERM = 16;
 constexpr size_t NA_DOUBLES = OFF_I + na_al((I_PERM + NA_NCAP + 1) / 2);
 
-// The scratch buffer: 4.4 MiB on every device the library runs on, held
+// The scratch buffer: 5.4 MiB on every device the library runs on, held
 // until the process ends and shared by every call on that device.
 static __device__ __align__(256) double scratch[NA_DOUBLES];
 
@@ -140,7 +142,8 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   s.X = base + OFF_X;
   s.Y = base + OFF_Y;
   s.qrT = base + OFF_QRT;
-  s.Z = nullptr;  // the mixed path is never taken here
+  s.qr_panels = NA_QRP;
+  s.Z = base + OFF_Z;
   s.th_stride = NA_STRIDE;
   s.sig2 = base + OFF_SIG2;
   s.perm = iv + I_PERM;
@@ -173,7 +176,7 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   u.inner_sweeps = 1;
   u.skip = 1e-30;
   u.cross_inner = 1;
-  u.precond = 1;
+  u.precond = 2;
   u.small_max = 2048;
   hipLaunchKernelGGL(k_na_setup, dim3(64), dim3(256), 0, st, theta, chi_l,
                      chi_r, base);
@@ -181,13 +184,16 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
     launch_jacobi_small_upto(b, s, u, u.small_max, st);
   } else {
     launch_pad(b, s, u, st);
-    if (qr_path(L, N, u.small_max, u.precond)) {
+    const int path = svd_path(L, N, u.small_max, u.precond, u.mixed);
+    if (path_has_qr(path)) {
       const int panels = (N + QB - 1) / QB;
-      for (int p = 0; p < panels; ++p) {
-        launch_qr_panel(b, s, u, p, st);
-        launch_qr_update(b, s, u, p, panels - 1 - p, st);
+      for (int stage = 0; stage < (path == PATH_QR2 ? 2 : 1); ++stage) {
+        for (int p = 0; p < panels; ++p) {
+          launch_qr_panel(b, s, u, stage, p, st);
+          launch_qr_update(b, s, u, stage, p, panels - 1 - p, st);
+        }
+        launch_qr_to_vectors(b, s, u, stage, N, st);
       }
-      launch_qr_to_vectors(b, s, u, N, st);
     }
     // a fixed sequence of max_sweeps sweeps: once a sweep rotates nothing
     // the next sweep start marks the chain done and its rounds exit at once
@@ -200,7 +206,9 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   }
   launch_truncate(b, s, u, st);
   const int kmax = std::max(1, std::min(chi_max, N));
-  launch_writeback(b, s, u, L, N, kmax, st);
+  const bool qr2 =
+      svd_path(L, N, u.small_max, u.precond, u.mixed) == PATH_QR2;
+  launch_writeback(b, s, u, L, N, kmax, qr2 ? (N + QB - 1) / QB : 0, st);
   if (hipGetLastError() != hipSuccess) return HMPS_E_DEVICE;
   int32_t flags[3] = {0, 0, 0};  // knew, err, done
   if (hipMemcpyAsync(flags, iv + I_KNEW, sizeof(int32_t) * 2,

@@ -12,33 +12,60 @@
 // right singular vectors W of M scaled by Sigma, and the left ones follow
 // as M W / Sigma, so Q itself is never formed.
 //
+// A second factorization R^T = Q2 R2 (PATH_QR2) brings the columns of
+// R2^T closer still to orthogonal; the same kernels run on R^T in Y
+// (stage 1) after the first QR of the vector matrix in X (stage 0).
+//
 //   k_qr_panel      Householder reflectors of one 16-column panel, the
-//                   panel held in LDS; the compact-WY factor T with
-//                   H_1 ... H_16 = I - V T V^T, T^{-1} = striu(V^T V) +
-//                   diag(1 / tau) (Joffrain et al., ACM TOMS 32 (2006))
+//                   panel rows held in registers; the compact-WY factor T
+//                   with H_1 ... H_16 = I - V T V^T (T column by column,
+//                   as in LAPACK's dlarft)
 //   k_qr_update     trailing columns C <- C - V T^T (V^T C) on the FP64
 //                   matrix cores, one 16-column tile per workgroup
-//   k_qr_to_vectors R^T into the vector buffer Y, zero padding included
+//   k_qr_to_vectors R^T into the vector buffer (Y, or Z after stage 1),
+//                   zero padding included
 #include "device_common.h"
 
 namespace hmps {
 namespace {
 using namespace dev;
 
-constexpr int PT = 256;  // threads of the QR kernels (4 wavefronts)
+constexpr int PT = 256;   // threads of the update and transpose kernels
+constexpr int QPT = 512;  // threads of the panel kernel (8 wavefronts)
+// panel rows per thread of the panel kernel
+constexpr int RPT = (QR_MAX_L + QPT - 1) / QPT;
 
+// The matrix a stage factors (column-major, stride ld, L x N) and where
+// its transposed triangular factor goes.
 struct QDims {
   int L, N, ld, qr;
+  double *M;    // the matrix, factored in place
+  double *out;  // R^T as N vectors of length N (stride vec_ld(N))
 };
 
-__device__ __forceinline__ QDims qdims(const Batch &b, int c, const UpdParams &u) {
+__device__ __forceinline__ QDims qdims(const Batch &b, int c,
+                                       const UpdParams &u,
+                                       const UpdScratch &s, int stage) {
   const int32_t *chi = chi_row(b, c);
   const int m = 3 * chi[u.k], n = 3 * chi[u.k + 2];
+  const int Lt = m > n ? m : n;
+  const int path = svd_path(Lt, m > n ? n : m, u.small_max, u.precond,
+                            u.mixed);
   QDims d;
-  d.L = m > n ? m : n;
   d.N = m > n ? n : m;
+  const size_t off = (size_t)c * s.th_stride;
+  if (stage == 0) {
+    d.L = Lt;
+    d.qr = path_has_qr(path);
+    d.M = s.X + off;
+    d.out = s.Y + off;
+  } else {
+    d.L = d.N;
+    d.qr = path == PATH_QR2;
+    d.M = s.Y + off;
+    d.out = s.Z + off;
+  }
   d.ld = vec_ld(d.L);
-  d.qr = qr_path(d.L, d.N, u.small_max, u.precond);
   return d;
 }
 
@@ -71,149 +98,169 @@ __device__ __forceinline__ double wave_sum16(double (&v)[16]) {
   return x;
 }
 
-// Sum of one value over the workgroup, every thread gets the result; the
-// four wave sums are added in a fixed order.
-__device__ __forceinline__ double block_sum1(double v, double *red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// Sums of 16 values over the workgroup into out[16] (LDS, every thread may
-// read it after the call).
-__device__ __forceinline__ void block_sum16(double (&v)[16], double *red,
-                                            double *out) {
-  const double x = wave_sum16(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((lane & 3) == 0) red[w * 16 + (lane >> 2)] = x;
-  __syncthreads();
-  if (threadIdx.x < 16) {
-    const int t = threadIdx.x;
-    out[t] = (red[t] + red[16 + t]) + (red[32 + t] + red[48 + t]);
-  }
-  __syncthreads();
-}
-
 // =====================================================================
 // Panel p: columns j0 .. j0 + w - 1 (j0 = 16 p) of M, rows j0 .. L - 1.
 // Column t of the panel (global column j = j0 + t): with x its rows j..L-1,
-// alpha = x_0, beta = -sign(alpha) ||x||, v = x / (alpha - beta) with v_0 =
-// 1, tau = (beta - alpha) / beta, so that (I - tau v v^T) x = beta e_0.
-// R_jj = beta; v_1.. are stored below the diagonal.  The same reduction
-// that applies the reflector to the later panel columns (v^T a_t', t' > t)
-// yields V^T v for the earlier ones, which builds T column by column:
-// T[0:t, t] = -tau_t T[0:t, 0:t] (V[:, 0:t]^T v_t), T[t][t] = tau_t.
+// alpha = x_0, beta = -sign(alpha) ||x||, v = (x - beta e_0) / (alpha -
+// beta) (so v_0 = 1), tau = (beta - alpha) / beta, and (I - tau v v^T) x =
+// beta e_0.  R_jj = beta; v_1.. are stored below the diagonal.
+// Thread i holds panel rows i, i + 512, i + 1024 of all 16 columns in
+// registers.  One reduction per column gives every product the column
+// needs: d_q = x^T y_q over rows t.. with y_q the later panel columns
+// (q > t), the earlier reflectors (q < t) and x itself (q = t, ||x||^2).
+// Since v = (x - beta e_0) / (alpha - beta), v^T y_q = (d_q - beta y_q[t])
+// / (alpha - beta); sign(-beta) = sign(alpha), so nothing cancels.  These
+// reflect the later columns, a_q -= tau v (v^T a_q), and build T column by
+// column: T[0:t, t] = -tau T[0:t, 0:t] (V[:, 0:t]^T v_t), T[t][t] = tau.
+// The eight wavefront partials are summed in a fixed order.
 // =====================================================================
-__global__ void __launch_bounds__(PT) k_qr_panel(Batch b, UpdScratch s,
-                                                 UpdParams u, int p) {
+__global__ void __launch_bounds__(QPT) k_qr_panel(Batch b, UpdScratch s,
+                                                  UpdParams u, int stage,
+                                                  int p) {
   const int c = blockIdx.x;
-  const QDims d = qdims(b, c, u);
+  const QDims d = qdims(b, c, u, s, stage);
   const int j0 = QB * p;
   if (!d.qr || j0 >= d.N) return;
   const int w = min(QB, d.N - j0);
   const int rows = d.L - j0;  // panel rows j0 .. L-1
-  double *X = s.X + (size_t)c * s.th_stride;
-  __shared__ double P[QB * QR_MAX_L];  // column t at P + t * rows
-  __shared__ double red[64];
+  double *M = d.M;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  __shared__ double red[(QPT / 64) * QB];
   __shared__ double dots[QB];
-  __shared__ double T[QB][QB];
-  const int tid = threadIdx.x;
-  for (int t = 0; t < QB; ++t)
-    for (int r = tid; r < rows; r += PT)
-      P[t * rows + r] = t < w ? X[(size_t)(j0 + t) * d.ld + j0 + r] : 0.0;
-  if (tid < QB * QB) T[tid / QB][tid % QB] = 0.0;
-  __syncthreads();
-  for (int t = 0; t < w; ++t) {
-    // ||x||^2 over panel rows t .. rows-1 of column t, and alpha
-    double *col = P + t * rows;
-    double part = 0.0;
-    for (int r = t + tid; r < rows; r += PT) part += col[r] * col[r];
-    const double s2 = block_sum1(part, red);
-    const double alpha = col[t];
-    double tau = 0.0, scale = 0.0, beta = alpha;
-    if (s2 > 0.0) {
-      beta = -copysign(sqrt(s2), alpha);
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    __syncthreads();  // every thread has read col[t] as alpha
-    for (int r = t + 1 + tid; r < rows; r += PT) col[r] *= scale;
-    if (tid == 0) col[t] = beta;
-    __syncthreads();
-    // dots[t'] = v_t^T (panel column t') over rows t.. : for t' > t the
-    // current column (to be reflected), for t' < t the reflector v_t'
-    // (zero above its row t', one at it)
-    double acc[QB];
+  __shared__ double yt[QB];  // row t of the panel (the y_q[t])
+  __shared__ double T[QB][QB + 1];
+  double a[RPT][QB];
+  // loads with clamped addresses and a select (no branch around a load)
 #pragma unroll
-    for (int q = 0; q < QB; ++q) acc[q] = 0.0;
-    for (int r = t + tid; r < rows; r += PT) {
-      const double vr = r == t ? 1.0 : col[r];
+  for (int i = 0; i < RPT; ++i) {
+    const int r = tid + QPT * i;
+    const int rr = r < rows ? r : rows - 1;
 #pragma unroll
-      for (int q = 0; q < QB; ++q) {
-        double a;
-        if (q < t)
-          a = r > q ? P[q * rows + r] : (r == q ? 1.0 : 0.0);
-        else if (q > t && q < w)
-          a = P[q * rows + r];
-        else
-          a = 0.0;
-        acc[q] += vr * a;
-      }
+    for (int q = 0; q < QB; ++q) {
+      const int qq = q < w ? q : w - 1;
+      const double x = M[(size_t)(j0 + qq) * d.ld + j0 + rr];
+      a[i][q] = (r < rows && q < w) ? x : 0.0;
     }
-    block_sum16(acc, red, dots);
-    // reflect the later columns: a_t' -= tau v (v^T a_t')
-    for (int r = t + tid; r < rows; r += PT) {
-      const double vr = r == t ? 1.0 : col[r];
-      for (int q = t + 1; q < w; ++q) P[q * rows + r] -= tau * vr * dots[q];
-    }
-    // T column t from the dots with the earlier reflectors, row i by
-    // thread i (each reads its own row of T, columns < t)
-    if (tid < t) {
-      double x = 0.0;
-      for (int q = tid; q < t; ++q) x += T[tid][q] * dots[q];
-      T[tid][t] = -tau * x;
-    }
-    if (tid == 0) T[t][t] = tau;
-    __syncthreads();
   }
-  for (int t = 0; t < w; ++t)
-    for (int r = tid; r < rows; r += PT)
-      X[(size_t)(j0 + t) * d.ld + j0 + r] = P[t * rows + r];
-  if (tid < QB * QB) s.qrT[(size_t)c * QB * QB + tid] = T[tid / QB][tid % QB];
+  if (tid < QB * QB) T[tid / QB][tid % QB] = 0.0;
+  // fully unrolled: every register index is a constant (w is uniform, so
+  // every thread takes the same branches and reaches the same barriers)
+#pragma unroll
+  for (int t = 0; t < QB; ++t) {
+    if (t < w) {
+      // row t is row 0 of thread t
+      if (tid == t) {
+#pragma unroll
+        for (int q = 0; q < QB; ++q) yt[q] = a[0][q];
+      }
+      double acc[QB];
+#pragma unroll
+      for (int q = 0; q < QB; ++q) acc[q] = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = tid + QPT * i;
+        const double x = r >= t ? a[i][t] : 0.0;
+#pragma unroll
+        for (int q = 0; q < QB; ++q) acc[q] = fma(x, a[i][q], acc[q]);
+      }
+      const double part = wave_sum16(acc);  // value lane >> 2
+      if ((lane & 3) == 0) red[wv * QB + (lane >> 2)] = part;
+      __syncthreads();
+      if (tid < QB) {
+        const double *rq = red + tid;
+        dots[tid] = ((rq[0] + rq[QB]) + (rq[2 * QB] + rq[3 * QB])) +
+                    ((rq[4 * QB] + rq[5 * QB]) + (rq[6 * QB] + rq[7 * QB]));
+      }
+      __syncthreads();
+      const double s2 = dots[t];
+      const double alpha = yt[t];
+      double tau = 0.0, scale = 0.0, beta = alpha;
+      if (s2 > 0.0) {
+        beta = -copysign(sqrt(s2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      // v^T y_q; with x = 0 the reflector is the identity and v = e_0
+      double vy[QB];
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+        vy[q] = s2 > 0.0 ? scale * (dots[q] - beta * yt[q]) : yt[q];
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = tid + QPT * i;
+        const double vr = r == t ? 1.0 : (r > t ? a[i][t] * scale : 0.0);
+#pragma unroll
+        for (int q = t + 1; q < QB; ++q)
+          a[i][q] = r >= t ? fma(-tau * vr, vy[q], a[i][q]) : a[i][q];
+        a[i][t] = r == t ? beta : (r > t ? vr : a[i][t]);
+      }
+      // T column t, row i by thread i (T[i][q] of the earlier columns)
+      if (tid < t) {
+        double x = 0.0;
+#pragma unroll
+        for (int q = 0; q < t; ++q) x += q >= tid ? T[tid][q] * vy[q] : 0.0;
+        T[tid][t] = -tau * x;
+      }
+      if (tid == t) T[t][t] = tau;
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = tid + QPT * i;
+    if (r < rows) {
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+        if (q < w) M[(size_t)(j0 + q) * d.ld + j0 + r] = a[i][q];
+    }
+  }
+  if (tid < QB * QB) qrT_slot(s, c, stage, p)[tid] = T[tid / QB][tid % QB];
 }
 
 // =====================================================================
 // Trailing update of panel p: tile x holds columns c0 = j0 + 16 + 16 x ..
 // c0 + 15 of M.  W = V^T C (16 x 16, FP64 MFMA over 16-row chunks, four
 // wavefront partials summed in a fixed order), W' = T^T W, C -= V W' (FP64
-// MFMA, computed transposed so that lanes store consecutive rows).  Only
-// rows j0 .. L-1 change; rows L .. ld-1 of M are zero and V is zero there.
+// MFMA, computed transposed so that lanes store consecutive rows): C <-
+// H_{16}^T .. H_1^T C.  Only rows j0 .. L-1 change; rows L .. ld-1 of M
+// are zero and V is zero there.
+// APPLY: the same block reflector, untransposed (W' = T W, C <- H_1 ..
+// H_16 C), on the k unit vectors in TH of a PATH_QR2 chain (length L,
+// stride ld, zero below row N): panels from last to first give Q u~.
 // =====================================================================
+template <bool APPLY>
 __global__ void __launch_bounds__(PT) k_qr_update(Batch b, UpdScratch s,
-                                                  UpdParams u, int p) {
+                                                  UpdParams u, int stage,
+                                                  int p) {
   const int c = blockIdx.y;
-  const QDims d = qdims(b, c, u);
+  const QDims d = qdims(b, c, u, s, stage);
   const int j0 = QB * p;
-  const int c0 = j0 + QB + QB * blockIdx.x;
-  if (!d.qr || c0 >= d.N) return;
+  int ncols = d.N, c0 = j0 + QB + QB * blockIdx.x;
+  double *C = d.M;
+  if (APPLY) {
+    const int path = svd_path(d.L, d.N, u.small_max, u.precond, u.mixed);
+    if (path != PATH_QR2) return;
+    ncols = s.knew[c];
+    c0 = QB * blockIdx.x;
+    C = s.TH + (size_t)c * s.th_stride;
+  } else if (!d.qr) {
+    return;
+  }
+  if (j0 >= d.N || c0 >= ncols) return;
   const int wcol = min(QB, d.N - j0);  // reflectors of this panel
-  double *X = s.X + (size_t)c * s.th_stride;
+  const double *X = d.M;
   const int ld = d.ld;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   __shared__ double Wp[4][QB][QB + 1];
   __shared__ double W2[QB][QB + 1];
   __shared__ double Ts[QB][QB + 1];
-  Ts[tid / QB][tid % QB] = s.qrT[(size_t)c * QB * QB + tid];
+  Ts[tid / QB][tid % QB] = qrT_slot(s, c, stage, p)[tid];
   // reflector t at row r: 0 above its diagonal row j0 + t, 1 on it
   const bool vcol_ok = li < wcol;
   const double *vcol = X + (size_t)(j0 + (vcol_ok ? li : 0)) * ld;
-  const bool ccol_ok = c0 + li < d.N;
-  const double *ccol = X + (size_t)(ccol_ok ? c0 + li : c0) * ld;
+  const bool ccol_ok = c0 + li < ncols;
+  const double *ccol = C + (size_t)(ccol_ok ? c0 + li : c0) * ld;
   auto vval = [&](int r, double x) -> double {
     const int dr = j0 + li;
     return !vcol_ok ? 0.0 : (r < dr ? 0.0 : (r == dr ? 1.0 : x));
@@ -239,10 +286,14 @@ __global__ void __launch_bounds__(PT) k_qr_update(Batch b, UpdScratch s,
   }
   __syncthreads();
   {
-    // W' = T^T W (T upper triangular)
+    // W' = T^T W or T W (T upper triangular)
     const int i = tid / QB, j = tid % QB;
     double x = 0.0;
-    for (int t = 0; t <= i; ++t) x += Ts[t][i] * Wp[0][t][j];
+    if (APPLY) {
+      for (int t = i; t < QB; ++t) x += Ts[i][t] * Wp[0][t][j];
+    } else {
+      for (int t = 0; t <= i; ++t) x += Ts[t][i] * Wp[0][t][j];
+    }
     W2[i][j] = x;
   }
   __syncthreads();
@@ -266,27 +317,28 @@ __global__ void __launch_bounds__(PT) k_qr_update(Batch b, UpdScratch s,
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int col = c0 + lk + 4 * q;
-      if (col < d.N && r < d.L) X[(size_t)col * ld + r] -= dd[q];
+      if (col < ncols && r < d.L) C[(size_t)col * ld + r] -= dd[q];
     }
   }
 }
 
 // =====================================================================
-// R^T into Y: vector i (row i of R) at Y + i * ldN, R[i][j] = M[j * ld + i]
-// for j >= i and 0 below; rows N .. ldN-1 and vectors N .. npad-1 zero.
-// One 16 x 16 tile per thread block, through LDS.
+// R^T into the stage's vector buffer: vector i (row i of R) at out + i *
+// ldN, R[i][j] = M[j * ld + i] for j >= i and 0 below; rows N .. ldN-1 and
+// vectors N .. npad-1 zero.  One 16 x 16 tile per thread block, through
+// LDS.
 // =====================================================================
 __global__ void __launch_bounds__(PT) k_qr_to_vectors(Batch b, UpdScratch s,
-                                                      UpdParams u) {
+                                                      UpdParams u, int stage) {
   const int c = blockIdx.z;
-  const QDims d = qdims(b, c, u);
+  const QDims d = qdims(b, c, u, s, stage);
   if (!d.qr) return;
   const int ldN = vec_ld(d.N);
   const int npad = n_blocks_even(d.N, JB) * JB;
   const int i0 = 16 * blockIdx.x, jj0 = 16 * blockIdx.y;  // vector, element
   if (i0 >= npad || jj0 >= ldN) return;
-  const double *X = s.X + (size_t)c * s.th_stride;
-  double *Y = s.Y + (size_t)c * s.th_stride;
+  const double *X = d.M;
+  double *Y = d.out;
   __shared__ double tile[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   {
@@ -302,22 +354,31 @@ __global__ void __launch_bounds__(PT) k_qr_to_vectors(Batch b, UpdScratch s,
 }  // namespace
 
 void launch_qr_panel(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                     int p, hipStream_t st) {
-  hipLaunchKernelGGL(k_qr_panel, dim3(b.B), dim3(PT), 0, st, b, s, u, p);
+                     int stage, int p, hipStream_t st) {
+  hipLaunchKernelGGL(k_qr_panel, dim3(b.B), dim3(QPT), 0, st, b, s, u, stage,
+                     p);
 }
 
 void launch_qr_update(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                      int p, int max_tiles, hipStream_t st) {
+                      int stage, int p, int max_tiles, hipStream_t st) {
   if (max_tiles <= 0) return;
-  hipLaunchKernelGGL(k_qr_update, dim3(max_tiles, b.B), dim3(PT), 0, st, b, s,
-                     u, p);
+  hipLaunchKernelGGL(k_qr_update<false>, dim3(max_tiles, b.B), dim3(PT), 0, st,
+                     b, s, u, stage, p);
+}
+
+void launch_qr_apply(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                     int p, int max_tiles, hipStream_t st) {
+  if (max_tiles <= 0) return;
+  hipLaunchKernelGGL(k_qr_update<true>, dim3(max_tiles, b.B), dim3(PT), 0, st,
+                     b, s, u, 0, p);
 }
 
 void launch_qr_to_vectors(const Batch &b, const UpdScratch &s,
-                          const UpdParams &u, int max_N, hipStream_t st) {
+                          const UpdParams &u, int stage, int max_N,
+                          hipStream_t st) {
   const int npad = n_blocks_even(max_N, JB) * JB;
   dim3 grid(npad / 16, vector_stride(max_N) / 16, b.B);
-  hipLaunchKernelGGL(k_qr_to_vectors, grid, dim3(PT), 0, st, b, s, u);
+  hipLaunchKernelGGL(k_qr_to_vectors, grid, dim3(PT), 0, st, b, s, u, stage);
 }
 
 }  // namespace hmps

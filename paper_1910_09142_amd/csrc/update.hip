@@ -36,16 +36,11 @@ struct Dims {
   int il_rows, il_cols;
 };
 
-// A chain on the QR path rotates R^T (N vectors of length N, in Y): its
+// A chain on a QR path rotates R^T (or R2^T; N vectors of length N): its
 // converged vectors lie on the other side of theta' than those of the
-// plain path (columns of M^T, see qr.hip), so the write-back swaps sides.
+// plain path (see qr.hip), so the write-back swaps sides.
 __device__ __forceinline__ int path_of(const Dims &d, const UpdParams &u) {
   return svd_path(d.L, d.N, u.small_max, u.precond, u.mixed);
-}
-// the write-back of the mixed path is that of the plain path (its vectors
-// are columns of theta' W, of length L, in X)
-__device__ __forceinline__ bool on_qr(const Dims &d, const UpdParams &u) {
-  return path_of(d, u) == PATH_QR;
 }
 __device__ __forceinline__ Dims vector_side(const Dims &d, bool qr) {
   Dims e = d;
@@ -223,7 +218,7 @@ __global__ void __launch_bounds__(NT) k_theta_norm(Batch b, UpdScratch s,
 __global__ void __launch_bounds__(NT) k_pad(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.y;
   const Dims d = dims_of(b, c, u.k);
-  const bool qr = path_of(d, u) >= PATH_QR;
+  const bool qr = path_has_qr(path_of(d, u));
   const int npad = n_blocks_even(d.N, JB) * JB;
   double *X = s.X + (size_t)c * s.th_stride;
   const int tail = d.ld - d.L;
@@ -490,12 +485,15 @@ __device__ __forceinline__ void store_other_side(const Batch &b, int c,
 }
 
 // Dims as they were before the truncation: chi[k+1] now holds knew, but
-// nothing here depends on the old middle dimension.
+// nothing here depends on the old middle dimension.  The two-QR path
+// writes both sides by projection (below).
 __global__ void __launch_bounds__(NT)
     k_writeback_direct(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.y;
   const Dims d = dims_of(b, c, u.k);
-  const bool qr = on_qr(d, u);
+  const int path = path_of(d, u);
+  if (path == PATH_QR2) return;
+  const bool qr = path == PATH_QR;
   const Dims e = vector_side(d, qr);
   const int vlen = qr ? d.N : d.L, vld = qr ? vec_ld(d.N) : d.ld;
   const int k = s.knew[c];
@@ -515,37 +513,86 @@ __global__ void __launch_bounds__(NT)
 // (theta' or its transpose as stored in TH), the unit singular vectors on
 // the other side are p_j = op(M) X_j / sigma_j^2: op(M) = M^T on the plain
 // path (X_j of length L, p_j of length N), op(M) = M on the QR path (X_j
-// = Y_j of length N, p_j of length L).  The projections are orthonormal
-// only to about eps sigma_0 / sigma_j, so they are corrected before they
-// are stored, to first order in E (G = P^T P = I + E) along the Cholesky
-// factor of G taken in the order of decreasing sigma: p_j <- p_j (1 - E_jj
-// / 2) - sum_{i<j} p_i E_ij.  Column j is made orthonormal against the
-// columns of larger singular value and never feeds back into them, so the
-// large rounding error of a tiny-sigma projection stays in that column
-// (where the state weighs it by sigma_j).
-//   k_other_project  P into a free buffer (Y on the plain path, X on the QR
-//                    path), column j at j * ldP, zero rows P_len .. ldP-1
-//   k_other_gram     G = P^T P into TH (free once P is formed), row-major
-//                    with stride round16(k), zero beyond k
-//   k_other_store    P (3 I - G) / 2, scaled, into the site tensor
+// = Y_j of length N, p_j of length L).  On the two-QR path the converged
+// vectors (in Z) are sigma_j u~_j with u~_j the left singular vectors in
+// the basis of Q (R = U~ Sigma W^T): the right ones are p_j = R^T u~_j /
+// sigma_j, from the R kept in the upper triangle of X, and the left ones
+// Q u~_j come from the stored reflectors (k_qr2_fill, the reflectors in
+// qr.hip, k_qr2_store_left).  A second projection, M p_j / sigma_j, would
+// amplify the residual error of p_j along the larger singular vectors by
+// sigma_0 / sigma_j.
+// The projections are orthonormal only to about eps sigma_0 / sigma_j, so
+// they are corrected before they are stored, to first order in E (G = P^T
+// P = I + E) along the Cholesky factor of G taken in the order of
+// decreasing sigma: p_j <- p_j (1 - E_jj / 2) - sum_{i<j} p_i E_ij.
+// Column j is made orthonormal against the columns of larger singular
+// value and never feeds back into them, so the large rounding error of a
+// tiny-sigma projection stays in that column (where the state weighs it by
+// sigma_j).
+//   k_other_project  P into a free buffer, column j at j * ldP, zero rows
+//                    P_len .. ldP-1
+//   k_other_gram     G = P^T P into a free buffer (row-major, stride
+//                    round16(k), zero beyond k)
+//   k_other_store    corrected, scaled P into the site tensor
 // All three on the FP64 matrix cores, one 16 x 16 tile per wavefront.
+enum { OM_PLAIN = 0, OM_QR, OM_QR2 };
 struct Other {
-  int qr, len, ldP, k, ldG;
+  int mode, len, ldP, k, ldG;
   double *P;
   double *G;
 };
 
 __device__ __forceinline__ Other other_of(const Dims &d, const UpdParams &u,
                                           const UpdScratch &s, int c) {
+  const int path = path_of(d, u);
   Other o;
-  o.qr = on_qr(d, u);
-  o.len = o.qr ? d.L : d.N;
+  o.mode = path == PATH_QR2 ? OM_QR2 : (path == PATH_QR ? OM_QR : OM_PLAIN);
+  o.len = o.mode == OM_QR ? d.L : d.N;
   o.ldP = vec_ld(o.len);
   o.k = s.knew[c];
   o.ldG = (o.k + 15) & ~15;
-  o.P = (o.qr ? s.X : s.Y) + (size_t)c * s.th_stride;
-  o.G = s.TH + (size_t)c * s.th_stride;
+  const size_t off = (size_t)c * s.th_stride;
+  o.P = (o.mode == OM_QR ? s.X : s.Y) + off;
+  o.G = (o.mode == OM_QR2 ? s.Z : s.TH) + off;
   return o;
+}
+
+// Two-QR path, left factor: u~_j = Z_pj / sigma_j into TH (length L, stride
+// ld, zero from row N), for the reflectors to turn into Q u~_j.
+__global__ void __launch_bounds__(NT)
+    k_qr2_fill(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.y;
+  const Dims d = dims_of(b, c, u.k);
+  if (path_of(d, u) != PATH_QR2) return;
+  const int k = s.knew[c];
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= d.ld * k) return;
+  const int r = t % d.ld, j = t / d.ld;
+  const int ldN = vec_ld(d.N);
+  const int pj = s.perm[(size_t)c * s.n_cap + j];
+  const double *z = s.Z + (size_t)c * s.th_stride + (size_t)pj * ldN;
+  const double v = r < d.N ? z[r] / s.sig[(size_t)c * s.n_cap + j] : 0.0;
+  s.TH[(size_t)c * s.th_stride + (size_t)j * d.ld + r] = v;
+}
+
+// Two-QR path: the left factor Q u~_j (in TH) into the site tensor, scaled
+// like the other side of the QR path.
+__global__ void __launch_bounds__(NT)
+    k_qr2_store_left(Batch b, UpdScratch s, UpdParams u) {
+  const int c = blockIdx.y;
+  const Dims d = dims_of(b, c, u.k);
+  if (path_of(d, u) != PATH_QR2) return;
+  const int k = s.knew[c];
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= d.L * k) return;
+  const int r = t % d.L, j = t / d.L;
+  const Dims e = vector_side(d, true);
+  const bool vec_center = (e.trans != 0) == (u.right != 0);
+  const double f = vec_center
+                       ? 1.0
+                       : s.fac[c] * s.sig[(size_t)c * s.n_cap + j];
+  store_other_side(b, c, u.k, e, k, r, j,
+                   f * s.TH[(size_t)c * s.th_stride + (size_t)j * d.ld + r]);
 }
 
 // P tile (rows r0 .. r0+15, vectors j0 .. j0+15) per wavefront.
@@ -563,7 +610,7 @@ __global__ void __launch_bounds__(NT)
   const bool jok = j0 + li < o.k;
   const int pj = perm[jok ? j0 + li : j0];
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  if (o.qr) {
+  if (o.mode == OM_QR) {
     // D[l][j] = sum_q M[l][q] Y[q][pj]: lane (li, lk) takes row r0 + li of
     // M (single coalesced loads per q) and q = q0 + 4 lk .. + 3 of Y_pj
     const int ldN = vec_ld(d.N);
@@ -586,18 +633,30 @@ __global__ void __launch_bounds__(NT)
       acc = mfma_f64(mv[3], jok ? yq.w : 0.0, acc);
     }
   } else {
-    // D[q][j] = sum_l M[l][q] X[l][pj]: both operands as aligned 32-byte
-    // loads of four consecutive l (rows L .. ld-1 of X are zero)
-    const double *xv = s.X + (size_t)c * s.th_stride + (size_t)pj * d.ld;
-    const bool qok = r0 + li < d.N;
-    const double *mcol = M + (size_t)(qok ? r0 + li : 0) * d.ld;
-    for (int l0 = 0; l0 < d.L; l0 += 16) {
+    // D[q][j] = sum_l A[l][q] V[l][pj]: both operands as aligned 32-byte
+    // loads of four consecutive l.  Plain path: A = M (column q of TH), V
+    // = X (length L, rows L .. ld-1 zero).  Two-QR path: A = R (column q
+    // of R is the upper part of column q of X: l <= q), V = the converged
+    // vectors in Z (length N).
+    const bool qr2 = o.mode == OM_QR2;
+    const int vlen = qr2 ? d.N : d.L, vld = qr2 ? vec_ld(d.N) : d.ld;
+    const double *xv = (qr2 ? s.Z : s.X) + (size_t)c * s.th_stride +
+                       (size_t)pj * vld;
+    const double *A = qr2 ? s.X + (size_t)c * s.th_stride : M;
+    const int qrow = r0 + li;
+    const bool qok = qrow < d.N;
+    const double *acol = A + (size_t)(qok ? qrow : 0) * d.ld;
+    // R is upper triangular: rows l <= r0 + 15 reach this tile
+    const int lend = qr2 ? min(vlen, r0 + 16) : vlen;
+    for (int l0 = 0; l0 < lend; l0 += 16) {
       const int lb = l0 + 4 * lk;
       const v4d xq = *reinterpret_cast<const v4d *>(xv + lb);
-      const v4d mq = *reinterpret_cast<const v4d *>(mcol + lb);
-      // rows L .. ld-1 of TH are not written by the update: mask them
-      const bool l0ok = lb < d.L, l1ok = lb + 1 < d.L, l2ok = lb + 2 < d.L,
-                 l3ok = lb + 3 < d.L;
+      const v4d mq = *reinterpret_cast<const v4d *>(acol + lb);
+      // rows L .. ld-1 of TH are not written by the update, and X holds
+      // the reflectors below the diagonal of R: mask them
+      const int lim = qr2 ? min(vlen - 1, qrow) : vlen - 1;
+      const bool l0ok = lb <= lim, l1ok = lb + 1 <= lim, l2ok = lb + 2 <= lim,
+                 l3ok = lb + 3 <= lim;
       acc = mfma_f64(qok && l0ok ? mq.x : 0.0, jok ? xq.x : 0.0, acc);
       acc = mfma_f64(qok && l1ok ? mq.y : 0.0, jok ? xq.y : 0.0, acc);
       acc = mfma_f64(qok && l2ok ? mq.z : 0.0, jok ? xq.z : 0.0, acc);
@@ -647,6 +706,7 @@ __global__ void __launch_bounds__(NT)
 // out[r][j] = P[r][j] (3 - G[j][j]) / 2 - sum_{i<j} P[r][i] G[i][j], times
 // 1 for an isometry or fac sigma_j for the centre; G is symmetric, so lane
 // (li, lk) loads G[j0 + li][i0 + 4 lk .. + 3] as one aligned 32-byte load.
+// The two-QR path stores this factor on its vector side.
 __global__ void __launch_bounds__(NT)
     k_other_store(Batch b, UpdScratch s, UpdParams u) {
   const int c = blockIdx.z;
@@ -680,10 +740,23 @@ __global__ void __launch_bounds__(NT)
   if (!jok) return;
   const int j = j0 + li;
   const double gjj = o.G[(size_t)j * o.ldG + j];
-  const Dims e = vector_side(d, o.qr);
+  const Dims e = vector_side(d, o.mode != OM_PLAIN);
   const bool vec_center = (e.trans != 0) == (u.right != 0);
-  const double f =
-      vec_center ? 1.0 : s.fac[c] * s.sig[(size_t)c * s.n_cap + j];
+  const double fsig = s.fac[c] * s.sig[(size_t)c * s.n_cap + j];
+  if (o.mode == OM_QR2) {
+    const double f = vec_center ? fsig : 1.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + lk + 4 * q;
+      if (r < o.len) {
+        const double pr = o.P[(size_t)j * o.ldP + r];
+        store_vector_side(b, c, u.k, e, o.k, r, j,
+                          f * (pr * (1.5 - 0.5 * gjj) - acc[q]));
+      }
+    }
+    return;
+  }
+  const double f = vec_center ? 1.0 : fsig;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int r = r0 + lk + 4 * q;
@@ -743,14 +816,26 @@ void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
 }
 
 void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                      int max_L, int max_N, int max_k, hipStream_t st) {
+                      int max_L, int max_N, int max_k, int qr2_panels,
+                      hipStream_t st) {
   (void)max_N;
   const int nd = (max_L * max_k + NT - 1) / NT;
   hipLaunchKernelGGL(k_writeback_direct, dim3(nd, b.B), dim3(NT), 0, st, b, s,
                      u);
-  // the other side has at most max_L rows (L on the QR path, N <= L on
-  // the plain path), padded to 16
   const int rows = (max_L + 15) & ~15, kk = (max_k + 15) & ~15;
+  if (qr2_panels > 0) {
+    // left factor of the two-QR path: Q u~ = H_1 .. H_N [u~; 0], the
+    // block reflectors from the last panel to the first; Z is read here
+    // and by the projection below, before the Gram overwrites it
+    const int nf = (rows * max_k + NT - 1) / NT;
+    hipLaunchKernelGGL(k_qr2_fill, dim3(nf, b.B), dim3(NT), 0, st, b, s, u);
+    for (int p = qr2_panels - 1; p >= 0; --p)
+      launch_qr_apply(b, s, u, p, kk / 16, st);
+    hipLaunchKernelGGL(k_qr2_store_left, dim3(nd, b.B), dim3(NT), 0, st, b, s,
+                       u);
+  }
+  // the other side has at most max_L rows (L on the QR path, N <= L on
+  // the plain and two-QR paths), padded to 16
   dim3 gp((rows + 63) / 64, kk / 16, b.B);
   hipLaunchKernelGGL(k_other_project, gp, dim3(NT), 0, st, b, s, u);
   dim3 gg((kk + 63) / 64, kk / 16, b.B);
