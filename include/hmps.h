@@ -318,8 +318,9 @@ hmps_status hmps_susceptibility(hmps_ctx *ctx, double beta, int32_t n_center,
  * by discarded weight; Results section: the cutoff and chi_max), applied
  * to a given theta'.  theta: host array, m x n row-major with m = 3 chi_l
  * (rows (s1, a)) and n = 3 chi_r (columns (s2, c)), 1 <= chi_l, chi_r <=
- * chi_cap, finite.  It runs the device kernels of an update of hmps_evolve
- * (blocked one-sided Jacobi, truncation with the rules of hmps_evolve,
+ * chi_cap, finite.  It runs the device kernels of an FP64 update of
+ * hmps_evolve (whatever the context's precision: the QR-preconditioned or
+ * plain blocked one-sided Jacobi, truncation with the rules of hmps_evolve,
  * write-back with the singular values absorbed to the right) on chain 0.
  * Outputs (host, caller-owned): rank = k kept; sigma[k] the kept singular
  * values of theta' (descending, not renormalised); left (optional,

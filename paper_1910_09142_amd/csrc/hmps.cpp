@@ -268,8 +268,10 @@ struct hmps_ctx {
   // device buffers (carved from the workspace)
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
   int n_cap = 0, slots = 0, qr_panels = 0;
+  size_t rrG_stride = 0;
   double *d_sites = nullptr, *d_TH = nullptr, *d_X = nullptr,
          *d_Y = nullptr, *d_Z = nullptr, *d_qrT = nullptr, *d_norm2 = nullptr,
+         *d_rrG = nullptr,
          *d_sig2 = nullptr, *d_sig = nullptr, *d_fac = nullptr,
          *d_logw = nullptr, *d_disc = nullptr, *d_gates = nullptr,
          *d_envs = nullptr, *d_wsz = nullptr, *d_bscr = nullptr,
@@ -332,6 +334,13 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   // T factors of every panel of both QR stages
   t->qr_panels = (mc + QB - 1) / QB;
   t->d_qrT = cv.take<double>(B * 2 * t->qr_panels * QB * QB);
+  // Gram of the Ritz basis of the two-QR mixed path (chi_max <= chi_cap)
+  {
+    const int kcap = std::min(n_cap, (chi_cap + 64 + 31) / 32 * 32);
+    const size_t ldk = (size_t)((kcap + 15) & ~15);
+    t->rrG_stride = ldk * ldk;
+    t->d_rrG = cv.take<double>(B * t->rrG_stride);
+  }
   t->d_sig2 = cv.take<double>(B * n_cap);
   t->d_sig = cv.take<double>(B * n_cap);
   t->d_perm = cv.take<int32_t>(B * n_cap);
@@ -417,6 +426,8 @@ UpdScratch scratch_of(hmps_ctx *ctx) {
   s.Z = ctx->d_Z;
   s.qrT = ctx->d_qrT;
   s.qr_panels = ctx->qr_panels;
+  s.rrG = ctx->d_rrG;
+  s.rrG_stride = ctx->rrG_stride;
   s.th_stride = ctx->th_stride;
   s.sig2 = ctx->d_sig2;
   s.perm = ctx->d_perm;
@@ -480,8 +491,10 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   int max_rr_n = 0, max_rr_l = 0, max_qr2_n = 0;
   double flops = 0.0, svd_flops = 0.0;
   const bool is_move = (op == OP_IDENT);
-  // centre moves are exact gauge changes: always FP64
-  const int mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32 && !is_move;
+  // centre moves are exact gauge changes, and hmps_svd_probe (theta' placed
+  // by the host) is the FP64 SVD: both always FP64
+  const int mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32 && !is_move &&
+                    !ctx->skip_theta;
   for (int c = 0; c < ctx->B; ++c) {
     const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
     {
@@ -504,7 +517,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       ++n_small;
     } else {
       ++n_blocked;
-      if (path == PATH_RR) {
+      if (path_is_rr(path)) {
         // FP32 rounds on all nvec vectors, FP64 rounds on the Ritz basis
         ++n_rr;
         max_rr_n = std::max(max_rr_n, nvec);
@@ -519,10 +532,8 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
         ++n_qr;
         max_qr_n = std::max(max_qr_n, nvec);
       }
-      if (path == PATH_QR2) {
-        ++n_qr2;
-        max_qr2_n = std::max(max_qr2_n, nvec);
-      }
+      if (path_has_qr2(path)) ++n_qr2;
+      if (path == PATH_QR2) max_qr2_n = std::max(max_qr2_n, nvec);
     }
   }
   UpdParams u;
@@ -622,11 +633,12 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
           esz = 4.0;
         } else if (path == PATH_QR || path == PATH_QR2) {
           vlen = nvec;  // R^T or R2^T
-        } else if (path == PATH_RR) {
+        } else if (path_is_rr(path)) {
           nv = rr_vectors(nvec, chi_max);
+          if (path == PATH_RR2) vlen = nvec;  // R^T W
         }
         const int nb = n_blocks_even(nv, JB);
-        const bool part = f32 ? path == PATH_RR : path != PATH_SMALL;
+        const bool part = f32 ? path_is_rr(path) : path != PATH_SMALL;
         round_bytes[c] =
             part ? (double)(nb - 1) * nb * JB * vector_stride(vlen) * esz : 0.0;
       }

@@ -65,17 +65,33 @@ __host__ __device__ inline bool qr_path(int L, int N, size_t small_max,
 //             converged vectors, orthonormalised in FP64, give the basis W
 //             of a Rayleigh-Ritz step: FP64 rounds on the columns of
 //             theta' W.
-enum { PATH_SMALL = 0, PATH_PLAIN = 1, PATH_QR = 2, PATH_RR = 3, PATH_QR2 = 4 };
+//   PATH_RR2  (mixed precision, precond >= 2) the FP32 rounds on R2^T: their
+//             vectors approximate the left singular vectors u~ in the basis
+//             of Q, and the FP64 rounds run on the columns of R^T W (whose
+//             converged vectors are sigma_j w_j, as on the QR path).
+enum {
+  PATH_SMALL = 0, PATH_PLAIN = 1, PATH_QR = 2, PATH_RR = 3, PATH_QR2 = 4,
+  PATH_RR2 = 5
+};
 __host__ __device__ inline int svd_path(int L, int N, size_t small_max,
                                         int precond, int mixed) {
   if (small_path(L, N, small_max)) return PATH_SMALL;
-  if (qr_path(L, N, small_max, precond))
-    return mixed ? PATH_RR : (precond >= 2 ? PATH_QR2 : PATH_QR);
+  if (qr_path(L, N, small_max, precond)) {
+    if (mixed) return precond >= 2 ? PATH_RR2 : PATH_RR;
+    return precond >= 2 ? PATH_QR2 : PATH_QR;
+  }
   return PATH_PLAIN;
 }
-// The paths whose first step is theta' = Q R.
+// The paths whose first step is theta' = Q R, those with a second QR, and
+// the mixed-precision paths.
 __host__ __device__ inline bool path_has_qr(int path) {
-  return path == PATH_QR || path == PATH_RR || path == PATH_QR2;
+  return path >= PATH_QR;
+}
+__host__ __device__ inline bool path_has_qr2(int path) {
+  return path == PATH_QR2 || path == PATH_RR2;
+}
+__host__ __device__ inline bool path_is_rr(int path) {
+  return path == PATH_RR || path == PATH_RR2;
 }
 // Largest Ritz basis: chi_max plus 64 (at least 64 vectors beyond the
 // cut), rounded to 32, at most N.  The basis holds only the vectors the
@@ -125,6 +141,8 @@ struct UpdScratch {
   int32_t *err;       // [B] nonzero: numerical failure
   int32_t *sweeps;    // [B] Jacobi sweeps done by the in-LDS path
   int32_t *rrk;       // [B] Ritz basis size of the mixed path (<= rr_vectors)
+  double *rrG;        // [B][rrG_stride] Gram of the basis on PATH_RR2
+  size_t rrG_stride;  // doubles per chain: round16(k')^2 for the largest k'
 };
 
 // T factor of panel p of QR stage `stage` of chain c.

@@ -184,18 +184,19 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   // the vector matrix of the chain's path: R^T (length N) in Y on the QR
   // path, R2^T (length N) in Z on the two-QR path; on the mixed path the
   // FP32 copy of R^T in X (first stage), then the rrk columns of theta' W
-  // in X (second stage); theta' in X else
-  if (F32 && path != PATH_RR) return;
-  const int L = (F32 || path == PATH_QR || path == PATH_QR2) ? N : Lt;
-  const int nvec = (!F32 && path == PATH_RR) ? s.rrk[c] : N;
+  // in X (second stage); on the two-QR mixed path the FP32 copy of R2^T in
+  // Y, then the rrk columns of R^T W in Y; theta' in X else
+  if (F32 && !path_is_rr(path)) return;
+  const int L = (F32 || path == PATH_QR || path_has_qr2(path)) ? N : Lt;
+  const int nvec = (!F32 && path_is_rr(path)) ? s.rrk[c] : N;
   const int NB = n_blocks_even(nvec, JB);
   if (r >= NB - 1 || pi >= NB / 2) return;
   const int ld = vec_ld(L);
   int bi, bj;
   rr_pair(r, pi, NB, bi, bj);
-  double *base = F32 ? s.X
-                     : (path == PATH_QR ? s.Y
-                                        : (path == PATH_QR2 ? s.Z : s.X));
+  double *base = path == PATH_QR2 ? s.Z
+                 : (path == PATH_QR || path == PATH_RR2) ? s.Y
+                                                         : s.X;
   T *X = reinterpret_cast<T *>(base) + (size_t)c * (F32 ? 2 : 1) * s.th_stride;
   const double tol = F32 ? u.tol32 : u.tol;
   const double skip = F32 ? u.skip32 : u.skip;

@@ -158,7 +158,9 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   s.done = iv + I_DONE;
   s.err = iv + I_ERR;
   s.sweeps = iv + I_SWEEPS;
-  s.rrk = nullptr;  // the mixed path is never taken here
+  s.rrk = nullptr;  // the mixed paths are never taken here
+  s.rrG = nullptr;
+  s.rrG_stride = 0;
   // the parameters of hmps_svd_probe on a context with chi_cap = NA_CHI
   // and default options
   UpdParams u;

@@ -61,7 +61,7 @@ __device__ __forceinline__ QDims qdims(const Batch &b, int c,
     d.out = s.Y + off;
   } else {
     d.L = d.N;
-    d.qr = path == PATH_QR2;
+    d.qr = path_has_qr2(path);
     d.M = s.Y + off;
     d.out = s.Z + off;
   }

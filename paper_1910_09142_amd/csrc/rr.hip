@@ -23,6 +23,15 @@
 // error of the basis), U the kept left singular vectors.  Truncation,
 // log-weight and write-back stay FP64 and take the rest of ||theta'||^2
 // (summed in FP64 from theta') as the unresolved tail.
+//
+// Two-QR variant (PATH_RR2): the FP32 rounds run on R2^T (R^T = Q2 R2, in
+// fewer sweeps), whose converged vectors approximate sigma_j u~_j, u~_j =
+// Q^T u_j the left singular vectors in the basis of Q.  With W the
+// orthonormalised basis of the k' largest, B = R^T W (N x k') is M^T (Q W):
+// the FP64 rounds on its columns converge to sigma_j w_j, the right Ritz
+// vectors, and the write-back is that of the QR path.  Buffers: R in the
+// upper triangle of X (kept), R2^T in Z, its FP32 copy in Y, the basis in
+// Z and Y, its Gram in rrG, B in Y.
 #include "device_common.h"
 
 namespace hmps {
@@ -30,7 +39,7 @@ namespace {
 using namespace dev;
 
 struct RDims {
-  int L, N, ld, ldN, kp, ldK, rr;
+  int L, N, ld, ldN, kp, ldK, rr, two;
 };
 
 // kp: the chain's Ritz basis size, set by k_rr_select (read after it)
@@ -44,7 +53,9 @@ __device__ __forceinline__ RDims rdims(const Batch &b, int c,
   d.N = m > n ? n : m;
   d.ld = vec_ld(d.L);
   d.ldN = vec_ld(d.N);
-  d.rr = svd_path(d.L, d.N, u.small_max, u.precond, u.mixed) == PATH_RR;
+  const int path = svd_path(d.L, d.N, u.small_max, u.precond, u.mixed);
+  d.rr = path_is_rr(path);
+  d.two = path == PATH_RR2;
   d.kp = d.rr ? s.rrk[c] : 0;
   d.ldK = (d.kp + 15) & ~15;
   return d;
@@ -56,8 +67,9 @@ __global__ void __launch_bounds__(NT) k_rr_to32(Batch b, UpdScratch s,
   const RDims d = rdims(b, c, u, s);
   if (!d.rr) return;
   const size_t cnt = (size_t)n_blocks_even(d.N, JB) * JB * d.ldN;
-  const double *Y = s.Y + (size_t)c * s.th_stride;
-  float *X = reinterpret_cast<float *>(s.X) + (size_t)c * 2 * s.th_stride;
+  const double *Y = (d.two ? s.Z : s.Y) + (size_t)c * s.th_stride;
+  float *X = reinterpret_cast<float *>(d.two ? s.Y : s.X) +
+             (size_t)c * 2 * s.th_stride;
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < cnt;
        i += (size_t)gridDim.x * NT)
     X[i] = (float)Y[i];
@@ -70,7 +82,8 @@ __global__ void __launch_bounds__(NT) k_rr_norms(Batch b, UpdScratch s,
   const int c = blockIdx.y;
   const RDims d = rdims(b, c, u, s);
   if (!d.rr) return;
-  const float *X = reinterpret_cast<const float *>(s.X) + (size_t)c * 2 * s.th_stride;
+  const float *X = reinterpret_cast<const float *>(d.two ? s.Y : s.X) +
+                   (size_t)c * 2 * s.th_stride;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t = 0; t < 4; ++t) {
     const int j = 16 * blockIdx.x + 4 * w + t;
@@ -144,8 +157,9 @@ __global__ void __launch_bounds__(NT) k_rr_gather(Batch b, UpdScratch s,
   const int c = blockIdx.y;
   const RDims d = rdims(b, c, u, s);
   if (!d.rr) return;
-  const float *X = reinterpret_cast<const float *>(s.X) + (size_t)c * 2 * s.th_stride;
-  double *W = s.Y + (size_t)c * s.th_stride;
+  const float *X = reinterpret_cast<const float *>(d.two ? s.Y : s.X) +
+                   (size_t)c * 2 * s.th_stride;
+  double *W = (d.two ? s.Z : s.Y) + (size_t)c * s.th_stride;
   const int32_t *perm = s.perm + (size_t)c * s.n_cap;
   const double *sig2 = s.sig2 + (size_t)c * s.n_cap;
   const size_t cnt = (size_t)d.kp * d.ldN;
@@ -159,12 +173,20 @@ __global__ void __launch_bounds__(NT) k_rr_gather(Batch b, UpdScratch s,
 }
 
 // The basis of pass p: W0 in Y (p = 0) or W1 in X (p = 1); the corrected
-// basis goes to the other buffer.
-__device__ __forceinline__ double *basis_src(const UpdScratch &s, int c, int p) {
-  return (p == 0 ? s.Y : s.X) + (size_t)c * s.th_stride;
+// basis goes to the other buffer.  Two-QR variant: Z and Y (X keeps R).
+__device__ __forceinline__ double *basis_src(const UpdScratch &s, int c, int p,
+                                             bool two) {
+  double *a = two ? s.Z : s.Y, *bb = two ? s.Y : s.X;
+  return (p == 0 ? a : bb) + (size_t)c * s.th_stride;
 }
-__device__ __forceinline__ double *basis_dst(const UpdScratch &s, int c, int p) {
-  return (p == 0 ? s.X : s.Y) + (size_t)c * s.th_stride;
+__device__ __forceinline__ double *basis_dst(const UpdScratch &s, int c, int p,
+                                             bool two) {
+  double *a = two ? s.Z : s.Y, *bb = two ? s.Y : s.X;
+  return (p == 0 ? bb : a) + (size_t)c * s.th_stride;
+}
+__device__ __forceinline__ double *basis_gram(const UpdScratch &s, int c,
+                                              bool two) {
+  return two ? s.rrG + (size_t)c * s.rrG_stride : s.Z + (size_t)c * s.th_stride;
 }
 
 // G = W^T W, one 16 x 16 tile per wavefront, rows of W as aligned 32-byte
@@ -179,8 +201,8 @@ __global__ void __launch_bounds__(NT) k_rr_gram(Batch b, UpdScratch s,
   const int li = lane & 15, lk = lane >> 4;
   const int j1 = blockIdx.x * 64 + 16 * w, j2 = blockIdx.y * 16;
   if (j1 >= d.ldK || j2 >= d.ldK) return;
-  const double *W = basis_src(s, c, p);
-  double *G = s.Z + (size_t)c * s.th_stride;
+  const double *W = basis_src(s, c, p, d.two);
+  double *G = basis_gram(s, c, d.two);
   const bool aok = j1 + li < d.kp, bok = j2 + li < d.kp;
   const double *pa = W + (size_t)(aok ? j1 + li : 0) * d.ldN;
   const double *pb = W + (size_t)(bok ? j2 + li : 0) * d.ldN;
@@ -212,9 +234,9 @@ __global__ void __launch_bounds__(NT) k_rr_correct(Batch b, UpdScratch s,
   const int li = lane & 15, lk = lane >> 4;
   const int r0 = blockIdx.x * 64 + 16 * w, j0 = blockIdx.y * 16;
   if (r0 >= d.ldN || j0 >= d.kp) return;
-  const double *W = basis_src(s, c, p);
-  double *Wn = basis_dst(s, c, p);
-  const double *G = s.Z + (size_t)c * s.th_stride;
+  const double *W = basis_src(s, c, p, d.two);
+  double *Wn = basis_dst(s, c, p, d.two);
+  const double *G = basis_gram(s, c, d.two);
   const bool jok = j0 + li < d.kp;
   const int jj = j0 + li;
   const double *grow = G + (size_t)(jok ? jj : 0) * d.ldK;
@@ -250,6 +272,9 @@ __global__ void __launch_bounds__(NT) k_rr_correct(Batch b, UpdScratch s,
 // and vectors k' .. npad(k')-1 zero.  Lane (li, lk) takes row l0 + li of M
 // (single coalesced loads per contraction index) and elements q0 + 4 lk ..
 // + 3 of W_j as one aligned 32-byte load.
+// Two-QR variant: B = R^T W (N x k') into Y, vector stride ldN: row q of
+// B is column q of R (the upper part of column q of X, rows i <= q) times
+// W, both operands as aligned 32-byte loads of four consecutive i.
 __global__ void __launch_bounds__(NT) k_rr_project(Batch b, UpdScratch s,
                                                    UpdParams u) {
   const int c = blockIdx.z;
@@ -259,35 +284,58 @@ __global__ void __launch_bounds__(NT) k_rr_project(Batch b, UpdScratch s,
   const int li = lane & 15, lk = lane >> 4;
   const int l0 = blockIdx.x * 64 + 16 * w, j0 = blockIdx.y * 16;
   const int npad = n_blocks_even(d.kp, JB) * JB;
-  if (l0 >= d.ld || j0 >= npad) return;
-  const double *M = s.TH + (size_t)c * s.th_stride;
-  const double *W = s.Y + (size_t)c * s.th_stride;  // W2 (after two passes)
-  double *X = s.X + (size_t)c * s.th_stride;
+  const int out_ld = d.two ? d.ldN : d.ld, out_len = d.two ? d.N : d.L;
+  if (l0 >= out_ld || j0 >= npad) return;
   const bool jok = j0 + li < d.kp;
-  const double *wv = W + (size_t)(jok ? j0 + li : 0) * d.ldN;
-  const bool lok = l0 + li < d.L;
-  const double *mrow = M + (lok ? l0 + li : 0);
   v4d acc = {0.0, 0.0, 0.0, 0.0};
-  for (int q0 = 0; q0 < d.N; q0 += 16) {
-    const int qb = q0 + 4 * lk;
-    const v4d wq = *reinterpret_cast<const v4d *>(wv + qb);
-    double mv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int qq = min(qb + q, d.N - 1);
-      const double x = mrow[(size_t)qq * d.ld];
-      mv[q] = (lok && qb + q < d.N) ? x : 0.0;
+  double *out;
+  if (d.two) {
+    const double *R = s.X + (size_t)c * s.th_stride;
+    const double *W = s.Z + (size_t)c * s.th_stride;  // W2 (after two passes)
+    out = s.Y + (size_t)c * s.th_stride;
+    const double *wv = W + (size_t)(jok ? j0 + li : 0) * d.ldN;
+    const int q = l0 + li;
+    const bool qok = q < d.N;
+    const double *rcol = R + (size_t)(qok ? q : 0) * d.ld;
+    const int iend = min(d.N, l0 + 16);  // R is upper triangular
+    for (int i0 = 0; i0 < iend; i0 += 16) {
+      const int ib = i0 + 4 * lk;
+      const v4d wq = *reinterpret_cast<const v4d *>(wv + ib);
+      const v4d rq = *reinterpret_cast<const v4d *>(rcol + ib);
+      const int lim = min(d.N - 1, q);
+      acc = mfma_f64(qok && ib <= lim ? rq.x : 0.0, jok ? wq.x : 0.0, acc);
+      acc = mfma_f64(qok && ib + 1 <= lim ? rq.y : 0.0, jok ? wq.y : 0.0, acc);
+      acc = mfma_f64(qok && ib + 2 <= lim ? rq.z : 0.0, jok ? wq.z : 0.0, acc);
+      acc = mfma_f64(qok && ib + 3 <= lim ? rq.w : 0.0, jok ? wq.w : 0.0, acc);
     }
-    acc = mfma_f64(mv[0], jok ? wq.x : 0.0, acc);
-    acc = mfma_f64(mv[1], jok ? wq.y : 0.0, acc);
-    acc = mfma_f64(mv[2], jok ? wq.z : 0.0, acc);
-    acc = mfma_f64(mv[3], jok ? wq.w : 0.0, acc);
+  } else {
+    const double *M = s.TH + (size_t)c * s.th_stride;
+    const double *W = s.Y + (size_t)c * s.th_stride;  // W2 (after two passes)
+    out = s.X + (size_t)c * s.th_stride;
+    const double *wv = W + (size_t)(jok ? j0 + li : 0) * d.ldN;
+    const bool lok = l0 + li < d.L;
+    const double *mrow = M + (lok ? l0 + li : 0);
+    for (int q0 = 0; q0 < d.N; q0 += 16) {
+      const int qb = q0 + 4 * lk;
+      const v4d wq = *reinterpret_cast<const v4d *>(wv + qb);
+      double mv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int qq = min(qb + q, d.N - 1);
+        const double x = mrow[(size_t)qq * d.ld];
+        mv[q] = (lok && qb + q < d.N) ? x : 0.0;
+      }
+      acc = mfma_f64(mv[0], jok ? wq.x : 0.0, acc);
+      acc = mfma_f64(mv[1], jok ? wq.y : 0.0, acc);
+      acc = mfma_f64(mv[2], jok ? wq.z : 0.0, acc);
+      acc = mfma_f64(mv[3], jok ? wq.w : 0.0, acc);
+    }
   }
   // D[i][j] (row l0 + i, vector j0 + j) in lane j + 16 (i % 4), element i/4
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int l = l0 + lk + 4 * q;
-    X[(size_t)(j0 + li) * d.ld + l] = (jok && l < d.L) ? acc[q] : 0.0;
+    out[(size_t)(j0 + li) * out_ld + l] = (jok && l < out_len) ? acc[q] : 0.0;
   }
 }
 

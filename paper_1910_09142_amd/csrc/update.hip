@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(NT)
   const Dims d = dims_of(b, c, u.k);
   // the mixed path resolves only the rr_vectors largest singular values;
   // the rest of ||theta'||^2 is the unresolved tail
-  const bool rr = path_of(d, u) == PATH_RR;
+  const bool rr = path_is_rr(path_of(d, u));
   const int N = rr ? s.rrk[c] : d.N;
   __shared__ double key[2048];
   __shared__ int idx[2048];
@@ -493,7 +493,8 @@ __global__ void __launch_bounds__(NT)
   const Dims d = dims_of(b, c, u.k);
   const int path = path_of(d, u);
   if (path == PATH_QR2) return;
-  const bool qr = path == PATH_QR;
+  // the two-QR mixed path ends like the QR path: sigma_j w_j in Y
+  const bool qr = path == PATH_QR || path == PATH_RR2;
   const Dims e = vector_side(d, qr);
   const int vlen = qr ? d.N : d.L, vld = qr ? vec_ld(d.N) : d.ld;
   const int k = s.knew[c];
@@ -546,7 +547,9 @@ __device__ __forceinline__ Other other_of(const Dims &d, const UpdParams &u,
                                           const UpdScratch &s, int c) {
   const int path = path_of(d, u);
   Other o;
-  o.mode = path == PATH_QR2 ? OM_QR2 : (path == PATH_QR ? OM_QR : OM_PLAIN);
+  o.mode = path == PATH_QR2 ? OM_QR2
+           : (path == PATH_QR || path == PATH_RR2) ? OM_QR
+                                                   : OM_PLAIN;
   o.len = o.mode == OM_QR ? d.L : d.N;
   o.ldP = vec_ld(o.len);
   o.k = s.knew[c];
