@@ -16,8 +16,9 @@ summed from theta' itself in FP64, before the SVD; later applications
 start from states that already differ at the 1e-13 level, so they are held
 at 1e-10); the factor left of the centre left-orthonormal and the one
 right of it right-orthonormal, both to 1e-12 (one factor is the
-normalised Jacobi vectors, the other their projections through theta',
-corrected to orthonormality).
+normalised Jacobi vectors, or on the two-QR path their images under the
+stored reflectors; the other their projections, corrected to
+orthonormality).  Every preconditioning level is run (none, one QR, two).
 Mixed mode (FP32 theta and gate): the state to 5e-6 relative, log-weights
 to 1e-6.
 """
@@ -120,6 +121,22 @@ def test_chi512_largest_bond():
 
 
 def test_mixed_precision_bond():
+    run_case(64, 64, 64, 2, 64, 1e-10, 2, precision=hmps.PREC_MIXED_FP32,
+             tol_state=5e-6, tol_logw=1e-6)
+
+
+@pytest.mark.parametrize("level", ["0", "1", "2"])
+def test_preconditioner_levels(level, monkeypatch):
+    # HMPS_QR, read when a context is created, selects how the blocked
+    # Jacobi SVD is preconditioned: none (rounds on theta'), one QR (rounds
+    # on R^T), or two (rounds on R2^T with R^T = Q2 R2, the default; the
+    # left factor from the stored reflectors).  Each level, in FP64 and in
+    # mixed precision (FP32 rounds, FP64 Ritz step), gives the oracle's
+    # update.
+    monkeypatch.setenv("HMPS_QR", level)
+    run_case(40, 40, 40, 3, 32, 1e-10, 3)
+    run_case(22, 50, 60, 2, 50, 1e-12, 2)
+    run_case(96, 96, 96, 1, 96, 1e-10, 2, seed=7)
     run_case(64, 64, 64, 2, 64, 1e-10, 2, precision=hmps.PREC_MIXED_FP32,
              tol_state=5e-6, tol_logw=1e-6)
 
