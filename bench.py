@@ -56,10 +56,13 @@ def parse(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="gate",
-                    choices=["gate", "m1", "c1", "c2", "c3", "c4", "c5"],
+                    choices=["gate", "m1", "c1", "c2", "c3", "c4", "c5",
+                             "wlimit"],
                     help="gate (default): the chi = 256 gate workload with "
                     "its extra fields; m1: that workload alone; c1..c5: "
-                    "whole samples of a ladder workload")
+                    "whole samples of a ladder workload; wlimit: the hybrid "
+                    "against its METTS (W = 0) and ancilla (W = L) limits "
+                    "(--steps samples per chain)")
     ap.add_argument("--chains", type=int, default=None,
                     help="chains (default: 64 for the gate workload, the "
                     "workload's own count for ladders)")
@@ -322,6 +325,84 @@ def sample_run(wl, B, precision):
             "energy_mean": float(m["energy"].mean())}
 
 
+def main_wlimit(args):
+    """The hybrid against its two limits on one code path (Results
+    section: the W = 16 hybrid against METTS and the ancilla method;
+    Entanglement and Cost of Hybrid States: the variance of each bond
+    energy along a leg).  A 2 x 8 S=1 ladder at beta = 2 (tau 0.05,
+    chi_max 128, cutoff 1e-12) with cluster widths W = 0 (METTS), 2, 4
+    (hybrid) and 8 (the ancilla method: one purified state, no sampling):
+    per W the energy per site with its standard error over independent
+    chains, the sample variance of every leg bond energy (device moments),
+    the cost per sample and the largest bond dimension.  Every chain starts
+    from a uniform random product state; its first --warmup samples are
+    discarded (burn-in towards the stationary distribution P_i / sum P_j)
+    and the next --steps are measured."""
+    import numpy as np
+    import torch
+    from paper_1910_09142_amd import hmps, workloads
+    L, beta, tau, chi, cut = 8, (args.beta or 2.0), 0.05, 128, 1e-12
+    B, S, burn = (args.chains or 64), args.steps, args.warmup
+    rows = []
+    t_all = time.perf_counter()
+    for W in (0, 2, 4, L):
+        # the ancilla limit samples nothing: one purified state
+        nc, ns, nb = (1, 1, 0) if W == L else (B, S, burn)
+        n, bonds, order, mask = workloads.ladder_arrays(L, 1.0, 1.0, W)
+        lat = hmps.Lattice(n, bonds, order, mask)
+        ctx = hmps.Context(nc, workloads.mps_length(L, W), chi, len(bonds))
+        ctx.hmps_init_cluster_env(lat, nc, 0)
+        e = np.zeros((nc, ns))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(nb + ns):
+            ctx.hmps_evolve(beta, tau, chi, cut)
+            if k >= nb:
+                m = ctx.hmps_measure(hmps.MEASURE_ENERGY |
+                                     hmps.MEASURE_ACCUMULATE)
+                e[:, k - nb] = m["energy"] / n
+            ctx.hmps_collapse_resample(k % 2)
+            print(f"wlimit W={W}: sample {k + 1}/{nb + ns} "
+                  f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+                  flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.hmps_stats()
+        leg = slice(L, 2 * L - 1)   # bonds (c, 0)-(c + 1, 0)
+        var = None
+        if nc * ns >= 2:
+            var = ctx.hmps_bond_moments()["var"][leg].tolist()
+        ctx.hmps_destroy()
+        means = e.mean(axis=1)       # per chain: chains are independent
+        se = float(means.std(ddof=1) / np.sqrt(nc)) if nc > 1 else 0.0
+        rows.append({"W": W, "method": ("METTS" if W == 0 else "ancilla"
+                                        if W == L else "hybrid"),
+                     "chains": nc, "samples_per_chain": ns,
+                     "burn_in_per_chain": nb,
+                     "energy_per_site": float(means.mean()),
+                     "standard_error": se,
+                     "leg_bond_variance": var,
+                     "seconds": dt, "samples_per_s": nc * (nb + ns) / dt,
+                     "max_chi": st.max_chi})
+    ref = rows[-1]["energy_per_site"]
+    for r in rows:
+        r["minus_ancilla"] = r["energy_per_site"] - ref
+    hyb = rows[2]
+    out = {
+        "metric": "METTS samples/sec, hybrid vs METTS vs ancilla limits",
+        "value": hyb["samples_per_s"], "unit": "METTS samples/s",
+        "n_gpus": 1, "steps": S, "warmup": burn,
+        "ms_per_step": 1e3 * hyb["seconds"] / (S + burn),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (Philox-seeded product states, "
+        "ladder Hamiltonian)",
+        "config": {"workload": f"ladder2x{L}_beta{beta:g}_chi{chi}_Wlimits",
+                   "n_chains": B, "L": L, "beta": beta, "tau": tau,
+                   "chi_max": chi, "cutoff": cut, "W": [0, 2, 4, L]},
+        "wlimit": rows, "seconds_total": time.perf_counter() - t_all}
+    print(json.dumps(out), flush=True)
+
+
 def gate_tag(wl, B):
     return wl.name if B == 1 else f"{wl.name}_batch{B}"
 
@@ -556,6 +637,8 @@ def main():
         sys.exit(2)
     if args.workload in ("gate", "m1"):
         main_gate(args, extras=args.workload == "gate" and not args.no_extras)
+    elif args.workload == "wlimit":
+        main_wlimit(args)
     else:
         main_ladder(args)
 

@@ -72,6 +72,9 @@ typedef int32_t hmps_status;
 #define HMPS_MEASURE_LOGW 4u   /* log-weights (no device contraction)    */
 #define HMPS_MEASURE_QN 8u     /* <Q>, Q = sum_phys S^z - sum_anc S^z    */
 #define HMPS_MEASURE_ALL 15u
+/* Not an output: add this measurement's per-bond correlators and energy
+ * of every chain to the device-side sample moments (hmps_bond_moments). */
+#define HMPS_MEASURE_ACCUMULATE 16u
 
 typedef struct {
   int32_t device;          /* HIP device ordinal                          */
@@ -227,9 +230,35 @@ hmps_status hmps_last_spectrum(hmps_ctx *ctx, int32_t cap, int32_t *rank,
  *   qn      [n_chains]           <sum_phys S^z - sum_ancilla S^z> (an
  *                                expectation value: an integer only for
  *                                environments collapsed in S^z, so FP64)
+ * With HMPS_MEASURE_ACCUMULATE the correlators are computed whether or
+ * not they are output, and added on the device to the per-chain moments.
  * E_INVALID for unknown bits.  Synchronises the stream. */
 hmps_status hmps_measure(hmps_ctx *ctx, uint32_t what, double *energy,
                          double *bond_ss, double *logw, double *qn);
+
+/* Sample variance of the estimators, bond by bond (Entanglement and Cost
+ * of Hybrid States: the variance of every bond energy <S_i.S_j> along the
+ * ladder, lower inside the purified cluster than outside).  Every
+ * hmps_measure call with HMPS_MEASURE_ACCUMULATE adds the n_chains values
+ * of each bond correlator and of the energy to per-chain running moments
+ * on the device (count, mean, sum of squared deviations: Welford's update
+ * in FP64); hmps_bond_moments combines the chains in chain order (Chan,
+ * Golub and LeVeque) and returns, over all accumulated chains and
+ * measurements:
+ *   n_samples            the number of values per bond
+ *   bond_mean [n_bonds]  their mean, bond_var [n_bonds] their unbiased
+ *                        sample variance (divisor n - 1)
+ *   energy_mean_var [2]  (optional) the same for the energy
+ * A Markov chain samples product states with probability P_i / sum_j P_j,
+ * so these are plain (unweighted) sample moments; consecutive samples of
+ * one chain are correlated, which a variance of the mean must account
+ * for.  hmps_init_cluster_env and hmps_moments_reset clear the moments.
+ * E_STATE with fewer than two values, E_INVALID for NULL outputs.
+ * Synchronises. */
+hmps_status hmps_moments_reset(hmps_ctx *ctx);
+hmps_status hmps_bond_moments(hmps_ctx *ctx, int64_t *n_samples,
+                              double *bond_mean, double *bond_var,
+                              double *energy_mean_var);
 
 /* Step 4: collapse every environment site in MPS order by a projective
  * measurement in `basis` (0 = S^z, 1 = S^x), tracing the cluster sites;

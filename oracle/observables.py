@@ -1,6 +1,8 @@
 """Long-range observables of one sample (Results section, susceptibility):
 correlators <S_i.S_j> of arbitrary spin pairs and the susceptibility
-estimator built from them.
+estimator built from them; and the sample moments of the per-bond
+estimators over many samples (the variance study of Section Entanglement
+and Cost of Hybrid States).
 
 Test infrastructure: the reference the GPU path is checked against, never
 called by it.
@@ -8,6 +10,8 @@ called by it.
 Parity: pinned against dense exact diagonalisation of sum_{j in C} sum_i
 S_j.S_i through the exhaustive hybrid identity (any centre set C, both
 bases) and against product states, where <S_i.S_j> = m_i m_j.
+sample_moments is the textbook definition, pinned by closed forms (a
+two-valued sample, a constant one, a hand-computed one).
 """
 from __future__ import annotations
 
@@ -37,3 +41,20 @@ def susceptibility(psi: mps.MPS, lat: model.Lattice, lay: model.Layout,
     center = list(center)
     pairs = [(j, i) for j in center for i in range(lat.n_phys)]
     return beta / 3.0 * sum(pair_correlations(psi, lat, lay, pairs)) / len(center)
+
+
+def sample_moments(values):
+    """Mean and unbiased sample variance of each column of `values` (rows:
+    samples, e.g. every chain's every measurement; columns: bonds):
+    mean_b = sum_s x_sb / n, var_b = sum_s (x_sb - mean_b)^2 / (n - 1).
+    The Markov chain draws product states with probability P_i / sum_j
+    P_j, so the samples are weighted equally."""
+    rows = [list(map(float, r)) for r in values]
+    n = len(rows)
+    if n < 2:
+        raise ValueError("the sample variance needs at least two samples")
+    cols = len(rows[0])
+    mean = [sum(r[b] for r in rows) / n for b in range(cols)]
+    var = [sum((r[b] - mean[b]) ** 2 for r in rows) / (n - 1)
+           for b in range(cols)]
+    return n, mean, var

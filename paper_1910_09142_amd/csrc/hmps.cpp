@@ -276,7 +276,7 @@ struct hmps_ctx {
          *d_logw = nullptr, *d_disc = nullptr, *d_gates = nullptr,
          *d_envs = nullptr, *d_wsz = nullptr, *d_bscr = nullptr,
          *d_norm = nullptr, *d_bond_ss = nullptr, *d_energy = nullptr,
-         *d_pair_ss = nullptr,
+         *d_pair_ss = nullptr, *d_mom = nullptr, *d_mom_out = nullptr,
          *d_qn = nullptr, *d_bond_J = nullptr;
   int32_t *d_chi = nullptr, *d_perm = nullptr, *d_knew = nullptr,
           *d_rot = nullptr, *d_done = nullptr, *d_err = nullptr,
@@ -363,6 +363,9 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_wsz = cv.take<double>(B * max_sites);
   t->d_bscr = cv.take<double>(B * slots * 4 * chi2);
   t->d_bond_ss = cv.take<double>(B * std::max(max_bonds, 1));
+  // per-chain moments of every bond and of the energy, and their total
+  t->d_mom = cv.take<double>(B * (size_t)(max_bonds + 1) * 3);
+  t->d_mom_out = cv.take<double>((size_t)(max_bonds + 1) * 3);
   t->d_bond_J = cv.take<double>(std::max(max_bonds, 1));
   t->d_bond_p = cv.take<int32_t>(std::max(max_bonds, 1));
   t->d_bond_q = cv.take<int32_t>(std::max(max_bonds, 1));
@@ -926,6 +929,8 @@ hmps_status hmps_init_cluster_env_at(hmps_ctx *ctx, const hmps_lattice *lat,
   HIPCHK(hipMemsetAsync(ctx->d_disc, 0, sizeof(double) * n_chains, s));
   HIPCHK(hipMemsetAsync(ctx->d_err, 0, sizeof(int32_t) * n_chains, s));
   HIPCHK(hipMemsetAsync(ctx->d_sweeps, 0, sizeof(int32_t) * n_chains, s));
+  // new chains start with no accumulated moments
+  launch_fill(ctx->d_mom, (size_t)n_chains * (P.n_bonds + 1) * 3, 0.0, s);
   Batch b = batch_of(ctx);
   InitArgs ia;
   ia.is_cluster = ctx->d_is_cluster;
@@ -1087,8 +1092,9 @@ hmps_status hmps_measure(hmps_ctx *ctx, uint32_t what, double *energy,
   hmps_status st = check_usable(ctx, true);
   if (st) return st;
   DeviceGuard guard(ctx->opt.device);
-  if (what & ~(uint32_t)HMPS_MEASURE_ALL)
+  if (what & ~(uint32_t)(HMPS_MEASURE_ALL | HMPS_MEASURE_ACCUMULATE))
     return fail(ctx, HMPS_E_INVALID, "unknown bits in what");
+  const bool accumulate = (what & HMPS_MEASURE_ACCUMULATE) != 0;
   if (!(what & HMPS_MEASURE_ENERGY)) energy = nullptr;
   if (!(what & HMPS_MEASURE_BONDS)) bond_ss = nullptr;
   if (!(what & HMPS_MEASURE_LOGW)) logw = nullptr;
@@ -1097,7 +1103,7 @@ hmps_status hmps_measure(hmps_ctx *ctx, uint32_t what, double *energy,
   hipStream_t s = ctx->stream;
   const size_t B = ctx->B;
   // the log-weights need no contraction
-  if (!energy && !qn && !(bond_ss && P.n_bonds > 0)) {
+  if (!accumulate && !energy && !qn && !(bond_ss && P.n_bonds > 0)) {
     if (logw)
       HIPCHK(hipMemcpyAsync(logw, ctx->d_logw, sizeof(double) * B,
                             hipMemcpyDeviceToHost, s));
@@ -1123,10 +1129,13 @@ hmps_status hmps_measure(hmps_ctx *ctx, uint32_t what, double *energy,
   ma.norm = ctx->d_norm;
   ma.bond_ss = ctx->d_bond_ss;
   launch_measure_envs(b, ma, s);
-  if (energy || bond_ss)
+  if (energy || bond_ss || accumulate)
     for (int b0 = 0; b0 < P.n_bonds; b0 += ctx->slots)
       launch_measure_bonds(b, ma, b0, std::min(ctx->slots, P.n_bonds - b0), s);
   launch_measure_finish(b, ma, ctx->d_energy, ctx->d_qn, s);
+  if (accumulate)
+    launch_moments_add(ctx->d_bond_ss, ctx->d_energy, ctx->d_mom, (int)B,
+                       P.n_bonds, s);
   HIPCHK(hipGetLastError());
   if (energy)
     HIPCHK(hipMemcpyAsync(energy, ctx->d_energy, sizeof(double) * B,
@@ -1142,6 +1151,53 @@ hmps_status hmps_measure(hmps_ctx *ctx, uint32_t what, double *energy,
     HIPCHK(hipMemcpyAsync(qn, ctx->d_qn, sizeof(double) * B,
                           hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  return HMPS_OK;
+}
+
+hmps_status hmps_moments_reset(hmps_ctx *ctx) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
+  hipStream_t s = ctx->stream;
+  launch_fill(ctx->d_mom, (size_t)ctx->B * (ctx->plan.n_bonds + 1) * 3, 0.0,
+              s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return HMPS_OK;
+}
+
+hmps_status hmps_bond_moments(hmps_ctx *ctx, int64_t *n_samples,
+                              double *bond_mean, double *bond_var,
+                              double *energy_mean_var) {
+  hmps_status st = check_usable(ctx, true);
+  if (st) return st;
+  DeviceGuard guard(ctx->opt.device);
+  if (!n_samples)
+    return fail(ctx, HMPS_E_INVALID, "n_samples must not be NULL");
+  const int nb = ctx->plan.n_bonds;
+  if (nb > 0 && (!bond_mean || !bond_var))
+    return fail(ctx, HMPS_E_INVALID, "bond_mean and bond_var must not be NULL");
+  hipStream_t s = ctx->stream;
+  launch_moments_reduce(ctx->d_mom, ctx->d_mom_out, ctx->B, nb, s);
+  HIPCHK(hipGetLastError());
+  std::vector<double> h((size_t)(nb + 1) * 3);
+  HIPCHK(hipMemcpyAsync(h.data(), ctx->d_mom_out, sizeof(double) * h.size(),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double n = h[3 * nb];
+  if (n < 2.0)
+    return fail(ctx, HMPS_E_STATE,
+                "fewer than two measurements accumulated (hmps_measure with "
+                "HMPS_MEASURE_ACCUMULATE)");
+  *n_samples = (int64_t)n;
+  for (int e = 0; e < nb; ++e) {
+    bond_mean[e] = h[3 * e + 1];
+    bond_var[e] = h[3 * e + 2] / (n - 1.0);
+  }
+  if (energy_mean_var) {
+    energy_mean_var[0] = h[3 * nb + 1];
+    energy_mean_var[1] = h[3 * nb + 2] / (n - 1.0);
+  }
   return HMPS_OK;
 }
 

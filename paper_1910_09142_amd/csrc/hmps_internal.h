@@ -243,6 +243,16 @@ void launch_measure_scale(const Batch &b, const MeasureArgs &m,
 // site pairs measured per pass by hmps_measure_pairs
 constexpr int PAIR_CHUNK = 256;
 
+// Per-bond sample moments (observe.hip): mom is [B][n_bonds + 1][3]
+// (count, mean, sum of squared deviations; the energy is entry n_bonds),
+// out is [n_bonds + 1][3] over all chains.
+void launch_moments_add(const double *bond_ss, const double *energy,
+                        double *mom, int B, int n_bonds, hipStream_t st);
+void launch_moments_reduce(const double *mom, double *out, int B,
+                           int n_bonds, hipStream_t st);
+// p[0 .. n) = v (a kernel, so that a captured stream records no memset)
+void launch_fill(double *p, size_t n, double v, hipStream_t st);
+
 struct CollapseArgs {
   const int32_t *is_cluster;  // [nsites]
   const int32_t *env_index;   // [nsites] index among env sites or -1

@@ -2,6 +2,8 @@
 // (Chen & Stoudenmire, arXiv:1910.09142, Hybrid METTS-Ancilla subsection):
 // initial states, measurement by transfer matrices, sequential projective
 // collapse of the environment with Philox4x64-10 draws.
+#include <algorithm>
+
 #include "device_common.h"
 
 namespace hmps {
@@ -152,6 +154,57 @@ __global__ void k_measure_finish(Batch b, MeasureArgs ma, double *energy,
 }
 
 // =====================================================================
+// Per-bond sample moments (the variance study of the estimators, Section
+// Entanglement and Cost of Hybrid States): for every chain c and every
+// bond b, and for the energy as entry n_bonds, a running count, mean and
+// sum of squared deviations, updated in the order of the measurements
+// (Welford's update, FP64).  One thread per (chain, entry); no atomics,
+// so the result does not depend on the launch.
+// =====================================================================
+__global__ void k_moments_add(const double *bond_ss, const double *energy,
+                              double *mom, int B, int nb) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * (nb + 1)) return;
+  const int c = t / (nb + 1), e = t % (nb + 1);
+  const double x = e < nb ? bond_ss[(size_t)c * nb + e] : energy[c];
+  double *m = mom + (size_t)t * 3;
+  const double n = m[0] + 1.0;
+  const double d = x - m[1];
+  const double mean = m[1] + d / n;
+  m[0] = n;
+  m[1] = mean;
+  m[2] += d * (x - mean);
+}
+
+// The chains combined in chain order (Chan, Golub and LeVeque's pairwise
+// update of count, mean and squared deviations): one thread per entry.
+__global__ void k_moments_reduce(const double *mom, double *out, int B,
+                                 int nb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e > nb) return;
+  double n = 0.0, mean = 0.0, m2 = 0.0;
+  for (int c = 0; c < B; ++c) {
+    const double *m = mom + ((size_t)c * (nb + 1) + e) * 3;
+    const double nc = m[0];
+    if (nc == 0.0) continue;
+    const double tot = n + nc;
+    const double d = m[1] - mean;
+    mean += d * (nc / tot);
+    m2 += m[2] + d * d * (n * nc / tot);
+    n = tot;
+  }
+  out[3 * e] = n;
+  out[3 * e + 1] = mean;
+  out[3 * e + 2] = m2;
+}
+
+__global__ void k_fill(double *p, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// =====================================================================
 // Collapse: E is the left density matrix of the measured/traced past.
 // =====================================================================
 __global__ void __launch_bounds__(NT) k_collapse(Batch b, CollapseArgs a) {
@@ -274,6 +327,26 @@ void launch_measure_scale(const Batch &b, const MeasureArgs &m,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_measure_scale, dim3((m.n_bonds + NT - 1) / NT, b.B),
                      dim3(NT), 0, st, b, m);
+}
+
+void launch_moments_add(const double *bond_ss, const double *energy,
+                        double *mom, int B, int n_bonds, hipStream_t st) {
+  const int n = B * (n_bonds + 1);
+  hipLaunchKernelGGL(k_moments_add, dim3((n + 255) / 256), dim3(256), 0, st,
+                     bond_ss, energy, mom, B, n_bonds);
+}
+
+void launch_moments_reduce(const double *mom, double *out, int B,
+                           int n_bonds, hipStream_t st) {
+  hipLaunchKernelGGL(k_moments_reduce, dim3((n_bonds + 256) / 256),
+                     dim3(256), 0, st, mom, out, B, n_bonds);
+}
+
+void launch_fill(double *p, size_t n, double v, hipStream_t st) {
+  if (n == 0) return;
+  const size_t blocks = std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n,
+                     v);
 }
 
 void launch_collapse(const Batch &b, const CollapseArgs &a, hipStream_t st) {

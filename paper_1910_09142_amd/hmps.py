@@ -29,6 +29,7 @@ MEASURE_BONDS = 2
 MEASURE_LOGW = 4
 MEASURE_QN = 8
 MEASURE_ALL = 15
+MEASURE_ACCUMULATE = 16    # add to the device-side moments (not an output)
 
 EXPORTS = [
     "hmps_workspace_bytes", "hmps_create", "hmps_init_cluster_env",
@@ -37,7 +38,8 @@ EXPORTS = [
     "hmps_schedule", "hmps_svd_probe", "hmps_measure_pairs",
     "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
     "hmps_apply_gate", "hmps_init_cluster_env_at", "hmps_evolve_updates",
-    "hmps_last_spectrum", "hmps_svd_probe_noalloc",
+    "hmps_last_spectrum", "hmps_svd_probe_noalloc", "hmps_moments_reset",
+    "hmps_bond_moments",
 ]
 
 
@@ -125,6 +127,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         P(C.c_double), P(C.c_double)]
     lib.hmps_apply_gate.argtypes = [C.c_void_p, C.c_double, C.c_double,
                                     C.c_int32, C.c_double, P(C.c_double)]
+    lib.hmps_moments_reset.argtypes = [C.c_void_p]
+    lib.hmps_bond_moments.argtypes = [C.c_void_p, P(C.c_int64),
+                                      P(C.c_double), P(C.c_double),
+                                      P(C.c_double)]
     lib.hmps_svd_probe_noalloc.argtypes = [
         C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
         C.c_double, C.c_void_p, P(C.c_int32), C.c_void_p, C.c_void_p]
@@ -309,6 +315,23 @@ class Context:
                 "bond_ss": ss[:, :nb] if what & MEASURE_BONDS else None,
                 "logw": lw if what & MEASURE_LOGW else None,
                 "qn": qn if what & MEASURE_QN else None}
+
+    def hmps_moments_reset(self):
+        self._check(self.lib.hmps_moments_reset(self.h), "hmps_moments_reset")
+
+    def hmps_bond_moments(self):
+        """Sample moments accumulated by hmps_measure(... |
+        MEASURE_ACCUMULATE): count, per-bond mean and variance, energy mean
+        and variance."""
+        nb = self.n_bonds
+        n = C.c_int64(0)
+        mean, var = np.zeros(max(nb, 1)), np.zeros(max(nb, 1))
+        emv = np.zeros(2)
+        self._check(self.lib.hmps_bond_moments(
+            self.h, C.byref(n), _ptr(mean, C.c_double), _ptr(var, C.c_double),
+            _ptr(emv, C.c_double)), "hmps_bond_moments")
+        return {"n": int(n.value), "mean": mean[:nb], "var": var[:nb],
+                "energy_mean": float(emv[0]), "energy_var": float(emv[1])}
 
     def hmps_collapse_resample(self, basis: int):
         out = np.zeros((self.n_chains, max(self.n_env, 1)), np.uint8)

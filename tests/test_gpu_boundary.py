@@ -148,8 +148,11 @@ def test_measure_mask_selects_outputs():
                 assert np.array_equal(part[key], full[key]), key
             else:
                 assert part[key] is None
+    # accumulating moments is not an output
+    acc = ctx.hmps_measure(hmps.MEASURE_ACCUMULATE)
+    assert all(v is None for v in acc.values())
     with pytest.raises(hmps.HmpsError) as e:
-        ctx.hmps_measure(16)
+        ctx.hmps_measure(32)
     assert e.value.status == hmps.HMPS_E_INVALID
     assert np.array_equal(ctx.hmps_measure()["energy"], full["energy"])
     ctx.hmps_destroy()

@@ -56,3 +56,22 @@ def test_product_state_correlators():
     for (i, j), v in zip(pairs, vals):
         want = 2.0 if i == j else m[i] * m[j]
         assert abs(v - want) < 1e-14
+
+
+def test_sample_moments_closed_forms():
+    # a hand-computed sample: 1, 2, 3, 4 -> mean 5/2, variance 5/3
+    n, mean, var = observables.sample_moments([[1.0], [2.0], [3.0], [4.0]])
+    assert n == 4 and mean == [2.5] and abs(var[0] - 5.0 / 3.0) < 1e-15
+    # a constant column has zero variance; columns are independent
+    n, mean, var = observables.sample_moments([[0.3, -1.0], [0.3, 1.0]] * 3)
+    assert mean == pytest.approx([0.3, 0.0]) and var[0] == 0.0
+    # two values a, b with counts k and n - k: variance k (n - k) (a - b)^2
+    # / (n (n - 1)), mean (k a + (n - k) b) / n
+    a, b, k, n = -0.75, 0.25, 7, 19
+    rows = [[a]] * k + [[b]] * (n - k)
+    got_n, mean, var = observables.sample_moments(rows)
+    assert got_n == n
+    assert abs(mean[0] - (k * a + (n - k) * b) / n) < 1e-15
+    assert abs(var[0] - k * (n - k) * (a - b) ** 2 / (n * (n - 1))) < 1e-15
+    with pytest.raises(ValueError):
+        observables.sample_moments([[1.0]])
