@@ -73,12 +73,18 @@ enum {
   PATH_SMALL = 0, PATH_PLAIN = 1, PATH_QR = 2, PATH_RR = 3, PATH_QR2 = 4,
   PATH_RR2 = 5
 };
+// The second QR pays from this many vectors on: below it the sweeps it
+// saves cost less than its launches (one chain of the 2x3 ladder, N <= 96,
+// runs 12% faster per sample with one QR; the chi = 256 gate workload, N =
+// 768, 16% faster with two).
+constexpr int QR2_MIN_N = 160;
 __host__ __device__ inline int svd_path(int L, int N, size_t small_max,
                                         int precond, int mixed) {
   if (small_path(L, N, small_max)) return PATH_SMALL;
   if (qr_path(L, N, small_max, precond)) {
-    if (mixed) return precond >= 2 ? PATH_RR2 : PATH_RR;
-    return precond >= 2 ? PATH_QR2 : PATH_QR;
+    const bool two = precond >= 2 && N >= QR2_MIN_N;
+    if (mixed) return two ? PATH_RR2 : PATH_RR;
+    return two ? PATH_QR2 : PATH_QR;
   }
   return PATH_PLAIN;
 }

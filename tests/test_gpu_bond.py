@@ -129,14 +129,16 @@ def test_mixed_precision_bond():
 def test_preconditioner_levels(level, monkeypatch):
     # HMPS_QR, read when a context is created, selects how the blocked
     # Jacobi SVD is preconditioned: none (rounds on theta'), one QR (rounds
-    # on R^T), or two (rounds on R2^T with R^T = Q2 R2, the default; the
-    # left factor from the stored reflectors).  Each level, in FP64 and in
+    # on R^T), or two (the default from 160 vectors on: rounds on R2^T with
+    # R^T = Q2 R2, the left factor from the stored reflectors).  Each level, in FP64 and in
     # mixed precision (FP32 rounds, FP64 Ritz step), gives the oracle's
     # update.
     monkeypatch.setenv("HMPS_QR", level)
     run_case(40, 40, 40, 3, 32, 1e-10, 3)
     run_case(22, 50, 60, 2, 50, 1e-12, 2)
     run_case(96, 96, 96, 1, 96, 1e-10, 2, seed=7)
+    # wide and ragged with two QRs (180 vectors of length 240)
+    run_case(60, 70, 80, 2, 70, 1e-10, 2, seed=9)
     run_case(64, 64, 64, 2, 64, 1e-10, 2, precision=hmps.PREC_MIXED_FP32,
              tol_state=5e-6, tol_logw=1e-6)
 
