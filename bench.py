@@ -128,12 +128,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(tag):
-    """HBM bytes per round-kernel launch from the committed rocprofv3
-    counter summary of this workload (FETCH_SIZE and WRITE_SIZE scaled by
-    the copy-kernel calibration), or None when there is none or it was
-    taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"k_jacobi_round_traffic_{tag}.md")
+def measured_traffic(kernel, tag):
+    """HBM bytes per launch of the round kernel `kernel` from the committed
+    rocprofv3 counter summary of this workload (FETCH_SIZE and WRITE_SIZE
+    scaled by the copy-kernel calibration), or None when there is none or
+    it was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic_{tag}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -156,6 +156,12 @@ def svd_roofline(tag, s0, s1, use_traffic):
     = Golub-Reinsch SVD flops of the updates (the algorithmic count) over
     the HIP-event span of the rounds on the library's stream."""
     launches = s1.round_launches - s0.round_launches
+    wide = s1.wide_launches - s0.wide_launches
+    # the rounds of these updates: all on 32-vector blocks, all on 16-wide
+    # ones, or both (a batch with chains on either side of the width rule)
+    kernel = ("k_jacobi_round_wide" if wide == launches else
+              "k_jacobi_round" if wide == 0 else
+              "k_jacobi_round+k_jacobi_round_wide")
     svd_s = s1.svd_seconds - s0.svd_seconds
     svd_f = s1.svd_flops - s0.svd_flops
     svd_b = s1.svd_bytes - s0.svd_bytes
@@ -164,8 +170,8 @@ def svd_roofline(tag, s0, s1, use_traffic):
         "bound": "mfma", "achieved": achieved,
         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS,
-        "traffic": measured_traffic(tag) if use_traffic else None,
-        "kernel": "k_jacobi_round",
+        "traffic": measured_traffic(kernel, tag) if use_traffic else None,
+        "kernel": kernel,
         "launches": launches,
         "avg_launch_us": 1e6 * svd_s / launches if launches else None,
         "flops_per_launch": svd_f / launches if launches else None,

@@ -140,6 +140,8 @@ typedef struct {
                                parts by hmps_evolve_updates (0: none)    */
   int64_t jacobi_sweeps_fp32; /* of jacobi_sweeps, the FP32 sweeps of the
                                mixed-precision SVD                        */
+  int64_t wide_launches;    /* of round_launches, rounds of 32-vector
+                               blocks (updates with >= 512 vectors)      */
 } hmps_stats_t;
 
 /* Bytes of device workspace needed for the given capacities. */

@@ -32,6 +32,14 @@ constexpr int OP_SWAP = -1;
 constexpr int RR_FP32_SWEEPS = 40;
 constexpr int OP_IDENT = -2;
 constexpr size_t ALIGN = 256;
+// Batches from this many chains on take wide (32-vector) blocks for their
+// large FP64 updates.  A wide block pair is four times the MFMA work of a
+// 16-wide one on a single compute unit, in half as many workgroups: it
+// pays once the rounds fill the chip.  Measured on the chi = 256 gate (768
+// vectors): 4 chains 143 vs 181 updates/s, 8: 278 vs 357, 16: 528 vs
+// 516, 32: 710 vs 662, 64: 909 vs 762.  A chain's result depends on its
+// own input and on this choice only.
+constexpr int WIDE_MIN_CHAINS = 16;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -254,6 +262,9 @@ struct hmps_ctx {
   // their two blocks (16 inner rounds instead of 31): measured on the same
   // ladder, 4% more outer sweeps and 23% less time (one chain).
   int cross_inner = 1;
+  // wide (32-vector) blocks for the large FP64 updates: -1 = from
+  // WIDE_MIN_CHAINS chains on, 0 = never, 1 = always (HMPS_WIDE)
+  int wide = -1;
   // largest theta' (m * n doubles) whose SVD runs in one workgroup's LDS;
   // larger ones take the blocked rounds.  The in-LDS kernel runs its pair
   // products on vector lanes, so beyond a few thousand entries the blocked
@@ -314,7 +325,7 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   const size_t site_cap = 3 * chi2;
   const int mc = 3 * chi_cap;
   // padded vector count: an even number of blocks of JB vectors
-  const int n_cap = (mc + 2 * JB - 1) / (2 * JB) * (2 * JB);
+  const int n_cap = npad_vectors(mc);
   // vectors of length L <= 3 chi_cap are stored with stride vector_stride
   const size_t th_stride = (size_t)vector_stride(mc) * n_cap;
   const int slots = std::max(2, std::min(std::max(max_bonds, 1), 8));
@@ -490,7 +501,10 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   // entries, else on the blocked rounds; the rounds' grid is sized by the
   // blocked chains alone
   int n_small = 0, n_blocked = 0, n_qr = 0, n_rr = 0, n_qr2 = 0;
-  int max_nb = 2, max_nb32 = 2, max_vlen = 1, max_nvec = 1, max_qr_n = 0;
+  // max_nb: 16-wide FP64 blocks, max_nbw: wide blocks (0: no chain takes
+  // that width), max_nb32: the FP32 rounds of the mixed path (16-wide)
+  int max_nb = 0, max_nbw = 0, max_nb32 = 2, max_vlen = 1, max_nvec = 1,
+      max_qr_n = 0;
   int max_rr_n = 0, max_rr_l = 0, max_qr2_n = 0;
   double flops = 0.0, svd_flops = 0.0;
   const bool is_move = (op == OP_IDENT);
@@ -498,6 +512,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   // by the host) is the FP64 SVD: both always FP64
   const int mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32 && !is_move &&
                     !ctx->skip_theta;
+  const int wide = ctx->wide >= 0 ? ctx->wide : (ctx->B >= WIDE_MIN_CHAINS);
   for (int c = 0; c < ctx->B; ++c) {
     const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
     {
@@ -528,6 +543,8 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
         max_nb32 = std::max(max_nb32, n_blocks_even(nvec, JB));
         max_nb = std::max(max_nb,
                           n_blocks_even(rr_vectors(nvec, chi_max), JB));
+      } else if (round_width(path, nvec, wide) == JBW) {
+        max_nbw = std::max(max_nbw, n_blocks_even(nvec, JBW));
       } else {
         max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
       }
@@ -562,6 +579,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   u.inner_sweeps = ctx->inner_sweeps;
   u.skip = ctx->skip;
   u.cross_inner = ctx->cross_inner;
+  u.wide = wide;
   Batch b = batch_of(ctx);
   UpdScratch s = scratch_of(ctx);
   hipStream_t st = ctx->stream;
@@ -608,9 +626,16 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
           else
             launch_jacobi_round(b, s, u, r, nb_max / 2, st);
         }
+        ctx->stats.round_launches += std::max(0, nb_max - 1);
+        // the chains on wide blocks: half the rounds per sweep
+        if (!f32 && max_nbw > 0) {
+          for (int r = 0; r < max_nbw - 1; ++r)
+            launch_jacobi_round_wide(b, s, u, r, max_nbw / 2, st);
+          ctx->stats.round_launches += max_nbw - 1;
+          ctx->stats.wide_launches += max_nbw - 1;
+        }
         ctx->stats.jacobi_sweeps += 1;
         if (f32) ctx->stats.jacobi_sweeps_fp32 += 1;
-        ctx->stats.round_launches += nb_max - 1;
         int32_t *slot =
             ctx->h_stage + (size_t)(2 + (sweep & 1)) * ctx->opt.max_chains;
         HIPCHK(hipMemcpyAsync(slot, ctx->d_rot, sizeof(int32_t) * ctx->B,
@@ -640,10 +665,11 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
           nv = rr_vectors(nvec, chi_max);
           if (path == PATH_RR2) vlen = nvec;  // R^T W
         }
-        const int nb = n_blocks_even(nv, JB);
+        const int jb = f32 ? JB : round_width(path, nv, wide);
+        const int nb = n_blocks_even(nv, jb);
         const bool part = f32 ? path_is_rr(path) : path != PATH_SMALL;
         round_bytes[c] =
-            part ? (double)(nb - 1) * nb * JB * vector_stride(vlen) * esz : 0.0;
+            part ? (double)(nb - 1) * nb * jb * vector_stride(vlen) * esz : 0.0;
       }
       hmps_status est = enqueue_sweep(0);
       if (est) return est;
@@ -805,6 +831,8 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
   if (const char *e = std::getenv("HMPS_INNER")) ctx->inner_sweeps = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("HMPS_SKIP")) ctx->skip = std::min(1e-26, std::atof(e));
   if (const char *e = std::getenv("HMPS_CROSS")) ctx->cross_inner = e[0] == '1';
+  if (const char *e = std::getenv("HMPS_WIDE"))
+    ctx->wide = e[0] == '0' ? 0 : (e[0] == '1' ? 1 : -1);
   if (const char *e = std::getenv("HMPS_QR"))
     ctx->precond = std::max(0, std::min(2, std::atoi(e)));
   if (const char *e = std::getenv("HMPS_SMALL_MAX"))

@@ -19,9 +19,18 @@ __host__ __device__ inline int vector_stride(int len) {
 }
 
 // Number of column blocks, rounded up to an even count.
-__host__ __device__ inline int n_blocks_even(int nvec, int jb) {
-  const int nb = (nvec + jb - 1) / jb;
-  return nb + (nb & 1);
+__host__ __device__ constexpr int n_blocks_even(int nvec, int jb) {
+  return (nvec + jb - 1) / jb + (((nvec + jb - 1) / jb) & 1);
+}
+// Wide rounds: blocks of JBW vectors (pairs of 64) for the chains with at
+// least W32_MIN_N vectors on the FP64 blocked paths -- half the rounds per
+// sweep, so half the passes over the vectors (jacobi.hip).
+constexpr int JBW = 32;
+constexpr int W32_MIN_N = 512;
+// Vectors of the blocked paths padded with zero vectors to an even number
+// of blocks of either width.
+__host__ __device__ constexpr int npad_vectors(int nvec) {
+  return n_blocks_even(nvec, JBW) * JBW;
 }
 // Largest m * n_even (doubles) handled by the single-workgroup SVD whose
 // matrix lives entirely in LDS.
@@ -87,6 +96,16 @@ __host__ __device__ inline int svd_path(int L, int N, size_t small_max,
     return two ? PATH_QR2 : PATH_QR;
   }
   return PATH_PLAIN;
+}
+// Block width of a chain's Jacobi rounds: JBW for the FP64 blocked paths
+// from W32_MIN_N vectors on (when `wide`), JB otherwise.  The choice
+// depends on the chain's own dimensions and on `wide`, which the host
+// sets for the whole update.
+__host__ __device__ inline int round_width(int path, int nvec, int wide) {
+  return (wide && nvec >= W32_MIN_N &&
+          (path == PATH_PLAIN || path == PATH_QR || path == PATH_QR2))
+             ? JBW
+             : JB;
 }
 // The paths whose first step is theta' = Q R, those with a second QR, and
 // the mixed-precision paths.
@@ -172,6 +191,7 @@ struct UpdParams {
   double skip;        // relative squared norm below which a vector is zero
   double skip32;      // the same for the FP32 rounds
   int cross_inner;    // inner rotations across the two blocks only (rounds > 0)
+  int wide;           // wide (32-vector) blocks allowed
   int precond;        // QR preconditioning of the blocked path: 0 none,
                       // 1 one QR, 2 two (FP64)
   size_t small_max;   // largest L * N of the in-LDS SVD path
@@ -194,6 +214,10 @@ void launch_jacobi_round(const Batch &b, const UpdScratch &s,
 void launch_jacobi_round32(const Batch &b, const UpdScratch &s,
                            const UpdParams &u, int round, int max_pairs,
                            hipStream_t st);
+// Round `round` of the wide (JBW) blocks of the chains that take them.
+void launch_jacobi_round_wide(const Batch &b, const UpdScratch &s,
+                              const UpdParams &u, int round, int max_pairs,
+                              hipStream_t st);
 void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
                      hipStream_t st);
 // qr2_panels: panels of the largest PATH_QR2 chain (0: none)

@@ -187,6 +187,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   // in X (second stage); on the two-QR mixed path the FP32 copy of R2^T in
   // Y, then the rrk columns of R^T W in Y; theta' in X else
   if (F32 && !path_is_rr(path)) return;
+  if (!F32 && round_width(path, N, u.wide) != JB) return;  // wide rounds
   const int L = (F32 || path == PATH_QR || path_has_qr2(path)) ? N : Lt;
   const int nvec = (!F32 && path_is_rr(path)) ? s.rrk[c] : N;
   const int NB = n_blocks_even(nvec, JB);
@@ -515,6 +516,378 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   if (tid == 0) atomicAdd(&s.rot_cur[c], 1);
 }
 
+
+// =====================================================================
+// Wide rounds: blocks of JBW = 32 vectors, one workgroup per block pair of
+// 64 vectors, for the chains that take them (round_width).  A sweep has
+// NB - 1 rounds of NB / 2 pairs: half the rounds, and half the passes over
+// the vectors, of the 16-wide rounds.  Per round:
+//   1. Gram of the 64 vectors, its ten upper 16 x 16 tiles by FP64 MFMA:
+//      waves 0-3 accumulate tiles (0,0) (0,1) (0,2) (0,3) (1,1) of the four
+//      16-vector sub-blocks, waves 4-7 the other five, each group over all
+//      16-row chunks (the second load of a chunk hits L2); the partials are
+//      summed in a fixed order;
+//   2. the convergence test of the 16-wide rounds;
+//   3. one cyclic Jacobi sweep of the 64 x 64 Gram, its upper triangle
+//      packed and double-buffered in LDS, one barrier per rotation round:
+//      lanes 0-31 of wave 0 derive the next round's angles (recomputing the
+//      entries they need as the block owners do), waves 1-7 own the 528
+//      2 x 2 blocks; on the cross rounds every thread keeps four (row,
+//      pair) items of Q in registers, the second column of a pair moving
+//      one lane per round; on the all-pairs round Q is updated in LDS;
+//   4. Xp <- Xp Q by FP64 MFMA, each wave reading and writing whole 16-row
+//      chunks of all 64 vectors.
+// =====================================================================
+constexpr int W_P2 = 2 * JBW;
+constexpr int W_NPAIR = JBW;
+constexpr int W_TRI = W_P2 * (W_P2 + 1) / 2;
+constexpr int W_NTILE = 10;
+constexpr int W_NBLK = W_NPAIR * (W_NPAIR + 1) / 2;
+// waves 1.. own the blocks: wave 0 derives the angles, and a wave whose
+// lanes split between the two tasks would run them one after the other
+constexpr int W_OWN0 = 64;
+constexpr int W_OWNERS = RT - W_OWN0;
+static_assert(W_NBLK <= 2 * W_OWNERS, "two blocks per owner at most");
+
+// packed upper triangle, i <= j
+__device__ __forceinline__ int wtri(int i, int j) {
+  return i * W_P2 - (i * (i - 1)) / 2 + (j - i);
+}
+
+__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
+    k_jacobi_round_wide(Batch b, UpdScratch s, UpdParams u, int r) {
+  const int c = blockIdx.y, pi = blockIdx.x;
+  if (s.done[c]) return;
+  const int32_t *chi = chi_row(b, c);
+  const int m = 3 * chi[u.k], n = 3 * chi[u.k + 2];
+  const int Lt = m > n ? m : n, N = m > n ? n : m;
+  const int path = svd_path(Lt, N, u.small_max, u.precond, u.mixed);
+  if (round_width(path, N, u.wide) != JBW) return;
+  const int L = (path == PATH_QR || path == PATH_QR2) ? N : Lt;
+  const int NB = n_blocks_even(N, JBW);
+  if (r >= NB - 1 || pi >= NB / 2) return;
+  const int ld = vec_ld(L);
+  int bi, bj;
+  rr_pair(r, pi, NB, bi, bj);
+  double *base = path == PATH_QR2 ? s.Z : (path == PATH_QR ? s.Y : s.X);
+  double *X = base + (size_t)c * s.th_stride;
+  const double tol = u.tol, skip = u.skip;
+  auto colidx = [&](int t) {
+    return t < JBW ? bi * JBW + t : bj * JBW + t - JBW;
+  };
+
+  __shared__ double G[2][W_TRI];
+  // partial Gram tiles (two slots), reused as Q once they are summed
+  __shared__ double scratch[2 * W_NTILE * 256];
+  static_assert(W_P2 * (W_P2 + 1) <= 2 * W_NTILE * 256, "Q fits");
+  double (*Q)[W_P2 + 1] = reinterpret_cast<double (*)[W_P2 + 1]>(scratch);
+  __shared__ double2 csn[2][W_NPAIR];
+  __shared__ int flag[2];
+  const bool cross = u.cross_inner && r > 0;
+  const int nrounds = cross ? W_NPAIR : W_P2 - 1;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int grp = w >> 2, wl = w & 3;
+  auto gs = [&](double *Gm, int x, int y) -> double & {
+    return x <= y ? Gm[wtri(x, y)] : Gm[wtri(y, x)];
+  };
+
+  // ---- 1. Gram matrix -----------------------------------------------------
+  if (tid == 0) {
+    flag[0] = 0;
+    flag[1] = 0;
+  }
+  {
+    constexpr int CSTEP = 16 * 4;  // four waves per group
+    v4d acc[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    const double *xs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      xs[k] = X + (size_t)colidx(16 * k + li) * ld + 4 * lk;
+    auto load4 = [&](int e0, v4d (&v)[4]) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        v[k] = *reinterpret_cast<const v4d *>(xs[k] + e0);
+    };
+    auto mm = [&](v4d &a, const v4d &x, const v4d &y) {
+      a = mfma_f64(x.x, y.x, a);
+      a = mfma_f64(x.y, y.y, a);
+      a = mfma_f64(x.z, y.z, a);
+      a = mfma_f64(x.w, y.w, a);
+    };
+    auto gram = [&](const v4d (&v)[4]) {
+      if (grp == 0) {
+        mm(acc[0], v[0], v[0]);
+        mm(acc[1], v[0], v[1]);
+        mm(acc[2], v[0], v[2]);
+        mm(acc[3], v[0], v[3]);
+        mm(acc[4], v[1], v[1]);
+      } else {
+        mm(acc[0], v[1], v[2]);
+        mm(acc[1], v[1], v[3]);
+        mm(acc[2], v[2], v[2]);
+        mm(acc[3], v[2], v[3]);
+        mm(acc[4], v[3], v[3]);
+      }
+    };
+    const int elast = ld - 16;
+    int e0 = 16 * wl;
+    v4d a0[4], a1[4];
+    load4(min(e0, elast), a0);
+    while (e0 < L) {
+      load4(min(e0 + CSTEP, elast), a1);
+      asm volatile("" ::: "memory");
+      gram(a0);
+      if (e0 + CSTEP >= L) break;
+      load4(min(e0 + 2 * CSTEP, elast), a0);
+      asm volatile("" ::: "memory");
+      gram(a1);
+      e0 += 2 * CSTEP;
+    }
+    // fixed-order sum of the four partials of each tile: waves wl = 0, 1
+    // write slots 0, 1, then waves wl = 2, 3 add into them
+    double *part = scratch + (size_t)(wl & 1) * W_NTILE * 256;
+#pragma unroll
+    for (int step = 0; step < 2; ++step) {
+      if ((wl >> 1) == step) {
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double *dst = part + (5 * grp + t) * 256 + (lk + 4 * q) * 16 + li;
+            *dst = step == 0 ? acc[t][q] : *dst + acc[t][q];
+          }
+      }
+      __syncthreads();
+    }
+  }
+  // packed upper triangle of G from the tiles: tile (x, y), x <= y, of the
+  // 16-vector sub-blocks -> partial index
+  for (int idx = tid; idx < W_P2 * W_P2; idx += RT) {
+    const int i = idx / W_P2, j = idx % W_P2;
+    if (i > j) continue;
+    const int x = i >> 4, y = j >> 4;
+    const int tile = x == 0 ? y : (x == 1 ? (y == 1 ? 4 : y + 3)
+                                          : (x == 2 ? (y == 2 ? 7 : 8) : 9));
+    const int o = tile * 256 + (i & 15) * 16 + (j & 15);
+    G[0][wtri(i, j)] = scratch[o] + scratch[W_NTILE * 256 + o];
+  }
+  __syncthreads();
+
+  // ---- 2. convergence test; Q = I; angles of the first rotation round -----
+  const double tol_in = fmax(0.125 * tol, 4e-16);
+  int needs = 0;
+  for (int idx = tid; idx < W_P2 * W_P2; idx += RT) {
+    const int i = idx / W_P2, j = idx % W_P2;
+    if (i < j && (!cross || (i < W_NPAIR && j >= W_NPAIR)) &&
+        pair_needs_rotation(G[0][wtri(i, i)], G[0][wtri(j, j)],
+                            G[0][wtri(i, j)], tol, skip))
+      needs = 1;
+    Q[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  if (tid < W_NPAIR) {
+    int p, q;
+    inner_pair(cross, 0, tid, W_P2, p, q);
+    double cr = 1.0, sr = 0.0;
+    if (pair_rotation(G[0][wtri(p, p)], G[0][wtri(q, q)], G[0][wtri(p, q)],
+                      tol_in, skip, cr, sr))
+      flag[0] = 1;
+    csn[0][tid] = make_double2(cr, sr);
+  }
+  if (__syncthreads_or(needs) == 0) {
+    if (tid < W_P2) {
+      const int col = colidx(tid);
+      if (col < N) s.sig2[(size_t)c * s.n_cap + col] = G[0][wtri(tid, tid)];
+    }
+    return;
+  }
+
+  // ---- 3. inner Jacobi sweep on G, rotations accumulated in Q -------------
+  int brp[2] = {0, 0}, bcp[2] = {0, 0};
+  bool own[2] = {false, false};
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    int k = tid - W_OWN0 + W_OWNERS * o;
+    own[o] = tid >= W_OWN0 && k < W_NBLK;
+    if (own[o]) {
+      int rp = 0;
+      while (k >= W_NPAIR - rp) {
+        k -= W_NPAIR - rp;
+        ++rp;
+      }
+      brp[o] = rp;
+      bcp[o] = rp + k;
+    }
+  }
+  // cross rounds: thread (row, i) holds Q[row][i] and Q[row][32 + (i + rr)
+  // % 32] for rows (tid >> 5) + 16 m
+  const int qi = tid & 31, qrow = tid >> 5;
+  double qa[4], qb[4];
+#pragma unroll
+  for (int mm = 0; mm < 4; ++mm) {
+    const int row = qrow + 16 * mm;
+    qa[mm] = row == qi ? 1.0 : 0.0;
+    qb[mm] = row == W_NPAIR + qi ? 1.0 : 0.0;
+  }
+  int gr = 0;
+  for (int isw = 0; isw < u.inner_sweeps; ++isw) {
+    for (int rr = 0; rr < nrounds; ++rr, ++gr) {
+      const int cur = gr & 1, nxt = cur ^ 1;
+      const int rn = rr + 1 < nrounds ? rr + 1 : 0;
+      double *Gc = G[cur];
+      double *Gn = G[nxt];
+      if (tid < W_NPAIR) {
+        // angles of pair tid of the next round: its members are row ra of
+        // pair ia = (a0, a1) and row rb of pair ib = (b0, b1) of this round
+        int pn, qn, ia, pa, ib, pb;
+        inner_pair(cross, rn, tid, W_P2, pn, qn);
+        inner_slot(cross, rr, pn, W_P2, ia, pa);
+        inner_slot(cross, rr, qn, W_P2, ib, pb);
+        const int ra = pn < pa ? 0 : 1, rb = qn < pb ? 0 : 1;
+        const int a0 = ra ? pa : pn, a1 = ra ? pn : pa;
+        const int b0 = rb ? pb : qn, b1 = rb ? qn : pb;
+        const double2 ja = csn[cur][ia], jb = csn[cur][ib];
+        double g[4], nv[4];
+        g[0] = Gc[wtri(a0, a0)];
+        g[1] = Gc[wtri(a0, a1)];
+        g[2] = g[1];
+        g[3] = Gc[wtri(a1, a1)];
+        rot_block(ja.x, ja.y, ja.x, ja.y, g, nv);
+        const double app = ra ? nv[3] : nv[0];
+        g[0] = Gc[wtri(b0, b0)];
+        g[1] = Gc[wtri(b0, b1)];
+        g[2] = g[1];
+        g[3] = Gc[wtri(b1, b1)];
+        rot_block(jb.x, jb.y, jb.x, jb.y, g, nv);
+        const double aqq = rb ? nv[3] : nv[0];
+        double apq;
+        if (ia < ib) {
+          g[0] = gs(Gc, a0, b0);
+          g[1] = gs(Gc, a0, b1);
+          g[2] = gs(Gc, a1, b0);
+          g[3] = gs(Gc, a1, b1);
+          rot_block(ja.x, ja.y, jb.x, jb.y, g, nv);
+          apq = ra ? (rb ? nv[3] : nv[2]) : (rb ? nv[1] : nv[0]);
+        } else {
+          g[0] = gs(Gc, b0, a0);
+          g[1] = gs(Gc, b0, a1);
+          g[2] = gs(Gc, b1, a0);
+          g[3] = gs(Gc, b1, a1);
+          rot_block(jb.x, jb.y, ja.x, ja.y, g, nv);
+          apq = rb ? (ra ? nv[3] : nv[2]) : (ra ? nv[1] : nv[0]);
+        }
+        double cr = 1.0, sr = 0.0;
+        const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
+        if (rot) flag[(isw + (rn == 0)) & 1] = 1;
+        csn[nxt][tid] = make_double2(cr, sr);
+      }
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        if (own[o]) {
+          int p1, q1, p2, q2;
+          inner_pair(cross, rr, brp[o], W_P2, p1, q1);
+          inner_pair(cross, rr, bcp[o], W_P2, p2, q2);
+          const double2 j1 = csn[cur][brp[o]], j2 = csn[cur][bcp[o]];
+          double g[4], nv[4];
+          g[0] = gs(Gc, p1, p2);
+          g[1] = gs(Gc, p1, q2);
+          g[2] = gs(Gc, q1, p2);
+          g[3] = gs(Gc, q1, q2);
+          rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
+          gs(Gn, p1, p2) = nv[0];
+          gs(Gn, p1, q2) = nv[1];
+          if (brp[o] != bcp[o]) gs(Gn, q1, p2) = nv[2];
+          gs(Gn, q1, q2) = nv[3];
+        }
+      }
+      if (cross) {
+        const double2 jq = csn[cur][qi];
+        const int src = (lane & 32) | ((lane + 1) & 31);
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+          const double na = jq.x * qa[mm] - jq.y * qb[mm];
+          const double nb = jq.y * qa[mm] + jq.x * qb[mm];
+          qa[mm] = na;
+          qb[mm] = __shfl(nb, src);
+        }
+      } else {
+        for (int item = tid - 64; item >= 0 && item < W_P2 * W_NPAIR;
+             item += RT - 64) {
+          const int row = item / W_NPAIR, cp = item % W_NPAIR;
+          int p, q;
+          inner_pair(false, rr, cp, W_P2, p, q);
+          const double2 jq = csn[cur][cp];
+          const double x = Q[row][p], y = Q[row][q];
+          Q[row][p] = jq.x * x - jq.y * y;
+          Q[row][q] = jq.y * x + jq.x * y;
+        }
+      }
+      __syncthreads();
+      if (rr == 0 && tid == 0) flag[(isw + 1) & 1] = 0;
+    }
+    if (!flag[isw & 1]) break;
+  }
+  if (cross) {
+    // an inner sweep is W_NPAIR shifts: the second column is 32 + i again
+#pragma unroll
+    for (int mm = 0; mm < 4; ++mm) {
+      Q[qrow + 16 * mm][qi] = qa[mm];
+      Q[qrow + 16 * mm][W_NPAIR + qi] = qb[mm];
+    }
+    __syncthreads();
+  }
+
+  // ---- 4. Xp <- Xp Q, as D = Q^T Xp^T per 16-row chunk --------------------
+  // each wave takes every eighth chunk; lane (li, lk) reads row e0 + li of
+  // vectors 4 kk + lk (kk < 16) and writes row e0 + li of the vectors
+  // 16 t + lk + 4 q of the four output tiles
+  // Each chunk is loaded in two halves (the 32 vectors of block I, then of
+  // block J: eight operands per lane each) into four accumulator tiles, and
+  // stored once both halves are in.
+  // 32-bit element offsets from one per-lane base per block: vector
+  // colidx(32 g + t) = (g ? bj : bi) * 32 + t, so the offset of lane
+  // group lk's vector 4 k + lk at row e is gbase[g] + 4 k ld + e, with the
+  // 4 k ld part uniform (per-vector pointers hoisted out of the loop would
+  // take the registers the accumulators need)
+  constexpr int CSTEP = 16 * NWAVE;
+  const int gbase0 = (bi * JBW + lk) * ld, gbase1 = (bj * JBW + lk) * ld;
+  for (int e0 = 16 * w; e0 < L; e0 += CSTEP) {
+    // keeps the Q operands inside the loop: hoisted out they would not fit
+    // the registers
+    asm volatile("" ::: "memory");
+    const int e = e0 + li;
+    v4d d[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int o = (g ? gbase1 : gbase0) + e;
+      double v[8];
+#pragma unroll
+      for (int k8 = 0; k8 < 8; ++k8) v[k8] = X[o + 4 * k8 * ld];
+#pragma unroll
+      for (int k8 = 0; k8 < 8; ++k8) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          d[t] = mfma_f64(Q[32 * g + 4 * k8 + lk][16 * t + li], v[k8], d[t]);
+        // at most four Q operands in flight
+        asm volatile("" ::: "memory");
+      }
+    }
+    // D_t[i][j] (vector 16 t + i, row e0 + j) in lane j, element q with
+    // i = lk + 4 q: block t >> 1, vector 16 (t & 1) + lk + 4 q of it
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int o = ((t >> 1) ? gbase1 : gbase0) + e + 16 * (t & 1) * ld;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) X[o + 4 * q * ld] = d[t][q];
+    }
+  }
+  if (tid == 0) atomicAdd(&s.rot_cur[c], 1);
+}
+
 }  // namespace
 
 void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
@@ -527,6 +900,13 @@ void launch_jacobi_round(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, int round, int max_pairs,
                          hipStream_t st) {
   hipLaunchKernelGGL(k_jacobi_round<double>, dim3(max_pairs, b.B), dim3(RT), 0,
+                     st, b, s, u, round);
+}
+
+void launch_jacobi_round_wide(const Batch &b, const UpdScratch &s,
+                              const UpdParams &u, int round, int max_pairs,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_round_wide, dim3(max_pairs, b.B), dim3(RT), 0,
                      st, b, s, u, round);
 }
 

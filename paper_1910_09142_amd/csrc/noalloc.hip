@@ -20,7 +20,8 @@ namespace {
 // Capacity: chi_l, chi_r <= NA_CHI (theta' up to 384 x 384).
 constexpr int NA_CHI = 128;
 constexpr int NA_MC = 3 * NA_CHI;
-constexpr int NA_NCAP = (NA_MC + 2 * JB - 1) / (2 * JB) * (2 * JB);
+constexpr int NA_NCAP = npad_vectors(NA_MC);
+static_assert(NA_MC < W32_MIN_N, "the rounds here are the 16-wide ones");
 constexpr size_t NA_STRIDE = (size_t)((NA_MC + 15) & ~15) * NA_NCAP;
 constexpr size_t NA_SITE = (size_t)3 * NA_CHI * NA_CHI;
 constexpr size_t na_al(size_t doubles) { return (doubles + 31) / 32 * 32; }
@@ -180,6 +181,7 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   u.cross_inner = 1;
   u.precond = 2;
   u.small_max = 2048;
+  u.wide = 0;  // theta' here stays below the wide-block size
   hipLaunchKernelGGL(k_na_setup, dim3(64), dim3(256), 0, st, theta, chi_l,
                      chi_r, base);
   if (small_path(L, N, u.small_max)) {

@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(PT) k_qr_to_vectors(Batch b, UpdScratch s,
   const QDims d = qdims(b, c, u, s, stage);
   if (!d.qr) return;
   const int ldN = vec_ld(d.N);
-  const int npad = n_blocks_even(d.N, JB) * JB;
+  const int npad = npad_vectors(d.N);
   const int i0 = 16 * blockIdx.x, jj0 = 16 * blockIdx.y;  // vector, element
   if (i0 >= npad || jj0 >= ldN) return;
   const double *X = d.M;
@@ -376,7 +376,7 @@ void launch_qr_apply(const Batch &b, const UpdScratch &s, const UpdParams &u,
 void launch_qr_to_vectors(const Batch &b, const UpdScratch &s,
                           const UpdParams &u, int stage, int max_N,
                           hipStream_t st) {
-  const int npad = n_blocks_even(max_N, JB) * JB;
+  const int npad = npad_vectors(max_N);
   dim3 grid(npad / 16, vector_stride(max_N) / 16, b.B);
   hipLaunchKernelGGL(k_qr_to_vectors, grid, dim3(PT), 0, st, b, s, u, stage);
 }

@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(NT) k_pad(Batch b, UpdScratch s, UpdParams u) 
   const int c = blockIdx.y;
   const Dims d = dims_of(b, c, u.k);
   const bool qr = path_has_qr(path_of(d, u));
-  const int npad = n_blocks_even(d.N, JB) * JB;
+  const int npad = npad_vectors(d.N);
   double *X = s.X + (size_t)c * s.th_stride;
   const int tail = d.ld - d.L;
   if (tail > 0)

@@ -42,15 +42,16 @@ def test_the_drivers_command_fits_its_time_limit():
 
 
 def test_traffic_is_used_only_for_the_measured_sources(monkeypatch):
-    tags = [f[len("k_jacobi_round_traffic_"):-3]
-            for f in os.listdir(os.path.join(ROOT, "profiles"))
-            if f.startswith("k_jacobi_round_traffic_")]
-    for tag in tags:
-        t = bench.measured_traffic(tag)
+    found = []
+    for f in os.listdir(os.path.join(ROOT, "profiles")):
+        if "_traffic_" in f and f.endswith(".md"):
+            kernel, tag = f[:-3].split("_traffic_", 1)
+            found.append((kernel, tag, f))
+    for kernel, tag, f in found:
+        t = bench.measured_traffic(kernel, tag)
         recorded = None
-        with open(os.path.join(ROOT, "profiles",
-                               f"k_jacobi_round_traffic_{tag}.md")) as f:
-            for line in f:
+        with open(os.path.join(ROOT, "profiles", f)) as fh:
+            for line in fh:
                 if line.startswith("source_sha256:"):
                     recorded = line.split(":", 1)[1].strip().strip("`")
         if recorded == bench.kernel_source_hash():
@@ -58,10 +59,12 @@ def test_traffic_is_used_only_for_the_measured_sources(monkeypatch):
         else:
             assert t is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
-    for tag in tags:
-        assert bench.measured_traffic(tag) is None
+    for kernel, tag, _ in found:
+        assert bench.measured_traffic(kernel, tag) is None
     # a workload without a counter summary has no traffic figure
-    assert bench.measured_traffic(workloads.C1.name) is None
+    assert bench.measured_traffic("k_jacobi_round", workloads.C1.name) is None
+    assert bench.measured_traffic("k_jacobi_round_wide",
+                                  workloads.C1.name) is None
 
 
 def test_oracle_baseline_on_a_small_bond():

@@ -53,7 +53,8 @@ def oracle_state(psi):
 
 def run_case(chi_l, chi_m, chi_r, n_chains, chi_max, cutoff, n_apply,
              precision=hmps.PREC_FP64, J=1.0, x=0.025, seed=3,
-             tol_state=1e-10, tol_logw=1e-12):
+             tol_state=1e-10, tol_logw=1e-12, wide=None):
+    """wide: None, or whether the rounds must have taken wide blocks."""
     print(f"case: bond {chi_l}x{chi_m}x{chi_r}, {n_chains} chains, "
           f"chi_max {chi_max}, precision {precision}", flush=True)
     center, right = workloads.bond_tensors(seed, n_chains, chi_l, chi_m,
@@ -89,6 +90,8 @@ def run_case(chi_l, chi_m, chi_r, n_chains, chi_max, cutoff, n_apply,
                 V = T1.transpose(1, 0, 2).reshape(k, -1)
                 iso = V @ V.T
             assert np.abs(iso - np.eye(k)).max() < 1e-12, (it, c)
+    if wide is not None:
+        assert (ctx.hmps_stats().wide_launches > 0) == wide
     ctx.hmps_destroy()
 
 
@@ -118,6 +121,48 @@ def test_chi512_largest_bond():
     # the largest chi_max of the ladder workloads: theta' 1536 x 1536,
     # 96 blocks of 16 vectors, theta and write-back at full size
     run_case(512, 512, 512, 1, 512, 1e-10, 2, seed=11)
+
+
+def test_wide_blocks_from_sixteen_chains():
+    # theta' 540 x 540 in 16 chains: the rounds take 32-vector blocks (18
+    # of them, the last ragged), each block pair one workgroup; every chain
+    # matches the oracle to the same bars as the 16-wide rounds
+    run_case(180, 180, 180, 16, 180, 1e-10, 2, seed=13, wide=True)
+
+
+def test_wide_blocks_follow_the_batch_size(monkeypatch):
+    # HMPS_WIDE (read when a context is created): unset, wide blocks from
+    # 16 chains on; 1 always (on the FP64 paths from 512 vectors); 0 never
+    run_case(180, 180, 180, 2, 180, 1e-10, 1, seed=13, wide=False)
+    monkeypatch.setenv("HMPS_WIDE", "1")
+    run_case(180, 180, 180, 2, 180, 1e-10, 2, seed=13, wide=True)
+    run_case(256, 256, 256, 1, 200, 1e-10, 2, seed=5, wide=True)
+    monkeypatch.setenv("HMPS_WIDE", "0")
+    run_case(180, 180, 180, 16, 180, 1e-10, 1, seed=13, wide=False)
+
+
+def test_wide_batch_is_bit_identical_to_single_chains(monkeypatch):
+    # a chain's update depends on its own input and the block width only:
+    # in a batch of 16 (wide by default) and alone with wide blocks forced
+    # it gives the same bits
+    chi, n = 180, 16
+    center, right = workloads.bond_tensors(21, n, chi, chi, chi)
+    ctx = hmps.Context(n, 2, chi, 1)
+    ctx.hmps_load_bond(center, right)
+    ctx.hmps_apply_gate(1.0, 0.025, chi, 1e-10)
+    assert ctx.hmps_stats().wide_launches > 0
+    batch = [(ctx.hmps_read_site(c, 0), ctx.hmps_read_site(c, 1))
+             for c in (0, 7, 15)]
+    ctx.hmps_destroy()
+    monkeypatch.setenv("HMPS_WIDE", "1")
+    ctx = hmps.Context(1, 2, chi, 1)
+    for i, c in enumerate((0, 7, 15)):
+        ctx.hmps_load_bond(center[c:c + 1], right[c:c + 1])
+        ctx.hmps_apply_gate(1.0, 0.025, chi, 1e-10)
+        assert np.array_equal(ctx.hmps_read_site(0, 0), batch[i][0])
+        assert np.array_equal(ctx.hmps_read_site(0, 1), batch[i][1])
+    assert ctx.hmps_stats().wide_launches > 0
+    ctx.hmps_destroy()
 
 
 def test_mixed_precision_bond():

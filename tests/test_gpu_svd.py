@@ -57,12 +57,28 @@ CASES = [
 
 @pytest.mark.parametrize("chi_l,chi_r,kind,chi_max,cutoff", CASES)
 def test_truncated_svd_against_lapack(chi_l, chi_r, kind, chi_max, cutoff):
+    check_svd(chi_l, chi_r, kind, chi_max, cutoff, False)
+
+
+# the cases with at least 512 vectors, with the rounds on 32-vector blocks
+# (HMPS_WIDE=1; by default a single update takes 16-wide blocks)
+@pytest.mark.parametrize("chi_l,chi_r,kind,chi_max,cutoff",
+                         [c for c in CASES if 3 * min(c[0], c[1]) >= 512])
+def test_truncated_svd_wide_blocks(chi_l, chi_r, kind, chi_max, cutoff,
+                                   monkeypatch):
+    monkeypatch.setenv("HMPS_WIDE", "1")
+    check_svd(chi_l, chi_r, kind, chi_max, cutoff, True)
+
+
+def check_svd(chi_l, chi_r, kind, chi_max, cutoff, wide):
     rng = np.random.default_rng(chi_l * 1000 + chi_r)
     m, n = 3 * chi_l, 3 * chi_r
     theta = make_theta(rng, m, n, kind)
-    print(f"case: svd {m}x{n} {kind} chi_max={chi_max}", flush=True)
+    print(f"case: svd {m}x{n} {kind} chi_max={chi_max} wide={wide}",
+          flush=True)
     ctx = hmps.Context(1, 2, max(chi_l, chi_r), 1)
     sigma, left, right = ctx.hmps_svd_probe(theta, chi_max, cutoff)
+    assert (ctx.hmps_stats().wide_launches > 0) == wide
     ctx.hmps_destroy()
     u, s, vt = np.linalg.svd(theta, full_matrices=False)
     k_ref = mps.truncation_rank(s, chi_max, cutoff)
