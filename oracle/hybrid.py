@@ -8,7 +8,11 @@ Readings of points the paper leaves open:
 
 * Collapse basis: sample n collapses its environment in S^z when n is even
   and in S^x when n is odd; sample 0 starts from a uniformly random S^z
-  product state (one Philox draw per environment site).
+  product state (one Philox draw per environment site).  With
+  ``z_only`` every collapse is in S^z: the policy that keeps each
+  evolution inside one sector of the total S^z (with the ancillas counted
+  with flipped sign) while the sector still changes from sample to sample
+  (Exploiting Conserved Quantum Numbers subsection).
 * Estimators are plain sample means over the chain (the chain visits
   product states i with probability P_i/Z, where P_i is the squared norm of
   e^{-beta H/2}|i>_E|B>_C; eq. (eq2)).
@@ -45,7 +49,8 @@ def run_sample(lat, lay, sch, M, tau, chi_max, cutoff, env, basis,
 def run_chain(lat: model.Lattice, beta: float, tau: float, chi_max: int,
               cutoff: float, n_samples: int, seed: int, chain: int = 0,
               env0: dict | None = None, basis0: int = 0,
-              record_spectra: bool = False, first_sample: int = 0) -> list:
+              record_spectra: bool = False, first_sample: int = 0,
+              z_only: bool = False) -> list:
     """Samples first_sample .. first_sample + n_samples - 1 of one Markov
     chain (a chain resumes at first_sample from the product state env0 of
     the previous collapse).  Each record holds the initial product state,
@@ -63,7 +68,7 @@ def run_chain(lat: model.Lattice, beta: float, tau: float, chi_max: int,
             st.spectra = []
         psi, meas = run_sample(lat, lay, sch, M, tau, chi_max, cutoff, env,
                                basis, st)
-        cb = n % 2
+        cb = 0 if z_only else n % 2
         flags = {}
         new_env = mps.collapse(psi, lay, cb, seed, chain, n, flags)
         out.append({"sample": n, "env": dict(env), "basis": basis,

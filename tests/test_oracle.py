@@ -384,6 +384,29 @@ def test_collapse_frequencies_follow_probabilities():
     assert chi2 < dof + 4 * math.sqrt(2 * dof) + 10
 
 
+def test_z_only_chain_conserves_the_charge_within_each_sample():
+    # every collapse in S^z: each evolution keeps Q = sum_phys S^z -
+    # sum_anc S^z at the S^z total of its initial environment (the Bell
+    # pairs carry Q = 0), the next sample starts in the sector of the
+    # collapse outcomes, and that sector changes between samples
+    # (Exploiting Conserved Quantum Numbers subsection).  The chain still
+    # samples the thermal state: its mean agrees with ED.
+    lat = model.ladder(3, 1.0, 1.0, W=1)
+    recs = hybrid.run_chain(lat, 1.0, 0.1, 32, 1e-12, 24, seed=4,
+                            z_only=True)
+    charges = []
+    for r in recs:
+        assert r["basis"] == 0 and r["collapse_basis"] == 0
+        q = sum(1 - r["env"][p] for p in r["env"])
+        assert abs(r["qn"] - q) < 1e-10
+        charges.append(q)
+    for r0, r1 in zip(recs, recs[1:]):
+        assert r1["env"] == r0["outcomes"]
+    assert len(set(charges)) > 1
+    mean, err = hybrid.estimate([r["energy"] for r in recs])
+    assert abs(mean - exact.thermal_energy(lat, 1.0)) < 4 * err + 2e-4
+
+
 def test_chain_mean_agrees_with_ed():
     # 2x3 ladder, W=1, beta=1, tau=0.1, chi_max=32, cutoff 1e-12, 20 samples
     lat = model.ladder(3, 1.0, 1.0, W=1)
