@@ -66,6 +66,27 @@ typedef int32_t hmps_status;
  * contraction is a small share of an update; the SVD sets the cost. */
 #define HMPS_PREC_MIXED_BF16X3 2
 
+/* Symmetry of the evolution (Exploiting Conserved Quantum Numbers
+ * subsection).  The gates conserve Q = sum_phys S^z - sum_ancilla S^z, the
+ * Bell pairs carry Q = 0, and an environment collapsed in S^z is a
+ * product state of definite Q, so every state of an evolution lies in one
+ * sector of Q, which changes from sample to sample with the collapse.
+ *   HMPS_SYM_NONE: dense site tensors.
+ *   HMPS_SYM_U1:   every bond index carries the charge of the sites left of
+ *                  it (ancillas counted with flipped sign), and each
+ *                  update's theta' splits into one block per charge of the
+ *                  new bond: every block is decomposed on its own, the
+ *                  singular values of all blocks are truncated together
+ *                  by the rule of hmps_evolve, and the new bond lists the
+ *                  kept vectors block by block in ascending charge.  The
+ *                  site tensors stay dense arrays whose entries outside
+ *                  the blocks are zero.  Collapses and initial states must
+ *                  be in S^z (basis 0); FP64 only.  Chains loaded by
+ *                  hmps_load_bond or replaced by hmps_svd_probe carry no
+ *                  charges and are updated densely. */
+#define HMPS_SYM_NONE 0
+#define HMPS_SYM_U1 1
+
 /* Bits of the `what` mask of hmps_measure. */
 #define HMPS_MEASURE_ENERGY 1u /* energy (needs every bond correlator)   */
 #define HMPS_MEASURE_BONDS 2u  /* <S_i.S_j> of every Hamiltonian bond    */
@@ -93,6 +114,11 @@ typedef struct {
    * must not call back into the library with the same context. */
   void (*progress)(void *user, int64_t done, int64_t total);
   void *progress_user;
+  int32_t symmetry;        /* HMPS_SYM_*                                  */
+  int32_t max_blocks;      /* HMPS_SYM_U1: charge blocks one pass of an
+                              update holds over all chains (an update takes
+                              several passes when it has more); 0 =
+                              max(64, 4 * max_chains)                      */
 } hmps_options;
 
 /* Hamiltonian H = sum_b J_b S_{i_b} . S_{j_b} on n_phys spin-1 sites
@@ -142,19 +168,29 @@ typedef struct {
                                mixed-precision SVD                        */
   int64_t wide_launches;    /* of round_launches, rounds of 32-vector
                                blocks (updates with >= 512 vectors)      */
+  int64_t u1_blocks;        /* HMPS_SYM_U1: charge blocks decomposed     */
 } hmps_stats_t;
 
 /* Bytes of device workspace needed for the given capacities. */
 size_t hmps_workspace_bytes(int32_t max_chains, int32_t max_sites,
                             int32_t chi_cap, int32_t max_bonds);
 
+/* The same for a context created with `symmetry` and `max_blocks` (the
+ * hmps_options fields; HMPS_SYM_NONE gives hmps_workspace_bytes).  Every
+ * charge block of an update is a two-site segment of up to 3 chi_cap x
+ * 3 chi_cap entries with its own SVD buffers. */
+size_t hmps_workspace_bytes_sym(int32_t max_chains, int32_t max_sites,
+                                int32_t chi_cap, int32_t max_bonds,
+                                int32_t symmetry, int32_t max_blocks);
+
 /* Create a context on opt->device using the caller's workspace (device
- * memory aligned to 256 bytes, at least hmps_workspace_bytes(...) long,
+ * memory aligned to 256 bytes, at least hmps_workspace_bytes_sym(...) long,
  * owned by the caller and not freed by the library).  E_INVALID for bad
  * capacities (max_chains outside [1, 65535]: chains are a grid dimension
  * of the launches; max_sites < 1; chi_cap outside [3, 640]; max_bonds <
- * 0; an unknown precision) or a misaligned workspace; E_NOMEM for a NULL
- * or too small workspace; E_DEVICE if opt->device is not usable. */
+ * 0; an unknown precision or symmetry; HMPS_SYM_U1 with mixed precision
+ * or max_blocks outside [0, 65535]) or a misaligned workspace; E_NOMEM for
+ * a NULL or too small workspace; E_DEVICE if opt->device is not usable. */
 hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt);
 
 /* Step 1 of the Markov chain (Hybrid METTS-Ancilla subsection; Bell pair
@@ -164,7 +200,8 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt);
  * with Philox4x64-10 (key = (seed, 0), counter = (chain, 0, MPS position,
  * 0), label = floor(3 u), u = top 53 bits / 2^53).  Resets the sample
  * counter to 0 and every log-weight to 0.  E_INVALID for a malformed
- * lattice, a label > 2, or capacities exceeded.  Same as
+ * lattice, a label > 2, capacities exceeded, or basis 1 on a HMPS_SYM_U1
+ * context.  Same as
  * hmps_init_cluster_env_at with chain_offset = 0 and sample = 0. */
 hmps_status hmps_init_cluster_env(hmps_ctx *ctx, const hmps_lattice *lat,
                                   int32_t n_chains, uint64_t seed,
@@ -196,7 +233,9 @@ hmps_status hmps_init_cluster_env_at(hmps_ctx *ctx, const hmps_lattice *lat,
  * squared norm is added to the chain's log-weight.  On return the
  * orthogonality centre is site 0.  E_INVALID: chi_max < 1 or > chi_cap,
  * cutoff < 0, tau <= 0 with beta > 0.  E_NUMERIC: the Jacobi SVD did not
- * converge in max_sweeps or produced a non-finite value. */
+ * converge in max_sweeps or produced a non-finite value.  E_NOMEM (U(1)):
+ * an update of one chain has more charge blocks than max_blocks; the
+ * chains keep the updates applied before it. */
 hmps_status hmps_evolve(hmps_ctx *ctx, double beta, double tau,
                         int32_t chi_max, double cutoff);
 
@@ -268,12 +307,25 @@ hmps_status hmps_bond_moments(hmps_ctx *ctx, int64_t *n_samples,
  * probability, u from Philox4x64-10 with counter (global chain id, sample,
  * MPS position, 1) (see hmps_init_cluster_env_at).  Then re-initialise every chain to the new product state
  * (in `basis`) with fresh Bell pairs and advance the sample counter.
- * env_out (host, may be NULL): n_chains x n_env labels.  Synchronises. */
+ * env_out (host, may be NULL): n_chains x n_env labels.  E_INVALID for
+ * basis 1 on a HMPS_SYM_U1 context (an S^x outcome has no definite
+ * charge).  Synchronises. */
 hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
                                    uint8_t *env_out);
 
 /* Counters since init. */
 hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out);
+
+/* Charges of bond `bond` (0..n_sites) of chain `chain` on a HMPS_SYM_U1
+ * context (Exploiting Conserved Quantum Numbers subsection): q[i], i <
+ * chi[bond], is the Q of the sites left of the bond for bond index i;
+ * a site tensor T[s][a][b] at a position holding a physical site is
+ * nonzero only where q_right[b] = q_left[a] + S^z(s), and -S^z(s) for an
+ * ancilla.  Host array of chi[bond] int32.  E_STATE unless the chains
+ * come from hmps_init_cluster_env on a HMPS_SYM_U1 context; E_INVALID for
+ * an index out of range. */
+hmps_status hmps_bond_charges(hmps_ctx *ctx, int32_t chain, int32_t bond,
+                              int32_t *q);
 
 /* Bond dimensions chi[c][b], b = 0..n_sites, of every chain (host array
  * of n_chains * (n_sites + 1) int32), after hmps_init_cluster_env or

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhmps.so")
 SOURCES = ["update.hip", "jacobi.hip", "qr.hip", "rr.hip", "observe.hip",
-           "noalloc.hip", "hmps.cpp"]
+           "u1.hip", "noalloc.hip", "hmps.cpp"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -10,11 +10,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -276,6 +278,25 @@ struct hmps_ctx {
   // about 14.
   int precond = 2;
   bool skip_theta = false;  // hmps_svd_probe: theta' is placed by the host
+  bool zero_ok = false;     // an all-zero theta' keeps nothing (U(1) blocks)
+  // U(1) symmetry (HMPS_SYM_U1): the charge blocks of an update are the
+  // chains of `sub` (two sites each, theta' placed by k_u1_gather)
+  int symmetry = HMPS_SYM_NONE;
+  int max_blocks = 0;
+  bool u1_live = false;  // the chains carry charges (init or collapse)
+  hmps_ctx *sub = nullptr;
+  // +1 where an MPS position holds a physical site, -1 an ancilla (swap
+  // updates move them; every Trotter step restores the layout)
+  std::vector<int> pos_sign;
+  // charges of every bond of every chain as runs (charge, count) in index
+  // order, one run per charge: [B][len+1]
+  std::vector<std::vector<std::pair<int, int>>> h_qg;
+  int32_t *d_u1_blk = nullptr, *d_u1_ch = nullptr, *d_u1_kv = nullptr,
+          *d_u1_jmap = nullptr;
+  double *d_u1_scale = nullptr;
+  int32_t *h_u1_kv = nullptr;  // pinned [max_blocks]
+  size_t u1_sub_off = 0, u1_sub_bytes = 0;
+  int64_t u1_blocks = 0;
   // device buffers (carved from the workspace)
   size_t site_cap = 0, chi2 = 0, th_stride = 0;
   int n_cap = 0, slots = 0, qr_panels = 0;
@@ -318,7 +339,7 @@ struct Carver {
 
 // Lays out every device buffer; with base == nullptr it only measures.
 size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
-             int chi_cap, int max_bonds) {
+             int chi_cap, int max_bonds, int max_blocks = 0) {
   Carver cv{base};
   const size_t B = max_chains;
   const size_t chi2 = (size_t)chi_cap * chi_cap;
@@ -388,6 +409,18 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_env_index = cv.take<int32_t>(max_sites);
   t->d_labels = cv.take<uint8_t>(B * max_sites);
   t->d_outcomes = cv.take<uint8_t>(B * max_sites);
+  if (max_blocks > 0) {
+    // U(1): block and chain tables of a pass, the merge's results, and the
+    // workspace of the block batch (two-site chains of up to chi_cap)
+    t->d_u1_blk = cv.take<int32_t>((size_t)max_blocks * U1_BLK);
+    t->d_u1_ch = cv.take<int32_t>(B * U1_CH);
+    t->d_u1_kv = cv.take<int32_t>(max_blocks);
+    t->d_u1_scale = cv.take<double>(max_blocks);
+    t->d_u1_jmap = cv.take<int32_t>(B * n_cap);
+    t->u1_sub_bytes = carve(nullptr, nullptr, max_blocks, 2, chi_cap, 0);
+    t->u1_sub_off = cv.off;
+    cv.off += align_up(t->u1_sub_bytes);
+  }
   return cv.off;
 }
 
@@ -492,9 +525,45 @@ hmps_status check_usable(hmps_ctx *ctx, bool need_init) {
   return HMPS_OK;
 }
 
+// Parameters of one two-site update on (k, k+1).
+UpdParams update_params(const hmps_ctx *ctx, int k, int op, bool right,
+                        int chi_max, double cutoff, int mixed, int wide) {
+  const bool is_move = (op == OP_IDENT);
+  UpdParams u;
+  u.k = k;
+  const int ncoup = (int)ctx->plan.couplings.size();
+  u.gate = ctx->d_gates +
+           81 * (op >= 0 ? op : (op == OP_SWAP ? ncoup : ncoup + 1));
+  u.is_gate = op >= 0;
+  u.right = right ? 1 : 0;
+  u.chi_max = is_move ? ctx->opt.chi_cap : chi_max;
+  u.cutoff = is_move ? 0.0 : cutoff;
+  u.tol = ctx->opt.jacobi_tol;
+  u.max_sweeps = ctx->opt.max_sweeps;
+  u.mixed = mixed;
+  u.tol32 = 8.0 * std::sqrt(3.0 * ctx->opt.chi_cap) * 1.1920929e-7;
+  // vectors below 1e-12 sigma_0 are left unrotated in FP32 and out of the
+  // Ritz basis (the numerically null part of a rank-deficient theta');
+  // every other pair is rotated to the FP32 tolerance relative to its own
+  // norms, so the basis vectors are orthogonal to about tol32
+  u.skip32 = 1e-24;
+  u.precond = ctx->precond;
+  u.small_max = ctx->small_max;
+  u.inner_sweeps = ctx->inner_sweeps;
+  u.skip = ctx->skip;
+  u.cross_inner = ctx->cross_inner;
+  u.wide = wide;
+  u.zero_ok = ctx->zero_ok ? 1 : 0;
+  return u;
+}
+
+hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
+                         int chi_max, double cutoff);
+
 // One two-site update on (k, k+1) for every chain.
 hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
                       double cutoff) {
+  if (ctx->u1_live) return do_update_u1(ctx, k, op, right, chi_max, cutoff);
   const int L = ctx->plan.len;
   int max_chiL = 1, max_chiR = 1;
   // each chain's SVD runs in LDS when its theta' has at most small_max
@@ -556,30 +625,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       if (path == PATH_QR2) max_qr2_n = std::max(max_qr2_n, nvec);
     }
   }
-  UpdParams u;
-  u.k = k;
-  const int ncoup = (int)ctx->plan.couplings.size();
-  u.gate = ctx->d_gates +
-           81 * (op >= 0 ? op : (op == OP_SWAP ? ncoup : ncoup + 1));
-  u.is_gate = op >= 0;
-  u.right = right ? 1 : 0;
-  u.chi_max = is_move ? ctx->opt.chi_cap : chi_max;
-  u.cutoff = is_move ? 0.0 : cutoff;
-  u.tol = ctx->opt.jacobi_tol;
-  u.max_sweeps = ctx->opt.max_sweeps;
-  u.mixed = mixed;
-  u.tol32 = 8.0 * std::sqrt(3.0 * ctx->opt.chi_cap) * 1.1920929e-7;
-  // vectors below 1e-12 sigma_0 are left unrotated in FP32 and out of the
-  // Ritz basis (the numerically null part of a rank-deficient theta');
-  // every other pair is rotated to the FP32 tolerance relative to its own
-  // norms, so the basis vectors are orthogonal to about tol32
-  u.skip32 = 1e-24;
-  u.precond = ctx->precond;
-  u.small_max = ctx->small_max;
-  u.inner_sweeps = ctx->inner_sweeps;
-  u.skip = ctx->skip;
-  u.cross_inner = ctx->cross_inner;
-  u.wide = wide;
+  const UpdParams u = update_params(ctx, k, op, right, chi_max, cutoff, mixed, wide);
   Batch b = batch_of(ctx);
   UpdScratch s = scratch_of(ctx);
   hipStream_t st = ctx->stream;
@@ -770,6 +816,256 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   return HMPS_OK;
 }
 
+// Charges of every bond after an initialisation: bond 0 carries 0; a
+// cluster physical site opens its Bell pair (bond index s carries S^z(s) =
+// 1 - s more), its ancilla closes it (-S^z: the pair carries 0), and an
+// environment site in S^z label l adds 1 - l.  labels: [B][n_env].
+void init_host_charges(hmps_ctx *ctx, const uint8_t *labels) {
+  const Plan &P = ctx->plan;
+  const int L = P.len;
+  ctx->pos_sign.assign(L, 1);
+  for (int p = 0; p < L; ++p)
+    if (P.is_ancilla[p]) ctx->pos_sign[p] = -1;
+  ctx->h_qg.assign((size_t)ctx->B * (L + 1), {});
+  for (int c = 0; c < ctx->B; ++c) {
+    auto *g = &ctx->h_qg[(size_t)c * (L + 1)];
+    int q = 0;
+    g[0] = {{0, 1}};
+    for (int p = 0; p < L; ++p) {
+      if (P.is_cluster[p] && !P.is_ancilla[p]) {
+        g[p + 1] = {{q + 1, 1}, {q, 1}, {q - 1, 1}};
+      } else if (P.is_ancilla[p]) {
+        g[p + 1] = {{q, 1}};
+      } else {
+        q += 1 - labels[(size_t)c * P.n_env + P.env_index[p]];
+        g[p + 1] = {{q, 1}};
+      }
+    }
+  }
+}
+
+// One U(1) update on (k, k+1) for every chain (Exploiting Conserved Quantum
+// Numbers subsection): theta' of every chain as in the dense update; then
+// its charge blocks, listed here from the charges of bonds k and k+2, are
+// decomposed as the chains of the block batch (ctx->sub, in passes of at
+// most max_blocks blocks), merged and truncated together per chain, and
+// written back block by block; bond k+1 lists the kept vectors by block in
+// ascending charge.
+hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
+                         int chi_max, double cutoff) {
+  const int L = ctx->plan.len;
+  const bool is_move = (op == OP_IDENT);
+  hmps_ctx *sub = ctx->sub;
+  // the sites at k and k+1 once the update is done (a swap exchanges them)
+  int sk = ctx->pos_sign[k], sk1 = ctx->pos_sign[k + 1];
+  if (op == OP_SWAP) std::swap(sk, sk1);
+  struct Piece {
+    int start = 0, count = 0;
+  };
+  struct Blk {
+    int q = 0;
+    Piece row[3], col[3];
+  };
+  std::vector<std::vector<Blk>> blocks(ctx->B);
+  int max_chiL = 1, max_chiR = 1;
+  double flops = 0.0;
+  int64_t n_blocks = 0;
+  for (int c = 0; c < ctx->B; ++c) {
+    const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
+    max_chiL = std::max(max_chiL, row[k]);
+    max_chiR = std::max(max_chiR, row[k + 2]);
+    flops += 18.0 * row[k] * row[k + 1] * row[k + 2] +
+             162.0 * row[k] * row[k + 2];
+    // rows (s1, a): charge q_k(a) + sk S^z(s1); columns (s2, c): q_{k+2}(c)
+    // - sk1 S^z(s2); S^z(s) = 1 - s
+    std::map<int, std::array<Piece, 3>> rows, cols;
+    // each bond's runs: one per charge, covering its dimension exactly
+    bool ok = true;
+    int start = 0;
+    for (const auto &g : ctx->h_qg[(size_t)c * (L + 1) + k]) {
+      for (int s1 = 0; s1 < 3; ++s1) {
+        Piece &pc = rows[g.first + sk * (1 - s1)][s1];
+        ok = ok && pc.count == 0 && g.second > 0;
+        pc = {start, g.second};
+      }
+      start += g.second;
+    }
+    ok = ok && start == row[k];
+    start = 0;
+    for (const auto &g : ctx->h_qg[(size_t)c * (L + 1) + k + 2]) {
+      for (int s2 = 0; s2 < 3; ++s2) {
+        Piece &pc = cols[g.first - sk1 * (1 - s2)][s2];
+        ok = ok && pc.count == 0 && g.second > 0;
+        pc = {start, g.second};
+      }
+      start += g.second;
+    }
+    ok = ok && start == row[k + 2];
+    if (!ok)
+      return fail(ctx, HMPS_E_NUMERIC,
+                  "charges of bonds " + std::to_string(k) + " and " +
+                      std::to_string(k + 2) + " of chain " +
+                      std::to_string(c) + " do not match their dimensions");
+    for (const auto &r : rows) {
+      const auto it = cols.find(r.first);
+      if (it == cols.end()) continue;
+      Blk bk;
+      bk.q = r.first;
+      int mq = 0, nq = 0;
+      for (int x = 0; x < 3; ++x) {
+        bk.row[x] = r.second[x];
+        bk.col[x] = it->second[x];
+        mq += bk.row[x].count;
+        nq += bk.col[x].count;
+      }
+      const double lq = std::max(mq, nq), nn = std::min(mq, nq);
+      flops += 14.0 * lq * nn * nn + 8.0 * nn * nn * nn;
+      blocks[c].push_back(bk);
+    }
+    n_blocks += (int64_t)blocks[c].size();
+  }
+  for (int c = 0; c < ctx->B; ++c)
+    if ((int)blocks[c].size() > ctx->max_blocks)
+      return fail(ctx, HMPS_E_NOMEM,
+                  "chain " + std::to_string(c) + " has " +
+                      std::to_string(blocks[c].size()) +
+                      " charge blocks, more than max_blocks");
+  const UpdParams u =
+      update_params(ctx, k, op, right, chi_max, cutoff, 0, 0);
+  Batch b = batch_of(ctx);
+  UpdScratch s = scratch_of(ctx);
+  hipStream_t st = ctx->stream;
+  launch_theta(b, s, u, max_chiL, max_chiR, st);
+  if (u.is_gate) launch_theta_norm(b, s, u, st);
+  LAUNCHCHK(ctx);
+  const int kmax = std::max(
+      1, std::min(u.chi_max, 3 * std::max(max_chiL, max_chiR)));
+  std::vector<std::vector<std::pair<int, int>>> newg(ctx->B);
+  for (int c0 = 0; c0 < ctx->B;) {
+    // the chains c0 .. c1-1 whose blocks fit one pass
+    int nb = 0, c1 = c0;
+    while (c1 < ctx->B && nb + (int)blocks[c1].size() <= ctx->max_blocks)
+      nb += (int)blocks[c1++].size();
+    std::vector<int32_t> tb((size_t)std::max(nb, 1) * U1_BLK, 0),
+        tc((size_t)(c1 - c0) * U1_CH, 0);
+    sub->h_chi.assign((size_t)std::max(nb, 1) * 3, 1);
+    int v = 0;
+    for (int c = c0; c < c1; ++c) {
+      int32_t *t = &tc[(size_t)(c - c0) * U1_CH];
+      t[0] = c;
+      t[1] = v;
+      t[2] = (int32_t)blocks[c].size();
+      for (const Blk &bk : blocks[c]) {
+        int32_t *e = &tb[(size_t)v * U1_BLK];
+        int cl = 1, cr = 1;
+        for (int x = 0; x < 3; ++x) {
+          cl = std::max(cl, bk.row[x].count);
+          cr = std::max(cr, bk.col[x].count);
+          e[4 + x] = bk.row[x].start;
+          e[7 + x] = bk.row[x].count;
+          e[10 + x] = bk.col[x].start;
+          e[13 + x] = bk.col[x].count;
+        }
+        e[0] = c - c0;
+        e[1] = bk.q;
+        e[2] = cl;
+        e[3] = cr;
+        sub->h_chi[(size_t)v * 3] = cl;
+        sub->h_chi[(size_t)v * 3 + 2] = cr;
+        ++v;
+      }
+    }
+    if (nb > 0) {
+      sub->B = nb;
+      HIPCHK(hipMemcpyAsync(ctx->d_u1_blk, tb.data(),
+                            sizeof(int32_t) * (size_t)nb * U1_BLK,
+                            hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(sub->d_chi, sub->h_chi.data(),
+                            sizeof(int32_t) * 3 * (size_t)nb,
+                            hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemsetAsync(sub->d_err, 0, sizeof(int32_t) * nb, st));
+      HIPCHK(hipMemsetAsync(sub->d_disc, 0, sizeof(double) * nb, st));
+      HIPCHK(hipMemsetAsync(sub->d_logw, 0, sizeof(double) * nb, st));
+    }
+    HIPCHK(hipMemcpyAsync(ctx->d_u1_ch, tc.data(),
+                          sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice,
+                          st));
+    U1Args a;
+    a.blk = ctx->d_u1_blk;
+    a.chains = ctx->d_u1_ch;
+    a.n_chains = c1 - c0;
+    a.n_blocks = nb;
+    a.k = k;
+    a.right = right ? 1 : 0;
+    a.bsites = sub->d_sites;
+    a.bsite_cap = sub->site_cap;
+    a.bTH = sub->d_TH;
+    a.bX = sub->d_X;
+    a.bstride = sub->th_stride;
+    a.bsig = sub->d_sig;
+    a.bknew = sub->d_knew;
+    a.bn_cap = sub->n_cap;
+    a.kv = ctx->d_u1_kv;
+    a.scale = ctx->d_u1_scale;
+    a.jmap = ctx->d_u1_jmap;
+    a.jstride = ctx->n_cap;
+    launch_u1_gather(b, s, a, st);
+    LAUNCHCHK(ctx);
+    if (nb > 0) {
+      // every block keeps all it resolves; the merge truncates
+      const hmps_status e =
+          do_update(sub, 0, OP_SWAP, right, sub->opt.chi_cap, 0.0);
+      if (e) return fail(ctx, e, "charge block SVD: " + sub->err);
+    }
+    launch_u1_merge(b, s, u, a, st);
+    launch_u1_scatter(b, a, max_chiL, max_chiR, kmax, st);
+    HIPCHK(hipGetLastError());
+    if (nb > 0)
+      HIPCHK(hipMemcpyAsync(ctx->h_u1_kv, ctx->d_u1_kv, sizeof(int32_t) * nb,
+                            hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    v = 0;
+    for (int c = c0; c < c1; ++c)
+      for (const Blk &bk : blocks[c]) {
+        const int kv = ctx->h_u1_kv[v++];
+        if (kv > 0) newg[c].push_back({bk.q, kv});
+      }
+    c0 = c1;
+  }
+  HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_knew, sizeof(int32_t) * ctx->B,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(ctx->h_stage + ctx->opt.max_chains, ctx->d_err,
+                        sizeof(int32_t) * ctx->B, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int c = 0; c < ctx->B; ++c) {
+    const int code = ctx->h_stage[ctx->opt.max_chains + c];
+    const int kn = ctx->h_stage[c];
+    int sum = 0;
+    for (const auto &g : newg[c]) sum += g.second;
+    if (code || sum != kn)
+      return fail(ctx, HMPS_E_NUMERIC,
+                  "U(1) update on sites (" + std::to_string(k) + "," +
+                      std::to_string(k + 1) + ") failed in chain " +
+                      std::to_string(c) + ": " +
+                      (code == 3 ? "more charge blocks or singular values "
+                                   "than the merge holds"
+                       : code    ? "zero or non-finite singular values"
+                                 : "block counts do not add up"));
+    ctx->h_chi[(size_t)c * (L + 1) + k + 1] = kn;
+    ctx->h_qg[(size_t)c * (L + 1) + k + 1] = newg[c];
+    ctx->stats.max_chi = std::max(ctx->stats.max_chi, kn);
+  }
+  ctx->pos_sign[k] = sk;
+  ctx->pos_sign[k + 1] = sk1;
+  ctx->have_spectrum = true;
+  ctx->stats.algo_flops += flops;
+  ctx->stats.updates += ctx->B;
+  if (op >= 0) ctx->stats.gate_updates += ctx->B;
+  if (is_move) ctx->stats.move_updates += ctx->B;
+  ctx->u1_blocks += n_blocks;
+  return HMPS_OK;
+}
+
 hmps_status move_center(hmps_ctx *ctx, int target) {
   while (ctx->center < target) {
     hmps_status st = do_update(ctx, ctx->center, OP_IDENT, true, 0, 0.0);
@@ -798,6 +1094,31 @@ size_t hmps_workspace_bytes(int32_t max_chains, int32_t max_sites,
   return carve(nullptr, nullptr, max_chains, max_sites, chi_cap, max_bonds);
 }
 
+}  // extern "C"
+
+namespace {
+// charge blocks the block batch holds: max_blocks, or 4 per chain and at
+// least 64 (the blocks of one chain's update must fit one pass)
+int u1_blocks_of(int32_t symmetry, int32_t max_chains, int32_t max_blocks) {
+  if (symmetry != HMPS_SYM_U1) return 0;
+  return max_blocks > 0 ? max_blocks
+                        : std::min(65535, std::max(64, 4 * max_chains));
+}
+}  // namespace
+
+extern "C" {
+
+size_t hmps_workspace_bytes_sym(int32_t max_chains, int32_t max_sites,
+                                int32_t chi_cap, int32_t max_bonds,
+                                int32_t symmetry, int32_t max_blocks) {
+  if (max_chains < 1 || max_sites < 1 || chi_cap < 1 || max_bonds < 0 ||
+      (symmetry != HMPS_SYM_NONE && symmetry != HMPS_SYM_U1) ||
+      max_blocks < 0 || max_blocks > 65535)
+    return 0;
+  return carve(nullptr, nullptr, max_chains, max_sites, chi_cap, max_bonds,
+               u1_blocks_of(symmetry, max_chains, max_blocks));
+}
+
 hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
   if (!out || !opt) return HMPS_E_INVALID;
   *out = nullptr;
@@ -810,8 +1131,15 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
       (opt->precision != HMPS_PREC_FP64 &&
        opt->precision != HMPS_PREC_MIXED_FP32))
     return HMPS_E_INVALID;  // HMPS_PREC_MIXED_BF16X3 included: not built
-  const size_t need = hmps_workspace_bytes(opt->max_chains, opt->max_sites,
-                                           opt->chi_cap, opt->max_bonds);
+  if ((opt->symmetry != HMPS_SYM_NONE && opt->symmetry != HMPS_SYM_U1) ||
+      (opt->symmetry == HMPS_SYM_U1 && opt->precision != HMPS_PREC_FP64) ||
+      opt->max_blocks < 0 || opt->max_blocks > 65535)
+    return HMPS_E_INVALID;
+  const int max_blocks =
+      u1_blocks_of(opt->symmetry, opt->max_chains, opt->max_blocks);
+  const size_t need = hmps_workspace_bytes_sym(
+      opt->max_chains, opt->max_sites, opt->chi_cap, opt->max_bonds,
+      opt->symmetry, opt->max_blocks);
   if (!opt->workspace || opt->workspace_bytes < need) return HMPS_E_NOMEM;
   if (((uintptr_t)opt->workspace) % ALIGN) return HMPS_E_INVALID;
   hmps_ctx *ctx = new hmps_ctx();
@@ -855,7 +1183,44 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
     return HMPS_E_DEVICE;
   }
   carve(ctx, reinterpret_cast<char *>(opt->workspace), opt->max_chains,
-        opt->max_sites, opt->chi_cap, opt->max_bonds);
+        opt->max_sites, opt->chi_cap, opt->max_bonds, max_blocks);
+  if (max_blocks > 0) {
+    // the block batch: a context of max_blocks two-site chains on the
+    // tail of the workspace, with the same SVD settings
+    ctx->symmetry = HMPS_SYM_U1;
+    ctx->max_blocks = max_blocks;
+    hmps_options so{};
+    so.device = opt->device;
+    so.stream = opt->stream;
+    so.workspace = reinterpret_cast<char *>(opt->workspace) + ctx->u1_sub_off;
+    so.workspace_bytes = ctx->u1_sub_bytes;
+    so.max_chains = max_blocks;
+    so.max_sites = 2;
+    so.chi_cap = opt->chi_cap;
+    so.max_bonds = 0;
+    so.precision = HMPS_PREC_FP64;
+    so.max_sweeps = ctx->opt.max_sweeps;
+    so.jacobi_tol = ctx->opt.jacobi_tol;
+    hmps_status e2 = hmps_create(&ctx->sub, &so);
+    if (e2 == HMPS_OK &&
+        hipHostMalloc((void **)&ctx->h_u1_kv, sizeof(int32_t) * max_blocks) !=
+            hipSuccess)
+      e2 = HMPS_E_DEVICE;
+    if (e2 == HMPS_OK &&
+        (hipMemsetAsync(ctx->sub->d_sweeps, 0, sizeof(int32_t) * max_blocks,
+                        ctx->stream) != hipSuccess ||
+         hipStreamSynchronize(ctx->stream) != hipSuccess))
+      e2 = HMPS_E_DEVICE;
+    if (e2 != HMPS_OK) {
+      hmps_destroy(ctx);
+      return e2;
+    }
+    Plan P;
+    P.len = 2;
+    ctx->sub->plan = P;
+    ctx->sub->skip_theta = true;
+    ctx->sub->zero_ok = true;
+  }
   *out = ctx;
   return HMPS_OK;
 }
@@ -865,6 +1230,8 @@ void hmps_destroy(hmps_ctx *ctx) {
   DeviceGuard guard(ctx->opt.device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
+  if (ctx->h_u1_kv) (void)hipHostFree(ctx->h_u1_kv);
+  if (ctx->sub) hmps_destroy(ctx->sub);
   for (hipEvent_t ev : ctx->sweep_ev)
     if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : ctx->svd_ev)
@@ -905,6 +1272,9 @@ hmps_status hmps_init_cluster_env_at(hmps_ctx *ctx, const hmps_lattice *lat,
     return fail(ctx, HMPS_E_INVALID, "n_bonds exceeds max_bonds");
   if (basis != 0 && basis != 1)
     return fail(ctx, HMPS_E_INVALID, "basis must be 0 or 1");
+  if (basis != 0 && ctx->symmetry == HMPS_SYM_U1)
+    return fail(ctx, HMPS_E_INVALID,
+                "a U(1) context takes environment states in S^z (basis 0)");
   std::vector<uint8_t> labels((size_t)n_chains * std::max(P.n_env, 1), 0);
   if (env_state) {
     for (size_t i = 0; i < (size_t)n_chains * P.n_env; ++i) {
@@ -971,6 +1341,15 @@ hmps_status hmps_init_cluster_env_at(hmps_ctx *ctx, const hmps_lattice *lat,
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
   init_host_chi(ctx);
+  ctx->u1_live = ctx->symmetry == HMPS_SYM_U1;
+  ctx->u1_blocks = 0;
+  if (ctx->u1_live) {
+    init_host_charges(ctx, labels.data());
+    std::memset(&ctx->sub->stats, 0, sizeof(ctx->sub->stats));
+    HIPCHK(hipMemsetAsync(ctx->sub->d_sweeps, 0,
+                          sizeof(int32_t) * ctx->max_blocks, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
   ctx->stats.n_chains = n_chains;
   ctx->stats.n_sites = P.len;
   ctx->stats.n_env = P.n_env;
@@ -1236,6 +1615,10 @@ hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
   DeviceGuard guard(ctx->opt.device);
   if (basis != 0 && basis != 1)
     return fail(ctx, HMPS_E_INVALID, "basis must be 0 or 1");
+  if (basis != 0 && ctx->u1_live)
+    return fail(ctx, HMPS_E_INVALID,
+                "a U(1) context collapses in S^z (basis 0): an S^x outcome "
+                "has no definite charge");
   if (ctx->center != 0) {
     st = move_center(ctx, 0);
     if (st) return st;
@@ -1269,8 +1652,17 @@ hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
   ia.basis = basis;
   launch_init(b, ia, ctx->d_logw, s);
   HIPCHK(hipGetLastError());
+  std::vector<uint8_t> outcomes;
+  if (ctx->u1_live) {
+    outcomes.resize((size_t)ctx->B * std::max(P.n_env, 1));
+    if (P.n_env > 0)
+      HIPCHK(hipMemcpyAsync(outcomes.data(), ctx->d_outcomes,
+                            (size_t)ctx->B * P.n_env, hipMemcpyDeviceToHost,
+                            s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   init_host_chi(ctx);
+  if (ctx->u1_live) init_host_charges(ctx, outcomes.data());
   ctx->center = 0;
   ctx->evo_pos = 0;
   ctx->sample += 1;
@@ -1284,6 +1676,22 @@ hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out) {
   hmps_stats_t s = ctx->stats;
   s.center = ctx->center;
   s.evolve_pos = ctx->evo_pos;
+  s.u1_blocks = ctx->u1_blocks;
+  if (ctx->sub && !ctx->poisoned) {
+    // the SVD work of the charge blocks
+    const hmps_stats_t &b = ctx->sub->stats;
+    s.jacobi_sweeps += b.jacobi_sweeps;
+    s.svd_flops += b.svd_flops;
+    s.svd_seconds += b.svd_seconds;
+    s.round_launches += b.round_launches;
+    s.svd_bytes += b.svd_bytes;
+    s.wide_launches += b.wide_launches;
+    std::vector<int32_t> sw(ctx->max_blocks);
+    if (hipMemcpy(sw.data(), ctx->sub->d_sweeps,
+                  sizeof(int32_t) * ctx->max_blocks,
+                  hipMemcpyDeviceToHost) == hipSuccess)
+      for (int32_t v : sw) s.jacobi_sweeps += v;
+  }
   if ((ctx->ready || ctx->bond_loaded) && !ctx->poisoned) {
     std::vector<double> disc(ctx->B);
     std::vector<int32_t> sw(ctx->B);
@@ -1449,6 +1857,7 @@ hmps_status hmps_svd_probe(hmps_ctx *ctx, int32_t chi_l, int32_t chi_r,
   ctx->B = 1;
   ctx->ready = false;
   ctx->bond_loaded = false;
+  ctx->u1_live = false;
   ctx->center = 0;
   ctx->h_chi = {chi_l, 1, chi_r};
   hipStream_t s = ctx->stream;
@@ -1521,6 +1930,7 @@ hmps_status hmps_load_bond(hmps_ctx *ctx, int32_t n_chains, int32_t chi_l,
   ctx->plan = P;
   ctx->B = n_chains;
   ctx->ready = false;
+  ctx->u1_live = false;
   ctx->bond_loaded = false;
   ctx->center = 0;
   std::memset(&ctx->stats, 0, sizeof(ctx->stats));
@@ -1616,6 +2026,23 @@ hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi) {
                         sizeof(int32_t) * ctx->B * (ctx->plan.len + 1),
                         hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HMPS_OK;
+}
+
+hmps_status hmps_bond_charges(hmps_ctx *ctx, int32_t chain, int32_t bond,
+                              int32_t *q) {
+  hmps_status st = check_usable(ctx, false);
+  if (st) return st;
+  if (!ctx->u1_live)
+    return fail(ctx, HMPS_E_STATE,
+                "no charges: the chains do not come from "
+                "hmps_init_cluster_env on a U(1) context");
+  const int L = ctx->plan.len;
+  if (!q || chain < 0 || chain >= ctx->B || bond < 0 || bond > L)
+    return fail(ctx, HMPS_E_INVALID, "chain or bond out of range");
+  int i = 0;
+  for (const auto &g : ctx->h_qg[(size_t)chain * (L + 1) + bond])
+    for (int t = 0; t < g.second; ++t) q[i++] = g.first;
   return HMPS_OK;
 }
 

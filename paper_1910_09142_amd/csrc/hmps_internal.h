@@ -195,6 +195,8 @@ struct UpdParams {
   int precond;        // QR preconditioning of the blocked path: 0 none,
                       // 1 one QR, 2 two (FP64)
   size_t small_max;   // largest L * N of the in-LDS SVD path
+  int zero_ok;        // a zero theta' keeps no vector instead of failing
+                      // (the charge blocks of a U(1) update)
 };
 
 // ---- launchers (update.hip, jacobi.hip, observe.hip) -----------------------------------------
@@ -247,6 +249,50 @@ void launch_rr_to32(const Batch &b, const UpdScratch &s, const UpdParams &u,
                     hipStream_t st);
 void launch_rr_stage2(const Batch &b, const UpdScratch &s, const UpdParams &u,
                       int max_N, int max_L, hipStream_t st);
+
+// U(1) updates (u1.hip).  Each charge block of an update is a chain of
+// a second batch (two sites, the block's theta' placed in its vector
+// layout).  Block table, U1_BLK ints per block:
+//   [0] index of the block's chain in the chain list of the pass,
+//   [1] charge, [2] chi_l', [3] chi_r' (block theta' is 3 chi_l' x 3 chi_r',
+//   rows (s1, a'), columns (s2, c'), zero outside the pieces below),
+//   [4 + s] first index a of the left bond whose row (s, a) falls in the
+//   block, [7 + s] their count, [10 + s], [13 + s] the same for the
+//   columns (s, c) and the right bond.
+// Chain list, U1_CH ints per chain: [0] chain, [1] first block, [2] blocks.
+constexpr int U1_BLK = 16;
+constexpr int U1_CH = 4;
+struct U1Args {
+  const int32_t *blk;   // [blocks][U1_BLK]
+  const int32_t *chains;  // [chains of the pass][U1_CH]
+  int n_chains;           // chains of the pass
+  int n_blocks;           // blocks of the pass
+  int k;                  // left site of the update
+  int right;              // the singular values go right
+  // the block batch: its sites (two per block), TH and X, sig, knew
+  double *bsites;
+  size_t bsite_cap;
+  double *bTH, *bX;
+  size_t bstride;
+  const double *bsig;
+  const int32_t *bknew;
+  int bn_cap;
+  // merge results
+  int32_t *kv;          // [blocks] vectors of each block kept
+  double *scale;        // [blocks] norm factor of the singular-value side
+  int32_t *jmap;        // [chain][jstride] new bond index -> block << 16 | i
+  int jstride;
+};
+// theta' blocks of every block of the pass (from the chains' TH)
+void launch_u1_gather(const Batch &b, const UpdScratch &s, const U1Args &a,
+                      hipStream_t st);
+// the kept set over all blocks of each chain (rule of k_truncate), the
+// chain's logw, discarded weight, kept spectrum and new bond dimension
+void launch_u1_merge(const Batch &b, const UpdScratch &s, const UpdParams &u,
+                     const U1Args &a, hipStream_t st);
+// the chains' new site tensors k and k+1 from the blocks' factors
+void launch_u1_scatter(const Batch &b, const U1Args &a, int max_chiL,
+                       int max_chiR, int max_k, hipStream_t st);
 
 struct MeasureArgs {
   const int32_t *bond_p, *bond_q;  // [n_bonds] MPS positions, p < q

@@ -182,6 +182,7 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   u.precond = 2;
   u.small_max = 2048;
   u.wide = 0;  // theta' here stays below the wide-block size
+  u.zero_ok = 0;
   hipLaunchKernelGGL(k_na_setup, dim3(64), dim3(256), 0, st, theta, chi_l,
                      chi_r, base);
   if (small_path(L, N, u.small_max)) {

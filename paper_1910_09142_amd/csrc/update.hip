@@ -23,6 +23,7 @@
 // preconditioned path needs.  Elements along a vector keep s-major order.
 #include "device_common.h"
 #include "small_path.h"
+#include "truncate_rule.h"
 
 namespace hmps {
 namespace {
@@ -324,15 +325,9 @@ __global__ void k_mark_small_done(Batch b, UpdScratch s, UpdParams u,
 }
 
 // =====================================================================
-// Truncation: sort the singular values (bitonic, LDS), then keep
-//   k = min(k_eps, chi_max), k_eps the smallest k >= 1 whose discarded
-//   tail sum_{j>=k} sigma_j^2 is <= cutoff * sum_j sigma_j^2 (relative
-//   discarded weight, Results section); values at or below SIGMA_FLOOR
-//   sigma_0 are numerically zero and always dropped.  No cut falls inside
-//   a run of ties (relative gaps <= TIE_TOL): when the target set the cut
-//   the whole run is kept (the discarded weight stays within the target),
-//   unless that passes chi_max; then, as when the cap sets the cut, the
-//   whole run is dropped unless it starts at sigma_0.
+// Truncation: sort the singular values (bitonic, LDS), then keep the
+//   number truncation_rule gives (chi_max, the relative discarded weight,
+//   the numerical floor, no cut inside a run of ties).
 //   ln ||theta'||^2 (k_theta_norm) goes into logw for a gate (the sampling
 //   weight is the product of these norms).
 // =====================================================================
@@ -377,53 +372,24 @@ __global__ void __launch_bounds__(NT)
     }
   }
   if (tid == 0) {
-    double total = 0.0;
-    for (int j = N - 1; j >= 0; --j) total += key[j] * key[j];
     double n2 = 0.0;  // ||theta'||^2 in FP64, summed from theta'
     if (u.is_gate || rr)
       for (int x = 0; x < NORM_SPLIT; ++x)
         n2 += s.norm2[(size_t)c * NORM_SPLIT + x];
-    const double unres = rr ? fmax(n2 - total, 0.0) : 0.0;
-    total += unres;
-    int kfloor = 0;
-    while (kfloor < N && key[kfloor] > SIGMA_FLOOR * key[0]) ++kfloor;
-    const double thr = u.cutoff * total;
-    int k_eps = N;
-    double tail = unres;
-    for (int k = N; k >= 1; --k) {
-      if (k < N) tail += key[k] * key[k];
-      if (tail <= thr)
-        k_eps = k;
-      else
-        break;
+    const TruncResult tr =
+        truncation_rule(key, N, rr, n2, u.chi_max, u.cutoff);
+    int k = tr.k;
+    const double total = tr.total;
+    double kept = tr.kept;
+    if (u.zero_ok && total == 0.0) {
+      k = 0;  // an empty charge block: nothing to keep
+      kept = 1.0;
+    } else if (!(total > 0.0) || !isfinite(total) || !(kept > 0.0)) {
+      s.err[c] = 2;
     }
-    // the largest k allowed: the cap and the numerical floor
-    int kcap = u.chi_max < kfloor ? u.chi_max : kfloor;
-    if (kcap < 1) kcap = 1;
-    int k = k_eps < kcap ? k_eps : kcap;
-    auto tied = [&](int j) {
-      return key[j - 1] - key[j] <= TIE_TOL * key[j - 1];
-    };
-    if (k < N && tied(k)) {
-      // no cut inside a run of ties: keep the whole run when the target
-      // set the cut and the run fits under the cap, else drop it (unless
-      // it starts at sigma_0)
-      int end = k;
-      while (end < N && tied(end)) ++end;
-      if (k_eps <= kcap && end <= kcap) {
-        k = end;
-      } else {
-        int i = k - 1;
-        while (i > 0 && tied(i)) --i;
-        if (i > 0) k = i;
-      }
-    }
-    double kept = 0.0;
-    for (int j = k - 1; j >= 0; --j) kept += key[j] * key[j];
-    if (!(total > 0.0) || !isfinite(total) || !(kept > 0.0)) s.err[c] = 2;
     s.fac[c] = 1.0 / sqrt(kept);
     if (u.is_gate) s.logw[c] += log(n2);
-    s.discarded[c] += (total - kept) / total;
+    if (total > 0.0) s.discarded[c] += (total - kept) / total;
     s.knew[c] = k;
     kk_s = k;
   }

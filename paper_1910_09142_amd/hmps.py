@@ -30,6 +30,8 @@ MEASURE_LOGW = 4
 MEASURE_QN = 8
 MEASURE_ALL = 15
 MEASURE_ACCUMULATE = 16    # add to the device-side moments (not an output)
+SYM_NONE = 0
+SYM_U1 = 1                 # charge-conserving (block-sparse) updates
 
 EXPORTS = [
     "hmps_workspace_bytes", "hmps_create", "hmps_init_cluster_env",
@@ -39,7 +41,7 @@ EXPORTS = [
     "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
     "hmps_apply_gate", "hmps_init_cluster_env_at", "hmps_evolve_updates",
     "hmps_last_spectrum", "hmps_svd_probe_noalloc", "hmps_moments_reset",
-    "hmps_bond_moments",
+    "hmps_bond_moments", "hmps_workspace_bytes_sym", "hmps_bond_charges",
 ]
 
 
@@ -50,7 +52,8 @@ class hmps_options(C.Structure):
                 ("chi_cap", C.c_int32), ("max_bonds", C.c_int32),
                 ("precision", C.c_int32), ("max_sweeps", C.c_int32),
                 ("jacobi_tol", C.c_double),
-                ("progress", C.c_void_p), ("progress_user", C.c_void_p)]
+                ("progress", C.c_void_p), ("progress_user", C.c_void_p),
+                ("symmetry", C.c_int32), ("max_blocks", C.c_int32)]
 
 
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int64, C.c_int64)
@@ -76,7 +79,7 @@ class hmps_stats_t(C.Structure):
                 ("round_launches", C.c_int64), ("svd_bytes", C.c_double),
                 ("center", C.c_int64), ("evolve_pos", C.c_int64),
                 ("jacobi_sweeps_fp32", C.c_int64),
-                ("wide_launches", C.c_int64)]
+                ("wide_launches", C.c_int64), ("u1_blocks", C.c_int64)]
 
 
 _lib = None
@@ -95,6 +98,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     P = C.POINTER
     lib.hmps_workspace_bytes.restype = C.c_size_t
     lib.hmps_workspace_bytes.argtypes = [C.c_int32] * 4
+    lib.hmps_workspace_bytes_sym.restype = C.c_size_t
+    lib.hmps_workspace_bytes_sym.argtypes = [C.c_int32] * 6
+    lib.hmps_bond_charges.argtypes = [C.c_void_p, C.c_int32, C.c_int32,
+                                      P(C.c_int32)]
     lib.hmps_create.argtypes = [P(C.c_void_p), P(hmps_options)]
     lib.hmps_init_cluster_env.argtypes = [C.c_void_p, P(hmps_lattice),
                                           C.c_int32, C.c_uint64,
@@ -150,7 +157,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "hmps_svd_probe", "hmps_measure_pairs",
                  "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
                  "hmps_apply_gate", "hmps_init_cluster_env_at",
-                 "hmps_evolve_updates", "hmps_last_spectrum"):
+                 "hmps_evolve_updates", "hmps_last_spectrum",
+                 "hmps_bond_charges"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -191,6 +199,13 @@ def hmps_workspace_bytes(max_chains, max_sites, chi_cap, max_bonds) -> int:
                                            max_bonds))
 
 
+def hmps_workspace_bytes_sym(max_chains, max_sites, chi_cap, max_bonds,
+                             symmetry, max_blocks=0) -> int:
+    return int(load().hmps_workspace_bytes_sym(max_chains, max_sites, chi_cap,
+                                               max_bonds, symmetry,
+                                               max_blocks))
+
+
 def hmps_gate(J: float, x: float) -> np.ndarray:
     out = np.zeros(81)
     st = load().hmps_gate(J, x, _ptr(out, C.c_double))
@@ -221,15 +236,16 @@ class Context:
 
     def __init__(self, max_chains, max_sites, chi_cap, max_bonds,
                  precision=PREC_FP64, device=0, stream=None, max_sweeps=0,
-                 jacobi_tol=0.0, progress=None):
+                 jacobi_tol=0.0, progress=None, symmetry=SYM_NONE,
+                 max_blocks=0):
         import torch
         lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("hmps needs a ROCm GPU (torch.cuda)")
         self.lib = lib
         self.device = device
-        nbytes = hmps_workspace_bytes(max_chains, max_sites, chi_cap,
-                                      max_bonds)
+        nbytes = hmps_workspace_bytes_sym(max_chains, max_sites, chi_cap,
+                                          max_bonds, symmetry, max_blocks)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8,
                                      device=f"cuda:{device}")
         base = self.workspace.data_ptr()
@@ -245,7 +261,8 @@ class Context:
                                 max_sites, chi_cap, max_bonds, precision,
                                 max_sweeps, jacobi_tol,
                                 C.cast(self._progress, C.c_void_p)
-                                if self._progress else None, None)
+                                if self._progress else None, None,
+                                symmetry, max_blocks)
         h = C.c_void_p()
         st = lib.hmps_create(C.byref(h), C.byref(self.opt))
         if st:
@@ -344,6 +361,15 @@ class Context:
         s = hmps_stats_t()
         self._check(self.lib.hmps_stats(self.h, C.byref(s)), "hmps_stats")
         return s
+
+    def hmps_bond_charges(self, chain, bond):
+        """Charges of the indices of bond `bond` of chain `chain` (U(1))."""
+        n = int(self.hmps_bond_dims()[chain, bond])
+        out = np.zeros(max(n, 1), np.int32)
+        self._check(self.lib.hmps_bond_charges(self.h, chain, bond,
+                                               _ptr(out, C.c_int32)),
+                    "hmps_bond_charges")
+        return out[:n]
 
     def hmps_bond_dims(self):
         out = np.zeros((self.n_chains, self.n_sites + 1), np.int32)
