@@ -75,6 +75,13 @@ def parse(argv=None):
                     help="gate workload: headline measurement only")
     ap.add_argument("--beta", type=float, default=None,
                     help="ladder workloads: override beta")
+    ap.add_argument("--symmetry", default="none", choices=["none", "u1"],
+                    help="ladder workloads: u1 splits every update into its "
+                    "charge blocks (every collapse in S^z)")
+    ap.add_argument("--collapse", default="alternate",
+                    choices=["alternate", "z"],
+                    help="ladder workloads: collapse basis S^z / S^x by "
+                    "sample parity, or S^z always (forced by --symmetry u1)")
     ap.add_argument("--window", default=None, metavar="START:COUNT",
                     help="ladder workloads: time Trotter steps START .. "
                     "START+COUNT-1 of the first evolution only (the steps "
@@ -83,6 +90,8 @@ def parse(argv=None):
     args = ap.parse_args(argv)
     if args.steps < 1 or args.warmup < 0:
         ap.error("--steps >= 1 and --warmup >= 0")
+    if args.symmetry == "u1":
+        args.collapse = "z"
     return args
 
 
@@ -539,13 +548,14 @@ def main_window(args, wl, B, ctx):
                    "W": wl.W, "J_leg": wl.J_leg, "J_rung": wl.J_rung,
                    "beta": wl.beta, "tau": wl.tau, "chi_max": wl.chi_max,
                    "cutoff": wl.cutoff, "trotter_steps": [start, start + count],
-                   "precision": args.precision},
+                   "precision": args.precision, "symmetry": args.symmetry},
         "trotter_updates_per_s": ups / elapsed,
         "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12,
         "chi_histogram_after": hist,
         "chi_mean_after": float(inner.mean()),
         "max_chi": int(inner.max()),
         "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
+        "u1_blocks": s1.u1_blocks - s0.u1_blocks,
         "roofline": svd_roofline(wl.name, s0, s1, False),
     }
     print(json.dumps(out), flush=True)
@@ -572,8 +582,10 @@ def main_ladder(args):
 
     precision = (hmps.PREC_MIXED_FP32 if args.precision == "mixed"
                  else hmps.PREC_FP64)
+    symmetry = hmps.SYM_U1 if args.symmetry == "u1" else hmps.SYM_NONE
     ctx = hmps.Context(B, workloads.mps_length(wl.L, wl.W), wl.chi_max,
-                       len(bonds), precision=precision, progress=progress)
+                       len(bonds), precision=precision, progress=progress,
+                       symmetry=symmetry)
     ctx.hmps_init_cluster_env(lat, B, wl.seed)
     if args.window:
         main_window(args, wl, B, ctx)
@@ -583,7 +595,7 @@ def main_ladder(args):
     def one_sample(idx):
         ctx.hmps_evolve(wl.beta, wl.tau, wl.chi_max, wl.cutoff)
         m = ctx.hmps_measure()
-        ctx.hmps_collapse_resample(idx % 2)
+        ctx.hmps_collapse_resample(0 if args.collapse == "z" else idx % 2)
         return m
 
     sample = 0
@@ -619,15 +631,19 @@ def main_ladder(args):
                    "n_chains": B, "L": wl.L, "W": wl.W,
                    "J_leg": wl.J_leg, "J_rung": wl.J_rung, "beta": wl.beta,
                    "tau": wl.tau, "chi_max": wl.chi_max, "cutoff": wl.cutoff,
-                   "samples_per_step": 1, "precision": args.precision},
+                   "samples_per_step": 1, "precision": args.precision,
+                   "symmetry": args.symmetry, "collapse": args.collapse},
         "samples_per_s": B * args.steps / elapsed,
         "trotter_updates_per_s": trotter_updates / elapsed,
         "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12,
         "max_chi": s1.max_chi,
         "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
+        "u1_blocks": s1.u1_blocks - s0.u1_blocks,
         "energy_mean": sum(energies) / len(energies),
         "roofline": svd_roofline(wl.name, s0, s1,
-                                 args.precision == "fp64" and B == wl.n_chains),
+                                 args.precision == "fp64" and
+                                 B == wl.n_chains and
+                                 args.symmetry == "none"),
     }
     print(json.dumps(out), flush=True)
 
