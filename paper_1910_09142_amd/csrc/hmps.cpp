@@ -338,8 +338,11 @@ struct Carver {
 };
 
 // Lays out every device buffer; with base == nullptr it only measures.
+// svd_only: the block batch of a U(1) context, which never measures (no
+// environments or bond scratch).
 size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
-             int chi_cap, int max_bonds, int max_blocks = 0) {
+             int chi_cap, int max_bonds, int max_blocks = 0,
+             bool svd_only = false) {
   Carver cv{base};
   const size_t B = max_chains;
   const size_t chi2 = (size_t)chi_cap * chi_cap;
@@ -391,9 +394,10 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   t->d_energy = cv.take<double>(B);
   t->d_qn = cv.take<double>(B);
   t->d_gates = cv.take<double>((size_t)(max_bonds + 2) * 81);
-  t->d_envs = cv.take<double>(B * (max_sites + 1) * chi2);
+  const size_t meas = svd_only ? 0 : 1;
+  t->d_envs = cv.take<double>(meas * B * (max_sites + 1) * chi2);
   t->d_wsz = cv.take<double>(B * max_sites);
-  t->d_bscr = cv.take<double>(B * slots * 4 * chi2);
+  t->d_bscr = cv.take<double>(meas * B * slots * 4 * chi2);
   t->d_bond_ss = cv.take<double>(B * std::max(max_bonds, 1));
   // per-chain moments of every bond and of the energy, and their total
   t->d_mom = cv.take<double>(B * (size_t)(max_bonds + 1) * 3);
@@ -417,7 +421,8 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
     t->d_u1_kv = cv.take<int32_t>(max_blocks);
     t->d_u1_scale = cv.take<double>(max_blocks);
     t->d_u1_jmap = cv.take<int32_t>(B * n_cap);
-    t->u1_sub_bytes = carve(nullptr, nullptr, max_blocks, 2, chi_cap, 0);
+    t->u1_sub_bytes =
+        carve(nullptr, nullptr, max_blocks, 2, chi_cap, 0, 0, true);
     t->u1_sub_off = cv.off;
     cv.off += align_up(t->u1_sub_bytes);
   }
@@ -1097,12 +1102,14 @@ size_t hmps_workspace_bytes(int32_t max_chains, int32_t max_sites,
 }  // extern "C"
 
 namespace {
-// charge blocks the block batch holds: max_blocks, or 4 per chain and at
-// least 64 (the blocks of one chain's update must fit one pass)
+// charge blocks the block batch holds: max_blocks, or 16 per chain and at
+// least 64 (the blocks of one chain's update must fit one pass; on the
+// 2x16 ladder at chi 256 an update has up to about 15 per chain, and
+// every pass is a sweep loop of its own)
 int u1_blocks_of(int32_t symmetry, int32_t max_chains, int32_t max_blocks) {
   if (symmetry != HMPS_SYM_U1) return 0;
   return max_blocks > 0 ? max_blocks
-                        : std::min(65535, std::max(64, 4 * max_chains));
+                        : std::min(65535, std::max(64, 16 * max_chains));
 }
 }  // namespace
 
@@ -1119,7 +1126,11 @@ size_t hmps_workspace_bytes_sym(int32_t max_chains, int32_t max_sites,
                u1_blocks_of(symmetry, max_chains, max_blocks));
 }
 
-hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
+}  // extern "C"
+
+namespace {
+hmps_status create_ctx(hmps_ctx **out, const hmps_options *opt,
+                       bool svd_only) {
   if (!out || !opt) return HMPS_E_INVALID;
   *out = nullptr;
   // chi_cap >= 3: a Bell pair carries a bond of dimension 3; chi_cap <= 640:
@@ -1137,9 +1148,9 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
     return HMPS_E_INVALID;
   const int max_blocks =
       u1_blocks_of(opt->symmetry, opt->max_chains, opt->max_blocks);
-  const size_t need = hmps_workspace_bytes_sym(
-      opt->max_chains, opt->max_sites, opt->chi_cap, opt->max_bonds,
-      opt->symmetry, opt->max_blocks);
+  const size_t need =
+      carve(nullptr, nullptr, opt->max_chains, opt->max_sites, opt->chi_cap,
+            opt->max_bonds, max_blocks, svd_only);
   if (!opt->workspace || opt->workspace_bytes < need) return HMPS_E_NOMEM;
   if (((uintptr_t)opt->workspace) % ALIGN) return HMPS_E_INVALID;
   hmps_ctx *ctx = new hmps_ctx();
@@ -1183,7 +1194,7 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
     return HMPS_E_DEVICE;
   }
   carve(ctx, reinterpret_cast<char *>(opt->workspace), opt->max_chains,
-        opt->max_sites, opt->chi_cap, opt->max_bonds, max_blocks);
+        opt->max_sites, opt->chi_cap, opt->max_bonds, max_blocks, svd_only);
   if (max_blocks > 0) {
     // the block batch: a context of max_blocks two-site chains on the
     // tail of the workspace, with the same SVD settings
@@ -1201,7 +1212,7 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
     so.precision = HMPS_PREC_FP64;
     so.max_sweeps = ctx->opt.max_sweeps;
     so.jacobi_tol = ctx->opt.jacobi_tol;
-    hmps_status e2 = hmps_create(&ctx->sub, &so);
+    hmps_status e2 = create_ctx(&ctx->sub, &so, true);
     if (e2 == HMPS_OK &&
         hipHostMalloc((void **)&ctx->h_u1_kv, sizeof(int32_t) * max_blocks) !=
             hipSuccess)
@@ -1223,6 +1234,13 @@ hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
   }
   *out = ctx;
   return HMPS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hmps_status hmps_create(hmps_ctx **out, const hmps_options *opt) {
+  return create_ctx(out, opt, false);
 }
 
 void hmps_destroy(hmps_ctx *ctx) {

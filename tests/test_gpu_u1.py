@@ -89,13 +89,13 @@ def test_u1_chain_matches_the_oracle():
 def test_u1_exhaustive_batch_equals_trotter():
     # all 81 S^z environment states of the 2x3 W=1 ladder, untruncated: the
     # P-weighted mean is the Trotter thermal average.  81 chains with up to
-    # 9 blocks each exceed the default 324 blocks of a pass: the updates run
-    # in several passes.
+    # 9 blocks each in passes of at most 200 blocks: the updates run in
+    # several passes.
     L, W, beta, tau = 3, 1, 1.0, 0.1
     olat = model.ladder(L, 1.0, 1.0, W=W)
     states = np.array(list(itertools.product(range(3), repeat=4)), np.uint8)
     print("case: U(1) exhaustive batch", flush=True)
-    ctx, lat = u1_ctx(L, W, 81, len(states))
+    ctx, lat = u1_ctx(L, W, 81, len(states), max_blocks=200)
     ctx.hmps_init_cluster_env(lat, len(states), 0, env_state=states)
     ctx.hmps_evolve(beta, tau, 81, 0.0)
     g = ctx.hmps_measure()
