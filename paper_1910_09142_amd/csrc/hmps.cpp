@@ -875,6 +875,7 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
   int max_chiL = 1, max_chiR = 1;
   double flops = 0.0;
   int64_t n_blocks = 0;
+  size_t largest = 0;  // entries of the largest block theta'
   for (int c = 0; c < ctx->B; ++c) {
     const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
     max_chiL = std::max(max_chiL, row[k]);
@@ -925,6 +926,12 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
       }
       const double lq = std::max(mq, nq), nn = std::min(mq, nq);
       flops += 14.0 * lq * nn * nn + 8.0 * nn * nn * nn;
+      int cl = 1, cr = 1;
+      for (int x = 0; x < 3; ++x) {
+        cl = std::max(cl, bk.row[x].count);
+        cr = std::max(cr, bk.col[x].count);
+      }
+      largest = std::max(largest, (size_t)9 * cl * cr);
       blocks[c].push_back(bk);
     }
     n_blocks += (int64_t)blocks[c].size();
@@ -945,6 +952,14 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
   LAUNCHCHK(ctx);
   const int kmax = std::max(
       1, std::min(u.chi_max, 3 * std::max(max_chiL, max_chiR)));
+  // The blocks take the in-LDS SVD only when all of them fit it: one
+  // launch.  Otherwise every block joins the blocked rounds that the large
+  // ones need anyway, where a small block costs a few more workgroups; the
+  // in-LDS kernel beside them would add its own latency.  Measured with 64
+  // chains on the 2x16 ladder at chi 256: 3574 -> 3817 gate applications/s;
+  // on the 2x3 ladder (every block small, one chain) the in-LDS path is
+  // 1.8x faster than the rounds.
+  sub->small_max = largest <= ctx->small_max ? ctx->small_max : 0;
   std::vector<std::vector<std::pair<int, int>>> newg(ctx->B);
   for (int c0 = 0; c0 < ctx->B;) {
     // the chains c0 .. c1-1 whose blocks fit one pass
