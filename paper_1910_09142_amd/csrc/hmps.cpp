@@ -291,10 +291,16 @@ struct hmps_ctx {
   // charges of every bond of every chain as runs (charge, count) in index
   // order, one run per charge: [B][len+1]
   std::vector<std::vector<std::pair<int, int>>> h_qg;
-  int32_t *d_u1_blk = nullptr, *d_u1_ch = nullptr, *d_u1_kv = nullptr,
-          *d_u1_jmap = nullptr;
+  int32_t *d_u1_blk = nullptr, *d_u1_kv = nullptr, *d_u1_jmap = nullptr;
   double *d_u1_scale = nullptr;
-  int32_t *h_u1_kv = nullptr;  // pinned [max_blocks]
+  int32_t *h_u1_kv = nullptr;   // pinned [max_blocks]
+  int32_t *h_u1_err = nullptr;  // pinned [max_blocks] the blocks' error flags
+  int32_t *h_u1_tab = nullptr;  // pinned block and chain tables of a pass
+  // the block batch leaves its ranks and flags on the device for the U(1)
+  // update to read with its own; its round time is read then
+  bool defer_finish = false;
+  bool pending_time = false;
+  double pending_svd_flops = 0.0;
   size_t u1_sub_off = 0, u1_sub_bytes = 0;
   int64_t u1_blocks = 0;
   // device buffers (carved from the workspace)
@@ -416,8 +422,9 @@ size_t carve(hmps_ctx *c, char *base, int max_chains, int max_sites,
   if (max_blocks > 0) {
     // U(1): block and chain tables of a pass, the merge's results, and the
     // workspace of the block batch (two-site chains of up to chi_cap)
-    t->d_u1_blk = cv.take<int32_t>((size_t)max_blocks * U1_BLK);
-    t->d_u1_ch = cv.take<int32_t>(B * U1_CH);
+    // the block table of a pass and its chain table right after it: one
+    // copy from the host
+    t->d_u1_blk = cv.take<int32_t>((size_t)max_blocks * U1_BLK + B * U1_CH);
     t->d_u1_kv = cv.take<int32_t>(max_blocks);
     t->d_u1_scale = cv.take<double>(max_blocks);
     t->d_u1_jmap = cv.take<int32_t>(B * n_cap);
@@ -778,6 +785,16 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   launch_writeback(b, s, u, max_vlen, max_nvec, kmax,
                    (max_qr2_n + QB - 1) / QB, st);
   HIPCHK(hipGetLastError());
+  if (ctx->defer_finish) {
+    // the block batch of a U(1) update: that update reads the ranks and
+    // error flags, and then the round time (finish_deferred)
+    ctx->pending_time = timed_svd;
+    ctx->pending_svd_flops = svd_flops;
+    ctx->have_spectrum = true;
+    ctx->stats.algo_flops += flops;
+    ctx->stats.updates += ctx->B;
+    return HMPS_OK;
+  }
   HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_knew, sizeof(int32_t) * ctx->B,
                         hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(ctx->h_stage + ctx->opt.max_chains, ctx->d_err,
@@ -847,6 +864,19 @@ void init_host_charges(hmps_ctx *ctx, const uint8_t *labels) {
       }
     }
   }
+}
+
+// The round time of a deferred update of the block batch, once its stream
+// has been synchronised.
+hmps_status finish_deferred(hmps_ctx *ctx, hmps_ctx *sub) {
+  if (sub->pending_time) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, sub->svd_ev[0], sub->svd_ev[1]));
+    sub->stats.svd_seconds += 1e-3 * ms;
+    sub->stats.svd_flops += sub->pending_svd_flops;
+    sub->pending_time = false;
+  }
+  return HMPS_OK;
 }
 
 // One U(1) update on (k, k+1) for every chain (Exploiting Conserved Quantum
@@ -961,13 +991,16 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
   // 1.8x faster than the rounds.
   sub->small_max = largest <= ctx->small_max ? ctx->small_max : 0;
   std::vector<std::vector<std::pair<int, int>>> newg(ctx->B);
+  bool single = true;  // one pass: its read-back is the update's last sync
   for (int c0 = 0; c0 < ctx->B;) {
     // the chains c0 .. c1-1 whose blocks fit one pass
     int nb = 0, c1 = c0;
     while (c1 < ctx->B && nb + (int)blocks[c1].size() <= ctx->max_blocks)
       nb += (int)blocks[c1++].size();
-    std::vector<int32_t> tb((size_t)std::max(nb, 1) * U1_BLK, 0),
-        tc((size_t)(c1 - c0) * U1_CH, 0);
+    if (c1 < ctx->B) single = false;
+    // the block table, then the chain table, in pinned memory: one copy
+    int32_t *tb = ctx->h_u1_tab;
+    int32_t *tc = tb + (size_t)nb * U1_BLK;
     sub->h_chi.assign((size_t)std::max(nb, 1) * 3, 1);
     int v = 0;
     for (int c = c0; c < c1; ++c) {
@@ -975,6 +1008,7 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
       t[0] = c;
       t[1] = v;
       t[2] = (int32_t)blocks[c].size();
+      t[3] = 0;
       for (const Blk &bk : blocks[c]) {
         int32_t *e = &tb[(size_t)v * U1_BLK];
         int cl = 1, cr = 1;
@@ -995,28 +1029,20 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
         ++v;
       }
     }
-    if (nb > 0) {
-      sub->B = nb;
-      HIPCHK(hipMemcpyAsync(ctx->d_u1_blk, tb.data(),
-                            sizeof(int32_t) * (size_t)nb * U1_BLK,
-                            hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync(sub->d_chi, sub->h_chi.data(),
-                            sizeof(int32_t) * 3 * (size_t)nb,
-                            hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemsetAsync(sub->d_err, 0, sizeof(int32_t) * nb, st));
-      HIPCHK(hipMemsetAsync(sub->d_disc, 0, sizeof(double) * nb, st));
-      HIPCHK(hipMemsetAsync(sub->d_logw, 0, sizeof(double) * nb, st));
-    }
-    HIPCHK(hipMemcpyAsync(ctx->d_u1_ch, tc.data(),
-                          sizeof(int32_t) * tc.size(), hipMemcpyHostToDevice,
-                          st));
+    const size_t n_tab = (size_t)nb * U1_BLK + (size_t)(c1 - c0) * U1_CH;
+    HIPCHK(hipMemcpyAsync(ctx->d_u1_blk, tb, sizeof(int32_t) * n_tab,
+                          hipMemcpyHostToDevice, st));
     U1Args a;
     a.blk = ctx->d_u1_blk;
-    a.chains = ctx->d_u1_ch;
+    a.chains = ctx->d_u1_blk + (size_t)nb * U1_BLK;
     a.n_chains = c1 - c0;
     a.n_blocks = nb;
     a.k = k;
     a.right = right ? 1 : 0;
+    a.bchi = sub->d_chi;
+    a.berr = sub->d_err;
+    a.bdisc = sub->d_disc;
+    a.blogw = sub->d_logw;
     a.bsites = sub->d_sites;
     a.bsite_cap = sub->site_cap;
     a.bTH = sub->d_TH;
@@ -1033,17 +1059,42 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
     LAUNCHCHK(ctx);
     if (nb > 0) {
       // every block keeps all it resolves; the merge truncates
+      sub->B = nb;
+      sub->defer_finish = true;
       const hmps_status e =
           do_update(sub, 0, OP_SWAP, right, sub->opt.chi_cap, 0.0);
+      sub->defer_finish = false;
       if (e) return fail(ctx, e, "charge block SVD: " + sub->err);
     }
     launch_u1_merge(b, s, u, a, st);
     launch_u1_scatter(b, a, max_chiL, max_chiR, kmax, st);
     HIPCHK(hipGetLastError());
-    if (nb > 0)
+    if (nb > 0) {
       HIPCHK(hipMemcpyAsync(ctx->h_u1_kv, ctx->d_u1_kv, sizeof(int32_t) * nb,
                             hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(ctx->h_u1_err, sub->d_err, sizeof(int32_t) * nb,
+                            hipMemcpyDeviceToHost, st));
+    }
+    if (single) {
+      HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_knew,
+                            sizeof(int32_t) * ctx->B, hipMemcpyDeviceToHost,
+                            st));
+      HIPCHK(hipMemcpyAsync(ctx->h_stage + ctx->opt.max_chains, ctx->d_err,
+                            sizeof(int32_t) * ctx->B, hipMemcpyDeviceToHost,
+                            st));
+    }
     HIPCHK(hipStreamSynchronize(st));
+    if (nb > 0) {
+      hmps_status e = finish_deferred(ctx, sub);
+      if (e) return e;
+    }
+    for (int w = 0; w < nb; ++w)
+      if (ctx->h_u1_err[w])
+        return fail(ctx, HMPS_E_NUMERIC,
+                    std::string("charge block SVD: ") +
+                        (ctx->h_u1_err[w] == 1
+                             ? "in-LDS Jacobi did not converge"
+                             : "zero or non-finite singular values"));
     v = 0;
     for (int c = c0; c < c1; ++c)
       for (const Blk &bk : blocks[c]) {
@@ -1052,11 +1103,14 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
       }
     c0 = c1;
   }
-  HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_knew, sizeof(int32_t) * ctx->B,
-                        hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(ctx->h_stage + ctx->opt.max_chains, ctx->d_err,
-                        sizeof(int32_t) * ctx->B, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  if (!single) {
+    HIPCHK(hipMemcpyAsync(ctx->h_stage, ctx->d_knew, sizeof(int32_t) * ctx->B,
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctx->h_stage + ctx->opt.max_chains, ctx->d_err,
+                          sizeof(int32_t) * ctx->B, hipMemcpyDeviceToHost,
+                          st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   for (int c = 0; c < ctx->B; ++c) {
     const int code = ctx->h_stage[ctx->opt.max_chains + c];
     const int kn = ctx->h_stage[c];
@@ -1229,8 +1283,14 @@ hmps_status create_ctx(hmps_ctx **out, const hmps_options *opt,
     so.jacobi_tol = ctx->opt.jacobi_tol;
     hmps_status e2 = create_ctx(&ctx->sub, &so, true);
     if (e2 == HMPS_OK &&
-        hipHostMalloc((void **)&ctx->h_u1_kv, sizeof(int32_t) * max_blocks) !=
-            hipSuccess)
+        (hipHostMalloc((void **)&ctx->h_u1_kv,
+                       sizeof(int32_t) * max_blocks) != hipSuccess ||
+         hipHostMalloc((void **)&ctx->h_u1_err,
+                       sizeof(int32_t) * max_blocks) != hipSuccess ||
+         hipHostMalloc((void **)&ctx->h_u1_tab,
+                       sizeof(int32_t) * ((size_t)max_blocks * U1_BLK +
+                                          (size_t)opt->max_chains * U1_CH)) !=
+             hipSuccess))
       e2 = HMPS_E_DEVICE;
     if (e2 == HMPS_OK &&
         (hipMemsetAsync(ctx->sub->d_sweeps, 0, sizeof(int32_t) * max_blocks,
@@ -1264,6 +1324,8 @@ void hmps_destroy(hmps_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   if (ctx->h_u1_kv) (void)hipHostFree(ctx->h_u1_kv);
+  if (ctx->h_u1_err) (void)hipHostFree(ctx->h_u1_err);
+  if (ctx->h_u1_tab) (void)hipHostFree(ctx->h_u1_tab);
   if (ctx->sub) hmps_destroy(ctx->sub);
   for (hipEvent_t ev : ctx->sweep_ev)
     if (ev) (void)hipEventDestroy(ev);

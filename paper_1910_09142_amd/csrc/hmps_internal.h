@@ -269,7 +269,10 @@ struct U1Args {
   int n_blocks;           // blocks of the pass
   int k;                  // left site of the update
   int right;              // the singular values go right
-  // the block batch: its sites (two per block), TH and X, sig, knew
+  // the block batch: its dimensions and flags (set by k_u1_gather), its
+  // sites (two per block), TH and X, sig, knew
+  int32_t *bchi, *berr;
+  double *bdisc, *blogw;
   double *bsites;
   size_t bsite_cap;
   double *bTH, *bX;
@@ -283,7 +286,8 @@ struct U1Args {
   int32_t *jmap;        // [chain][jstride] new bond index -> block << 16 | i
   int jstride;
 };
-// theta' blocks of every block of the pass (from the chains' TH)
+// theta' blocks of every block of the pass (from the chains' TH), and the
+// block batch's dimensions {chi_l', 1, chi_r'} with its flags cleared
 void launch_u1_gather(const Batch &b, const UpdScratch &s, const U1Args &a,
                       hipStream_t st);
 // the kept set over all blocks of each chain (rule of k_truncate), the

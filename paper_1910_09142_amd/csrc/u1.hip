@@ -52,6 +52,14 @@ __global__ void __launch_bounds__(NT)
   const bool tp = np > mp;
   const int Lp = tp ? np : mp, Np = tp ? mp : np;
   const int ldp = vec_ld(Lp);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.bchi[3 * v] = cl;
+    a.bchi[3 * v + 1] = 1;
+    a.bchi[3 * v + 2] = cr;
+    a.berr[v] = 0;
+    a.bdisc[v] = 0.0;
+    a.blogw[v] = 0.0;
+  }
   double *dTH = a.bTH + (size_t)v * a.bstride;
   double *dX = a.bX + (size_t)v * a.bstride;
   const size_t total = (size_t)ldp * Np;
