@@ -524,9 +524,9 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
 // the vectors, of the 16-wide rounds.  Per round:
 //   1. Gram of the 64 vectors, its ten upper 16 x 16 tiles by FP64 MFMA:
 //      waves 0-3 accumulate tiles (0,0) (0,1) (0,2) (0,3) (1,1) of the four
-//      16-vector sub-blocks, waves 4-7 the other five, each group over all
-//      16-row chunks (the second load of a chunk hits L2); the partials are
-//      summed in a fixed order;
+//      16-vector sub-blocks, waves 4-7 the other five (sub-blocks 1-3 only),
+//      each group over all 16-row chunks (the second load of a chunk may hit
+//      L2); the partials are summed in a fixed order;
 //   2. the convergence test of the 16-wide rounds;
 //   3. one cyclic Jacobi sweep of the 64 x 64 Gram, its upper triangle
 //      packed and double-buffered in LDS, one barrier per rotation round:
@@ -606,10 +606,13 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       xs[k] = X + (size_t)colidx(16 * k + li) * ld + 4 * lk;
+    // group 1 never uses sub-block 0 (tiles (1,2) .. (3,3))
     auto load4 = [&](int e0, v4d (&v)[4]) {
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        v[k] = *reinterpret_cast<const v4d *>(xs[k] + e0);
+        v[k] = (k > 0 || grp == 0)
+                   ? *reinterpret_cast<const v4d *>(xs[k] + e0)
+                   : v4d{0.0, 0.0, 0.0, 0.0};
     };
     auto mm = [&](v4d &a, const v4d &x, const v4d &y) {
       a = mfma_f64(x.x, y.x, a);
