@@ -316,6 +316,21 @@ hmps_status hmps_collapse_resample(hmps_ctx *ctx, int32_t basis,
 /* Counters since init. */
 hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out);
 
+/* Block width of the Jacobi rounds (a tuning choice: the rounds rotate
+ * pairs of 16-vector blocks, or of 32-vector blocks for large FP64 updates
+ * in large batches).  Entry i: updates of a batch of at least
+ * chains_min[i] chains take 32-vector blocks for every chain of at least
+ * nvec_min[i] vectors (the smaller dimension of theta').  nvec_min
+ * ascending from 512, chains_min >= 1 and not increasing; at most 16
+ * entries; n = 0 restores the default, measured on MI355X: {540 vectors:
+ * 64 chains, 768: 16, 1152: 8, 1536: 8}.  The width
+ * changes the rounding of an update, not its result beyond it.  The
+ * environment variable HMPS_WIDE=0 or 1, read at create time, overrides
+ * the rule (never or always).  E_INVALID for a malformed rule. */
+hmps_status hmps_set_width_rule(hmps_ctx *ctx, int32_t n,
+                                const int32_t *nvec_min,
+                                const int32_t *chains_min);
+
 /* Charges of bond `bond` (0..n_sites) of chain `chain` on a HMPS_SYM_U1
  * context (Exploiting Conserved Quantum Numbers subsection): q[i], i <
  * chi[bond], is the Q of the sites left of the bond for bond index i;

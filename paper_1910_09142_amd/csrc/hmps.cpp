@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <string>
 #include <vector>
@@ -34,14 +35,24 @@ constexpr int OP_SWAP = -1;
 constexpr int RR_FP32_SWEEPS = 40;
 constexpr int OP_IDENT = -2;
 constexpr size_t ALIGN = 256;
-// Batches from this many chains on take wide (32-vector) blocks for their
-// large FP64 updates.  A wide block pair is four times the MFMA work of a
-// 16-wide one on a single compute unit, in half as many workgroups: it
-// pays once the rounds fill the chip.  Measured on the chi = 256 gate (768
-// vectors): 4 chains 143 vs 181 updates/s, 8: 278 vs 357, 16: 528 vs
-// 516, 32: 710 vs 662, 64: 909 vs 762.  A chain's result depends on its
-// own input and on this choice only.
-constexpr int WIDE_MIN_CHAINS = 16;
+// The width rule: an update takes wide (32-vector) blocks for its chains of
+// at least nvec_min vectors when the batch has at least chains_min chains
+// (entries with nvec_min ascending and chains_min not increasing, so the
+// entries a batch size satisfies give one threshold).  A wide block pair
+// is four times the MFMA work of a 16-wide one on a single compute unit,
+// in half as many workgroups: it pays once the rounds fill the chip, with
+// fewer chains for larger updates.  The default is the table measured on
+// MI355X by tune_width.py (width_rule_gfx950.json): gate applications on
+// bonds of chi = 180, 256, 384, 512 with 1 .. 64 chains; e.g. at chi = 256
+// (768 vectors) 16-wide vs wide 356.6 vs 283.6 per s at 8 chains, 514.3
+// vs 536.4 at 16, 767.5 vs 912.7 at 64.  hmps_set_width_rule replaces it.
+// A chain's result depends on its own input and on the width it takes.
+struct WidthEntry {
+  int nvec_min, chains_min;
+};
+constexpr int MAX_WIDTH_RULE = 16;
+const WidthEntry DEFAULT_WIDTH_RULE[] = {
+    {540, 64}, {768, 16}, {1152, 8}, {1536, 8}};
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -264,9 +275,11 @@ struct hmps_ctx {
   // their two blocks (16 inner rounds instead of 31): measured on the same
   // ladder, 4% more outer sweeps and 23% less time (one chain).
   int cross_inner = 1;
-  // wide (32-vector) blocks for the large FP64 updates: -1 = from
-  // WIDE_MIN_CHAINS chains on, 0 = never, 1 = always (HMPS_WIDE)
+  // wide (32-vector) blocks for the large FP64 updates: -1 = by the width
+  // rule, 0 = never, 1 = always (HMPS_WIDE)
   int wide = -1;
+  std::vector<WidthEntry> width_rule{std::begin(DEFAULT_WIDTH_RULE),
+                                    std::end(DEFAULT_WIDTH_RULE)};
   // largest theta' (m * n doubles) whose SVD runs in one workgroup's LDS;
   // larger ones take the blocked rounds.  The in-LDS kernel runs its pair
   // products on vector lanes, so beyond a few thousand entries the blocked
@@ -537,9 +550,21 @@ hmps_status check_usable(hmps_ctx *ctx, bool need_init) {
   return HMPS_OK;
 }
 
+// The smallest vector count that takes wide blocks in an update of this
+// batch (0: none).
+int wide_threshold(const hmps_ctx *ctx) {
+  if (ctx->wide == 0) return 0;
+  if (ctx->wide == 1) return W32_MIN_N;
+  int t = 0;
+  for (const WidthEntry &e : ctx->width_rule)
+    if (ctx->B >= e.chains_min && (t == 0 || e.nvec_min < t)) t = e.nvec_min;
+  return t;
+}
+
 // Parameters of one two-site update on (k, k+1).
 UpdParams update_params(const hmps_ctx *ctx, int k, int op, bool right,
-                        int chi_max, double cutoff, int mixed, int wide) {
+                        int chi_max, double cutoff, int mixed,
+                        int wide_min) {
   const bool is_move = (op == OP_IDENT);
   UpdParams u;
   u.k = k;
@@ -564,7 +589,7 @@ UpdParams update_params(const hmps_ctx *ctx, int k, int op, bool right,
   u.inner_sweeps = ctx->inner_sweeps;
   u.skip = ctx->skip;
   u.cross_inner = ctx->cross_inner;
-  u.wide = wide;
+  u.wide_min = wide_min;
   u.zero_ok = ctx->zero_ok ? 1 : 0;
   return u;
 }
@@ -593,7 +618,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   // by the host) is the FP64 SVD: both always FP64
   const int mixed = ctx->opt.precision == HMPS_PREC_MIXED_FP32 && !is_move &&
                     !ctx->skip_theta;
-  const int wide = ctx->wide >= 0 ? ctx->wide : (ctx->B >= WIDE_MIN_CHAINS);
+  const int wide = wide_threshold(ctx);
   for (int c = 0; c < ctx->B; ++c) {
     const int *row = &ctx->h_chi[(size_t)c * (L + 1)];
     {
@@ -2121,6 +2146,32 @@ hmps_status hmps_bond_dims(hmps_ctx *ctx, int32_t *chi) {
                         sizeof(int32_t) * ctx->B * (ctx->plan.len + 1),
                         hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return HMPS_OK;
+}
+
+hmps_status hmps_set_width_rule(hmps_ctx *ctx, int32_t n,
+                                const int32_t *nvec_min,
+                                const int32_t *chains_min) {
+  hmps_status st = check_usable(ctx, false);
+  if (st) return st;
+  if (n < 0 || n > MAX_WIDTH_RULE || (n > 0 && (!nvec_min || !chains_min)))
+    return fail(ctx, HMPS_E_INVALID, "width rule: 0..16 entries");
+  std::vector<WidthEntry> rule;
+  for (int i = 0; i < n; ++i) {
+    if (nvec_min[i] < W32_MIN_N || chains_min[i] < 1 ||
+        (i > 0 && (nvec_min[i] <= nvec_min[i - 1] ||
+                   chains_min[i] > chains_min[i - 1])))
+      return fail(ctx, HMPS_E_INVALID,
+                  "width rule: nvec_min ascending from " +
+                      std::to_string(W32_MIN_N) +
+                      ", chains_min >= 1 and not increasing");
+    rule.push_back({nvec_min[i], chains_min[i]});
+  }
+  ctx->width_rule =
+      n > 0 ? rule
+            : std::vector<WidthEntry>{std::begin(DEFAULT_WIDTH_RULE),
+                                      std::end(DEFAULT_WIDTH_RULE)};
+  if (ctx->sub) ctx->sub->width_rule = ctx->width_rule;
   return HMPS_OK;
 }
 

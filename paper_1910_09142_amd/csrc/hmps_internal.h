@@ -45,10 +45,10 @@ constexpr double TIE_TOL = 1e-8;
 constexpr int NORM_SPLIT = 16;
 
 // Householder QR preconditioning of the blocked Jacobi SVD: panel width,
-// and the longest vectors whose 16-column panel fits in one workgroup's
-// LDS (QB * QR_MAX_L doubles).
+// and the longest vectors whose 16-column panel one workgroup of the panel
+// kernel holds in registers (three rows per thread: chi <= 512).
 constexpr int QB = 16;
-constexpr int QR_MAX_L = 1152;
+constexpr int QR_MAX_L = 1536;
 
 // The per-chain path of an update's SVD: the in-LDS Jacobi for L * N <=
 // small_max, else the blocked rounds -- on R^T of theta' = Q R when the
@@ -98,11 +98,11 @@ __host__ __device__ inline int svd_path(int L, int N, size_t small_max,
   return PATH_PLAIN;
 }
 // Block width of a chain's Jacobi rounds: JBW for the FP64 blocked paths
-// from W32_MIN_N vectors on (when `wide`), JB otherwise.  The choice
-// depends on the chain's own dimensions and on `wide`, which the host
-// sets for the whole update.
-__host__ __device__ inline int round_width(int path, int nvec, int wide) {
-  return (wide && nvec >= W32_MIN_N &&
+// from wide_min vectors on (wide_min >= W32_MIN_N; 0: never), JB
+// otherwise.  The host sets wide_min for the whole update from the batch
+// size (the width rule).
+__host__ __device__ inline int round_width(int path, int nvec, int wide_min) {
+  return (wide_min > 0 && nvec >= wide_min &&
           (path == PATH_PLAIN || path == PATH_QR || path == PATH_QR2))
              ? JBW
              : JB;
@@ -191,7 +191,8 @@ struct UpdParams {
   double skip;        // relative squared norm below which a vector is zero
   double skip32;      // the same for the FP32 rounds
   int cross_inner;    // inner rotations across the two blocks only (rounds > 0)
-  int wide;           // wide (32-vector) blocks allowed
+  int wide_min;       // wide (32-vector) blocks from this many vectors on
+                      // (0: none)
   int precond;        // QR preconditioning of the blocked path: 0 none,
                       // 1 one QR, 2 two (FP64)
   size_t small_max;   // largest L * N of the in-LDS SVD path

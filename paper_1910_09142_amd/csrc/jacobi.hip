@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   // in X (second stage); on the two-QR mixed path the FP32 copy of R2^T in
   // Y, then the rrk columns of R^T W in Y; theta' in X else
   if (F32 && !path_is_rr(path)) return;
-  if (!F32 && round_width(path, N, u.wide) != JB) return;  // wide rounds
+  if (!F32 && round_width(path, N, u.wide_min) != JB) return;  // wide rounds
   const int L = (F32 || path == PATH_QR || path_has_qr2(path)) ? N : Lt;
   const int nvec = (!F32 && path_is_rr(path)) ? s.rrk[c] : N;
   const int NB = n_blocks_even(nvec, JB);
@@ -562,7 +562,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   const int m = 3 * chi[u.k], n = 3 * chi[u.k + 2];
   const int Lt = m > n ? m : n, N = m > n ? n : m;
   const int path = svd_path(Lt, N, u.small_max, u.precond, u.mixed);
-  if (round_width(path, N, u.wide) != JBW) return;
+  if (round_width(path, N, u.wide_min) != JBW) return;
   const int L = (path == PATH_QR || path == PATH_QR2) ? N : Lt;
   const int NB = n_blocks_even(N, JBW);
   if (r >= NB - 1 || pi >= NB / 2) return;

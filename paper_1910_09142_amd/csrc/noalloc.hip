@@ -181,7 +181,7 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
   u.cross_inner = 1;
   u.precond = 2;
   u.small_max = 2048;
-  u.wide = 0;  // theta' here stays below the wide-block size
+  u.wide_min = 0;  // theta' here stays below the wide-block size
   u.zero_ok = 0;
   hipLaunchKernelGGL(k_na_setup, dim3(64), dim3(256), 0, st, theta, chi_l,
                      chi_r, base);

@@ -42,6 +42,7 @@ EXPORTS = [
     "hmps_apply_gate", "hmps_init_cluster_env_at", "hmps_evolve_updates",
     "hmps_last_spectrum", "hmps_svd_probe_noalloc", "hmps_moments_reset",
     "hmps_bond_moments", "hmps_workspace_bytes_sym", "hmps_bond_charges",
+    "hmps_set_width_rule",
 ]
 
 
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.hmps_workspace_bytes_sym.argtypes = [C.c_int32] * 6
     lib.hmps_bond_charges.argtypes = [C.c_void_p, C.c_int32, C.c_int32,
                                       P(C.c_int32)]
+    lib.hmps_set_width_rule.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32),
+                                        P(C.c_int32)]
     lib.hmps_create.argtypes = [P(C.c_void_p), P(hmps_options)]
     lib.hmps_init_cluster_env.argtypes = [C.c_void_p, P(hmps_lattice),
                                           C.c_int32, C.c_uint64,
@@ -158,7 +161,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                  "hmps_susceptibility", "hmps_read_site", "hmps_load_bond",
                  "hmps_apply_gate", "hmps_init_cluster_env_at",
                  "hmps_evolve_updates", "hmps_last_spectrum",
-                 "hmps_bond_charges"):
+                 "hmps_bond_charges", "hmps_set_width_rule"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -237,7 +240,7 @@ class Context:
     def __init__(self, max_chains, max_sites, chi_cap, max_bonds,
                  precision=PREC_FP64, device=0, stream=None, max_sweeps=0,
                  jacobi_tol=0.0, progress=None, symmetry=SYM_NONE,
-                 max_blocks=0):
+                 max_blocks=0, width_rule=None):
         import torch
         lib = load()
         if not torch.cuda.is_available():
@@ -268,6 +271,8 @@ class Context:
         if st:
             raise HmpsError(st, "hmps_create")
         self.h = h
+        if width_rule is not None:
+            self.hmps_set_width_rule(width_rule)
         self.n_chains = 0
         self.n_env = 0
         self.n_bonds = 0
@@ -361,6 +366,16 @@ class Context:
         s = hmps_stats_t()
         self._check(self.lib.hmps_stats(self.h, C.byref(s)), "hmps_stats")
         return s
+
+    def hmps_set_width_rule(self, rule):
+        """rule: [(nvec_min, chains_min), ...] (see hmps_set_width_rule);
+        [] restores the default."""
+        nv = np.ascontiguousarray([r[0] for r in rule], np.int32)
+        ch = np.ascontiguousarray([r[1] for r in rule], np.int32)
+        self._check(self.lib.hmps_set_width_rule(
+            self.h, len(rule), _ptr(nv, C.c_int32) if len(rule) else None,
+            _ptr(ch, C.c_int32) if len(rule) else None),
+            "hmps_set_width_rule")
 
     def hmps_bond_charges(self, chain, bond):
         """Charges of the indices of bond `bond` of chain `chain` (U(1))."""

@@ -53,14 +53,16 @@ def oracle_state(psi):
 
 def run_case(chi_l, chi_m, chi_r, n_chains, chi_max, cutoff, n_apply,
              precision=hmps.PREC_FP64, J=1.0, x=0.025, seed=3,
-             tol_state=1e-10, tol_logw=1e-12, wide=None):
-    """wide: None, or whether the rounds must have taken wide blocks."""
+             tol_state=1e-10, tol_logw=1e-12, wide=None, width_rule=None):
+    """wide: None, or whether the rounds must have taken wide blocks;
+    width_rule: the context's width rule (None: the default)."""
     print(f"case: bond {chi_l}x{chi_m}x{chi_r}, {n_chains} chains, "
           f"chi_max {chi_max}, precision {precision}", flush=True)
     center, right = workloads.bond_tensors(seed, n_chains, chi_l, chi_m,
                                            chi_r)
     cap = max(chi_l, chi_m, chi_r, chi_max)
-    ctx = hmps.Context(n_chains, 2, cap, 1, precision=precision)
+    ctx = hmps.Context(n_chains, 2, cap, 1, precision=precision,
+                       width_rule=width_rule)
     ctx.hmps_load_bond(center, right)
     psis = [mps.MPS([to_oracle(center[c]), to_oracle(right[c])], 0)
             for c in range(n_chains)]
@@ -123,16 +125,35 @@ def test_chi512_largest_bond():
     run_case(512, 512, 512, 1, 512, 1e-10, 2, seed=11)
 
 
-def test_wide_blocks_from_sixteen_chains():
-    # theta' 540 x 540 in 16 chains: the rounds take 32-vector blocks (18
-    # of them, the last ragged), each block pair one workgroup; every chain
-    # matches the oracle to the same bars as the 16-wide rounds
-    run_case(180, 180, 180, 16, 180, 1e-10, 2, seed=13, wide=True)
+def test_wide_blocks_by_the_width_rule():
+    # theta' 540 x 540 in 16 chains.  Under a rule {512 vectors: 16 chains}
+    # the rounds take 32-vector blocks (18 of them, the last ragged), each
+    # block pair one workgroup, and every chain matches the oracle to the
+    # bars of the 16-wide rounds; the default rule (measured: 540 vectors
+    # take wide blocks from 64 chains on) keeps them 16-wide
+    run_case(180, 180, 180, 16, 180, 1e-10, 2, seed=13, wide=True,
+             width_rule=[(512, 16)])
+    run_case(180, 180, 180, 16, 180, 1e-10, 1, seed=13, wide=False)
+
+
+def test_width_rule_is_checked():
+    ctx = hmps.Context(2, 2, 8, 1)
+    for bad in ([(500, 4)],                 # below 512 vectors
+                [(768, 0)],                 # no chains
+                [(768, 4), (600, 2)],       # nvec_min not ascending
+                [(768, 4), (1024, 8)],      # chains_min increasing
+                [(512 + i, 1) for i in range(17)]):   # too many entries
+        with pytest.raises(hmps.HmpsError, match="status 1"):
+            ctx.hmps_set_width_rule(bad)
+    ctx.hmps_set_width_rule([(600, 32), (900, 8), (1500, 8)])
+    ctx.hmps_set_width_rule([])             # the default again
+    ctx.hmps_destroy()
 
 
 def test_wide_blocks_follow_the_batch_size(monkeypatch):
-    # HMPS_WIDE (read when a context is created): unset, wide blocks from
-    # 16 chains on; 1 always (on the FP64 paths from 512 vectors); 0 never
+    # HMPS_WIDE (read when a context is created): unset, the width rule (by
+    # default 540 vectors take wide blocks from 64 chains on); 1 always (on
+    # the FP64 paths from 512 vectors); 0 never
     run_case(180, 180, 180, 2, 180, 1e-10, 1, seed=13, wide=False)
     monkeypatch.setenv("HMPS_WIDE", "1")
     run_case(180, 180, 180, 2, 180, 1e-10, 2, seed=13, wide=True)
@@ -143,11 +164,11 @@ def test_wide_blocks_follow_the_batch_size(monkeypatch):
 
 def test_wide_batch_is_bit_identical_to_single_chains(monkeypatch):
     # a chain's update depends on its own input and the block width only:
-    # in a batch of 16 (wide by default) and alone with wide blocks forced
-    # it gives the same bits
+    # in a batch of 16 (wide under the rule {512: 16}) and alone with wide
+    # blocks forced it gives the same bits
     chi, n = 180, 16
     center, right = workloads.bond_tensors(21, n, chi, chi, chi)
-    ctx = hmps.Context(n, 2, chi, 1)
+    ctx = hmps.Context(n, 2, chi, 1, width_rule=[(512, 16)])
     ctx.hmps_load_bond(center, right)
     ctx.hmps_apply_gate(1.0, 0.025, chi, 1e-10)
     assert ctx.hmps_stats().wide_launches > 0
