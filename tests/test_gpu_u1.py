@@ -16,7 +16,8 @@ Also checked: the untruncated exhaustive batch against the Trotter thermal
 average (1e-11); the charges the library reports against the nonzero
 pattern of every site tensor (exactly zero outside the blocks); <Q> equal
 to the charge of the last bond; the dense GPU path on the 2x8 ladder at
-the cap; and results independent of how the blocks are grouped in passes.
+the cap and on the 2x16 ladder at chi_max = 256; and results independent of
+how the blocks are grouped in passes.
 """
 import itertools
 
@@ -165,6 +166,37 @@ def test_u1_matches_the_dense_path_at_the_cap():
         assert np.abs(g["logw"] - d["logw"]).max() <= 1e-6
         assert np.abs(g["qn"] - np.round(g["qn"])).max() <= 1e-10
         assert np.array_equal(g["outcomes"], d["outcomes"])
+
+
+def test_u1_matches_the_dense_path_on_the_2x16_ladder():
+    # 2x16 ladder, W=2, J_rung=0.5, tau=0.05, chi_max=256, cutoff 1e-10,
+    # 8 chains, the first 6 Trotter steps (bonds reach chi ~ 200, theta' up
+    # to 768 x 768 split into its charge blocks): energies and correlators
+    # of the two paths agree at the level of a capped free-running state
+    wl = workloads.C3
+    L, W = wl.L, wl.W
+    print("case: U(1) vs dense, 2x16 at chi 256, 6 steps", flush=True)
+    n, bonds, order, mask = workloads.ladder_arrays(L, wl.J_leg, wl.J_rung,
+                                                    W)
+    lat = hmps.Lattice(n, bonds, order, mask)
+    out = {}
+    for sym in (hmps.SYM_U1, hmps.SYM_NONE):
+        ctx = hmps.Context(8, workloads.mps_length(L, W), wl.chi_max,
+                           len(bonds), symmetry=sym)
+        ctx.hmps_init_cluster_env(lat, 8, 17)
+        ctx.hmps_evolve(0.6, wl.tau, wl.chi_max, wl.cutoff)
+        out[sym] = (ctx.hmps_measure(), ctx.hmps_bond_dims(),
+                    ctx.hmps_stats().u1_blocks)
+        ctx.hmps_destroy()
+    (gu, chiu, blocks), (gd, chid, _) = out[hmps.SYM_U1], out[hmps.SYM_NONE]
+    assert blocks > 0
+    de = np.abs(gu["energy"] - gd["energy"]) / np.abs(gd["energy"])
+    print(f"  max dE/E {de.max():.2e}, max chi {chiu.max()}", flush=True)
+    assert chiu.max() > 128
+    assert de.max() <= 1e-8
+    assert np.abs(gu["bond_ss"] - gd["bond_ss"]).max() <= 2.5e-7
+    assert np.abs(gu["logw"] - gd["logw"]).max() <= 1e-6
+    assert np.abs(gu["qn"] - np.round(gu["qn"])).max() <= 1e-10
 
 
 def test_u1_results_do_not_depend_on_the_passes():
