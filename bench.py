@@ -46,6 +46,7 @@ DEFAULT_CHAINS = 64
 PLAN_GATES_PER_S_BATCHED = 150.0    # chi = 256, 64 chains
 PLAN_GATES_PER_S_SINGLE = 12.0      # chi = 256, one chain
 PLAN_SAMPLE_SECONDS = 60.0          # one 2x8 beta = 1 sample of 64 chains
+PLAN_U1_SAMPLE_SECONDS = 30.0       # the same sample with U(1) updates
 PLAN_STARTUP_SECONDS = 150.0        # first torch import on a fresh box,
                                     # inputs, library load
 
@@ -107,7 +108,7 @@ def planned_seconds(args) -> float:
     if args.workload == "gate" and not args.no_extras:
         t += n * B / PLAN_GATES_PER_S_BATCHED        # mixed, batched
         t += n / PLAN_GATES_PER_S_SINGLE              # one chain
-        t += PLAN_SAMPLE_SECONDS
+        t += PLAN_SAMPLE_SECONDS + PLAN_U1_SAMPLE_SECONDS
     return t + args.cpu_seconds
 
 
@@ -307,17 +308,17 @@ def gate_run(wl, center, right, precision, steps, warmup, label):
             "algo_tflops": (s1.algo_flops - s0.algo_flops) / elapsed / 1e12}
 
 
-def sample_run(wl, B, precision):
+def sample_run(wl, B, precision, symmetry=0):
     """One full Markov-chain sample of B chains of a ladder workload:
-    evolution to beta/2, measurement, collapse (timed from resident
-    product states)."""
+    evolution to beta/2, measurement, collapse in S^z (timed from resident
+    S^z product states); symmetry 1: U(1) block-sparse updates."""
     import torch
     from paper_1910_09142_amd import hmps, workloads
     n, bonds, order, mask = workloads.ladder_arrays(wl.L, wl.J_leg,
                                                     wl.J_rung, wl.W)
     lat = hmps.Lattice(n, bonds, order, mask)
     ctx = hmps.Context(B, workloads.mps_length(wl.L, wl.W), wl.chi_max,
-                       len(bonds), precision=precision)
+                       len(bonds), precision=precision, symmetry=symmetry)
     ctx.hmps_init_cluster_env(lat, B, wl.seed)
     s0 = ctx.hmps_stats()
     torch.cuda.synchronize()
@@ -481,6 +482,16 @@ def main_gate(args, extras):
                                  name="ladder2x8_W2_beta1_chi128")
         out["samples_per_s"] = sample_run(c2, DEFAULT_CHAINS, prec)
         print("sample run done", file=sys.stderr, flush=True)
+        if args.precision == "fp64":
+            # the same sample with U(1) block-sparse updates (Exploiting
+            # Conserved Quantum Numbers subsection)
+            u1 = sample_run(c2, DEFAULT_CHAINS, prec, hmps.SYM_U1)
+            u1["speedup_vs_dense"] = (u1["value"] /
+                                      out["samples_per_s"]["value"])
+            u1["energy_mean_diff_vs_dense"] = abs(
+                u1["energy_mean"] - out["samples_per_s"]["energy_mean"])
+            out["samples_per_s_u1"] = u1
+            print("U(1) sample run done", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = cpu_baseline_bond(wl, center, right,
                                                 args.cpu_seconds)
