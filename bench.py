@@ -572,6 +572,22 @@ def main_window(args, wl, B, ctx):
     print(json.dumps(out), flush=True)
 
 
+def qn_histogram(charges):
+    """{Q: count} of the samples whose <Q> is an integer to 1e-6, and the
+    count of the others (S^x environments have no definite Q)."""
+    hist, other = {}, 0
+    for q in charges:
+        r = round(q)
+        if abs(q - r) <= 1e-6:
+            hist[str(r)] = hist.get(str(r), 0) + 1
+        else:
+            other += 1
+    out = dict(sorted(hist.items(), key=lambda kv: int(kv[0])))
+    if other:
+        out["not_integer"] = other
+    return out
+
+
 def main_ladder(args):
     import torch
     from paper_1910_09142_amd import hmps, workloads
@@ -616,10 +632,11 @@ def main_ladder(args):
     s0 = ctx.hmps_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    energies = []
+    energies, charges = [], []
     for _ in range(args.steps):
         m = one_sample(sample)
         energies += m["energy"].tolist()
+        charges += m["qn"].tolist()
         sample += 1
         print(f"timed sample done ({time.perf_counter() - t0:.1f} s)",
               file=sys.stderr, flush=True)
@@ -651,6 +668,10 @@ def main_ladder(args):
         "jacobi_sweeps": s1.jacobi_sweeps - s0.jacobi_sweeps,
         "u1_blocks": s1.u1_blocks - s0.u1_blocks,
         "energy_mean": sum(energies) / len(energies),
+        # the total S^z of the timed samples (an integer when the
+        # environment was collapsed in S^z; Exploiting Conserved Quantum
+        # Numbers subsection: it fluctuates from sample to sample)
+        "qn_histogram": qn_histogram(charges),
         "roofline": svd_roofline(wl.name, s0, s1,
                                  args.precision == "fp64" and
                                  B == wl.n_chains and

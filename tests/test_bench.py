@@ -78,3 +78,10 @@ def test_oracle_baseline_on_a_small_bond():
     assert "gate applications" in cb["sample"]
     for key in ("cpu_model", "blas", "blas_threads", "os_cpu_count"):
         assert key in cb
+
+
+def test_charge_histogram():
+    # integer <Q> (S^z environments) counted per value, the rest apart
+    h = bench.qn_histogram([0.0, 1.0 + 1e-9, -2.0, 0.5, 1.0, -2.0])
+    assert h == {"-2": 2, "0": 1, "1": 2, "not_integer": 1}
+    assert list(h)[:3] == ["-2", "0", "1"]

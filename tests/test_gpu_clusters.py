@@ -77,3 +77,42 @@ def test_interleaved_columns_chain():
         if got != want:
             assert ref[n]["near"] > 0, f"sample {n}: {got} != {want}"
             break
+
+
+def test_checkerboard_cluster_u1():
+    # the checkerboard cluster with U(1) updates: ancillas sit between
+    # physical sites of the MPS and swaps move them past the sampled sites,
+    # so the charge of every position follows the swaps.  The exhaustive
+    # S^z batch equals the Trotter average, every chain's <Q> is its
+    # environment's S^z total, and the site tensors vanish outside their
+    # charge blocks.
+    L, beta, tau = 3, 1.0, 0.1
+    olat, glat = masked_ladder(L, {0, 3, 4})
+    lay = model.layout(olat)
+    n_env = len(lay.env_positions)
+    states = np.array(list(itertools.product(range(3), repeat=n_env)),
+                      np.uint8)
+    print("case: checkerboard cluster, U(1)", flush=True)
+    n_sites = olat.n_phys + sum(olat.in_cluster)
+    ctx = hmps.Context(len(states), n_sites, 81, len(olat.bonds),
+                       symmetry=hmps.SYM_U1)
+    ctx.hmps_init_cluster_env(glat, len(states), 0, env_state=states)
+    ctx.hmps_evolve(beta, tau, 81, 0.0)
+    g = ctx.hmps_measure()
+    w = np.exp(g["logw"] - g["logw"].max())
+    avg = float((w * g["energy"]).sum() / w.sum())
+    ref = exact.trotter_energy(olat, beta, tau)
+    print(f"  weighted mean {avg:.13f} Trotter {ref:.13f}", flush=True)
+    assert abs(avg - ref) < 1e-11
+    q = (1 - states.astype(int)).sum(axis=1)
+    assert np.abs(g["qn"] - q).max() < 1e-10
+    sz = 1 - np.arange(3)
+    for c in (0, 13, len(states) - 1):
+        qs = [ctx.hmps_bond_charges(c, b) for b in range(n_sites + 1)]
+        for p in range(n_sites):
+            T = ctx.hmps_read_site(c, p)
+            sign = -1 if lay.is_ancilla[p] else 1
+            allowed = (qs[p + 1][None, None, :] ==
+                       qs[p][None, :, None] + sign * sz[:, None, None])
+            assert np.abs(T[~allowed]).max(initial=0.0) == 0.0, (c, p)
+    ctx.hmps_destroy()
