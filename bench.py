@@ -353,7 +353,11 @@ def main_wlimit(args):
     the cost per sample and the largest bond dimension.  Every chain starts
     from a uniform random product state; its first --warmup samples are
     discarded (burn-in towards the stationary distribution P_i / sum P_j)
-    and the next --steps are measured."""
+    and the next --steps are measured.  --symmetry u1 runs the hybrid and
+    ancilla points with U(1) block-sparse updates and every collapse in
+    S^z (Exploiting Conserved Quantum Numbers subsection); METTS keeps the
+    dense path and the alternating bases, since S^z collapses of every site
+    would keep it in one sector of the total S^z."""
     import numpy as np
     import torch
     from paper_1910_09142_amd import hmps, workloads
@@ -366,7 +370,9 @@ def main_wlimit(args):
         nc, ns, nb = (1, 1, 0) if W == L else (B, S, burn)
         n, bonds, order, mask = workloads.ladder_arrays(L, 1.0, 1.0, W)
         lat = hmps.Lattice(n, bonds, order, mask)
-        ctx = hmps.Context(nc, workloads.mps_length(L, W), chi, len(bonds))
+        u1 = args.symmetry == "u1" and W > 0
+        ctx = hmps.Context(nc, workloads.mps_length(L, W), chi, len(bonds),
+                           symmetry=hmps.SYM_U1 if u1 else hmps.SYM_NONE)
         ctx.hmps_init_cluster_env(lat, nc, 0)
         e = np.zeros((nc, ns))
         torch.cuda.synchronize()
@@ -377,7 +383,7 @@ def main_wlimit(args):
                 m = ctx.hmps_measure(hmps.MEASURE_ENERGY |
                                      hmps.MEASURE_ACCUMULATE)
                 e[:, k - nb] = m["energy"] / n
-            ctx.hmps_collapse_resample(k % 2)
+            ctx.hmps_collapse_resample(0 if u1 else k % 2)
             print(f"wlimit W={W}: sample {k + 1}/{nb + ns} "
                   f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
                   flush=True)
@@ -393,6 +399,7 @@ def main_wlimit(args):
         se = float(means.std(ddof=1) / np.sqrt(nc)) if nc > 1 else 0.0
         rows.append({"W": W, "method": ("METTS" if W == 0 else "ancilla"
                                         if W == L else "hybrid"),
+                     "symmetry": "u1" if u1 else "none",
                      "chains": nc, "samples_per_chain": ns,
                      "burn_in_per_chain": nb,
                      "energy_per_site": float(means.mean()),
@@ -414,7 +421,8 @@ def main_wlimit(args):
         "ladder Hamiltonian)",
         "config": {"workload": f"ladder2x{L}_beta{beta:g}_chi{chi}_Wlimits",
                    "n_chains": B, "L": L, "beta": beta, "tau": tau,
-                   "chi_max": chi, "cutoff": cut, "W": [0, 2, 4, L]},
+                   "chi_max": chi, "cutoff": cut, "W": [0, 2, 4, L],
+                   "symmetry": args.symmetry},
         "wlimit": rows, "seconds_total": time.perf_counter() - t_all}
     print(json.dumps(out), flush=True)
 
