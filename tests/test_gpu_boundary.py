@@ -6,6 +6,7 @@
   reproduce the uninterrupted batch bit for bit (every Philox counter
   carries the global chain id and the sample index).
 * An evolution applied in parts equals the whole evolution bit for bit.
+* The same holds on a U(1) context, with every collapse in S^z.
 * The `what` mask of hmps_measure selects outputs without changing them.
 * A Jacobi SVD that cannot converge within max_sweeps returns E_NUMERIC and
   poisons the context (E_STATE afterwards); the kernels still exit
@@ -187,3 +188,54 @@ def test_split_bf16_precision_is_rejected():
     with pytest.raises(hmps.HmpsError) as e:
         make(1, precision=hmps.PREC_MIXED_BF16X3)
     assert e.value.status == hmps.HMPS_E_INVALID
+
+
+def run_z(ctx, n_samples):
+    out = []
+    for _ in range(n_samples):
+        ctx.hmps_evolve(BETA, TAU, CHI, CUT)
+        m = ctx.hmps_measure()
+        m["outcomes"] = ctx.hmps_collapse_resample(0)
+        out.append(m)
+    return out
+
+
+def test_u1_offsets_resume_and_parts_bit_for_bit():
+    # the same bookkeeping on a U(1) context (every collapse in S^z): a
+    # split batch, a resumed chain and an evolution in parts reproduce the
+    # uninterrupted runs bit for bit
+    print("case: U(1) offsets, resume, parts", flush=True)
+    u1 = {"symmetry": hmps.SYM_U1}
+    ctx, lat = make(4, **u1)
+    ctx.hmps_init_cluster_env(lat, 4, 11)
+    whole = run_z(ctx, 3)
+    ctx.hmps_destroy()
+    for off in (0, 2):
+        ctx, lat = make(2, **u1)
+        ctx.hmps_init_cluster_env(lat, 2, 11, chain_offset=off)
+        part = run_z(ctx, 3)
+        ctx.hmps_destroy()
+        for n in range(3):
+            same(whole[n], part[n], slice(off, off + 2))
+    # resume at sample 2 from the S^z outcomes of sample 1
+    ctx, lat = make(4, **u1)
+    ctx.hmps_init_cluster_env(lat, 4, 11, env_state=whole[1]["outcomes"],
+                              sample=2)
+    part = run_z(ctx, 1)
+    ctx.hmps_destroy()
+    same(whole[2], part[0])
+    # an evolution in parts
+    env = np.array([[0, 2, 1, 1]], np.uint8)
+    ctx, lat = make(1, **u1)
+    ctx.hmps_init_cluster_env(lat, 1, 0, env_state=env)
+    ctx.hmps_evolve(BETA, TAU, CHI, CUT)
+    ref = ctx.hmps_measure()
+    ns, steps = hmps.hmps_schedule(lat)
+    total = 5 * len(steps)
+    ctx.hmps_init_cluster_env(lat, 1, 0, env_state=env)
+    for first, count in ((0, 37), (37, 64), (101, total - 101)):
+        ctx.hmps_evolve_updates(BETA, TAU, CHI, CUT, first, count)
+    got = ctx.hmps_measure()
+    ctx.hmps_destroy()
+    for key in ("energy", "bond_ss", "logw", "qn"):
+        assert np.array_equal(got[key], ref[key]), key
