@@ -534,7 +534,10 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
 //      entries they need as the block owners do), waves 1-7 own the 528
 //      2 x 2 blocks; on the cross rounds every thread keeps four (row,
 //      pair) items of Q in registers, the second column of a pair moving
-//      one lane per round; on the all-pairs round Q is updated in LDS;
+//      one lane per round, and the second block's vectors are relabelled
+//      in G after every round so that the pairs, and with them every LDS
+//      offset of the angle lanes and the owners, stay fixed; on the
+//      all-pairs round Q is updated in LDS;
 //   4. Xp <- Xp Q by FP64 MFMA, each wave reading and writing whole 16-row
 //      chunks of all 64 vectors.
 // =====================================================================
@@ -724,8 +727,55 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
       bcp[o] = rp + k;
     }
   }
-  // cross rounds: thread (row, i) holds Q[row][i] and Q[row][32 + (i + rr)
-  // % 32] for rows (tid >> 5) + 16 m
+  // Cross rounds relabel the second block after every round: the vector of
+  // the second block at label 32 + a moves to label 32 + (a - 1) mod 32 in
+  // the next round's copy of G.  Pair i is then (i, 32 + i) in every round,
+  // so every LDS offset of the loop is fixed, and it is computed here once.
+  // The values, and the order of the operations on them, are those of the
+  // pairing (i, 32 + (i + rr) mod 32) on fixed labels.  After a full inner
+  // sweep (32 rounds) the labels are the original ones again.
+  //   block owners: per block, the four entries read (rows (rp, 32 + rp),
+  //   columns (cp, 32 + cp)) and the four written in the next labels;
+  //   angle lane i: the next round's pair i is (i, 32 + (i + 1) mod 32) in
+  //   this round's labels, the first member from pair i and the second from
+  //   pair ip = (i + 1) mod 32: the diagonal 2 x 2 blocks of both pairs and
+  //   the block between them, rows from the lower-numbered pair.
+  int fo[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) fo[k] = 0;
+  bool aswap = false;
+  if (cross) {
+    auto gso = [](int x, int y) { return x <= y ? wtri(x, y) : wtri(y, x); };
+    if (tid < W_NPAIR) {
+      const int i = tid, ip = (tid + 1) & (W_NPAIR - 1);
+      aswap = ip < i;
+      const int ro = aswap ? ip : i, co = aswap ? i : ip;
+      fo[0] = wtri(i, i);
+      fo[1] = wtri(i, W_NPAIR + i);
+      fo[2] = wtri(W_NPAIR + i, W_NPAIR + i);
+      fo[3] = wtri(ip, ip);
+      fo[4] = wtri(ip, W_NPAIR + ip);
+      fo[5] = wtri(W_NPAIR + ip, W_NPAIR + ip);
+      fo[6] = gso(ro, co);
+      fo[7] = gso(ro, W_NPAIR + co);
+      fo[8] = gso(W_NPAIR + ro, co);
+      fo[9] = gso(W_NPAIR + ro, W_NPAIR + co);
+    }
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      if (own[o]) {
+        const int rp = brp[o], cp = bcp[o];
+        const int rpm = (rp - 1) & (W_NPAIR - 1), cpm = (cp - 1) & (W_NPAIR - 1);
+        fo[8 * o + 0] = wtri(rp, cp);
+        fo[8 * o + 1] = wtri(rp, W_NPAIR + cp);
+        fo[8 * o + 2] = wtri(cp, W_NPAIR + rp);
+        fo[8 * o + 3] = wtri(W_NPAIR + rp, W_NPAIR + cp);
+        fo[8 * o + 4] = wtri(rp, W_NPAIR + cpm);
+        fo[8 * o + 5] = wtri(cp, W_NPAIR + rpm);
+        fo[8 * o + 6] = gso(W_NPAIR + rpm, W_NPAIR + cpm);
+      }
+    }
+  }
   const int qi = tid & 31, qrow = tid >> 5;
   double qa[4], qb[4];
 #pragma unroll
@@ -741,7 +791,50 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
       const int rn = rr + 1 < nrounds ? rr + 1 : 0;
       double *Gc = G[cur];
       double *Gn = G[nxt];
-      if (tid < W_NPAIR) {
+      if (cross) {
+        if (tid < W_NPAIR) {
+          const double2 ji = csn[cur][tid];
+          const double2 jp = csn[cur][(tid + 1) & (W_NPAIR - 1)];
+          double g[4], nv[4];
+          g[0] = Gc[fo[0]];
+          g[1] = Gc[fo[1]];
+          g[2] = g[1];
+          g[3] = Gc[fo[2]];
+          rot_block(ji.x, ji.y, ji.x, ji.y, g, nv);
+          const double app = nv[0];
+          g[0] = Gc[fo[3]];
+          g[1] = Gc[fo[4]];
+          g[2] = g[1];
+          g[3] = Gc[fo[5]];
+          rot_block(jp.x, jp.y, jp.x, jp.y, g, nv);
+          const double aqq = nv[3];
+          g[0] = Gc[fo[6]];
+          g[1] = Gc[fo[7]];
+          g[2] = Gc[fo[8]];
+          g[3] = Gc[fo[9]];
+          const double2 jr = aswap ? jp : ji, jc = aswap ? ji : jp;
+          rot_block(jr.x, jr.y, jc.x, jc.y, g, nv);
+          const double apq = aswap ? nv[2] : nv[1];
+          double cr = 1.0, sr = 0.0;
+          const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
+          if (rot) flag[(isw + (rn == 0)) & 1] = 1;
+          csn[nxt][tid] = make_double2(cr, sr);
+        }
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+          if (own[o]) {
+            const double2 j1 = csn[cur][brp[o]], j2 = csn[cur][bcp[o]];
+            double g[4], nv[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) g[k] = Gc[fo[8 * o + k]];
+            rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
+            Gn[fo[8 * o + 0]] = nv[0];
+            Gn[fo[8 * o + 4]] = nv[1];
+            if (brp[o] != bcp[o]) Gn[fo[8 * o + 5]] = nv[2];
+            Gn[fo[8 * o + 6]] = nv[3];
+          }
+        }
+      } else if (tid < W_NPAIR) {
         // angles of pair tid of the next round: its members are row ra of
         // pair ia = (a0, a1) and row rb of pair ib = (b0, b1) of this round
         int pn, qn, ia, pa, ib, pb;
@@ -788,7 +881,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
       }
 #pragma unroll
       for (int o = 0; o < 2; ++o) {
-        if (own[o]) {
+        if (!cross && own[o]) {
           int p1, q1, p2, q2;
           inner_pair(cross, rr, brp[o], W_P2, p1, q1);
           inner_pair(cross, rr, bcp[o], W_P2, p2, q2);
