@@ -323,7 +323,7 @@ hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out);
  * nvec_min[i] vectors (the smaller dimension of theta').  nvec_min
  * ascending from 512, chains_min >= 1 and not increasing; at most 16
  * entries; n = 0 restores the default, measured on MI355X: {540 vectors:
- * 64 chains, 768: 16, 1152: 8, 1536: 8}.  The width
+ * 16 chains, 768: 16, 1152: 8, 1536: 8}.  The width
  * changes the rounding of an update, not its result beyond it.  The
  * environment variable HMPS_WIDE=0 or 1, read at create time, overrides
  * the rule (never or always).  E_INVALID for a malformed rule. */

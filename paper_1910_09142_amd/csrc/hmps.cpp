@@ -44,15 +44,15 @@ constexpr size_t ALIGN = 256;
 // fewer chains for larger updates.  The default is the table measured on
 // MI355X by tune_width.py (width_rule_gfx950.json): gate applications on
 // bonds of chi = 180, 256, 384, 512 with 1 .. 64 chains; e.g. at chi = 256
-// (768 vectors) 16-wide vs wide 356.6 vs 283.6 per s at 8 chains, 514.3
-// vs 536.4 at 16, 767.5 vs 912.7 at 64.  hmps_set_width_rule replaces it.
+// (768 vectors) 16-wide vs wide 356.9 vs 321.1 per s at 8 chains, 515.8
+// vs 602.3 at 16, 766.4 vs 983.3 at 64.  hmps_set_width_rule replaces it.
 // A chain's result depends on its own input and on the width it takes.
 struct WidthEntry {
   int nvec_min, chains_min;
 };
 constexpr int MAX_WIDTH_RULE = 16;
 const WidthEntry DEFAULT_WIDTH_RULE[] = {
-    {540, 64}, {768, 16}, {1152, 8}, {1536, 8}};
+    {540, 16}, {768, 16}, {1152, 8}, {1536, 8}};
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -280,6 +280,10 @@ struct hmps_ctx {
   int wide = -1;
   std::vector<WidthEntry> width_rule{std::begin(DEFAULT_WIDTH_RULE),
                                     std::end(DEFAULT_WIDTH_RULE)};
+  // the batch size the width rule reads, when not B: the U(1) block batch
+  // reads the chain count of the whole update, so that every pass of an
+  // update gives a block the same width
+  int width_batch = 0;
   // largest theta' (m * n doubles) whose SVD runs in one workgroup's LDS;
   // larger ones take the blocked rounds.  The in-LDS kernel runs its pair
   // products on vector lanes, so beyond a few thousand entries the blocked
@@ -555,9 +559,10 @@ hmps_status check_usable(hmps_ctx *ctx, bool need_init) {
 int wide_threshold(const hmps_ctx *ctx) {
   if (ctx->wide == 0) return 0;
   if (ctx->wide == 1) return W32_MIN_N;
+  const int batch = ctx->width_batch > 0 ? ctx->width_batch : ctx->B;
   int t = 0;
   for (const WidthEntry &e : ctx->width_rule)
-    if (ctx->B >= e.chains_min && (t == 0 || e.nvec_min < t)) t = e.nvec_min;
+    if (batch >= e.chains_min && (t == 0 || e.nvec_min < t)) t = e.nvec_min;
   return t;
 }
 
@@ -1085,6 +1090,7 @@ hmps_status do_update_u1(hmps_ctx *ctx, int k, int op, bool right,
     if (nb > 0) {
       // every block keeps all it resolves; the merge truncates
       sub->B = nb;
+      sub->width_batch = ctx->B;
       sub->defer_finish = true;
       const hmps_status e =
           do_update(sub, 0, OP_SWAP, right, sub->opt.chi_cap, 0.0);

@@ -552,6 +552,10 @@ constexpr int W_OWN0 = 64;
 constexpr int W_OWNERS = RT - W_OWN0;
 static_assert(W_NBLK <= 2 * W_OWNERS, "two blocks per owner at most");
 
+template <int V> struct IntC {
+  static constexpr int value = V;
+};
+
 // packed upper triangle, i <= j
 __device__ __forceinline__ int wtri(int i, int j) {
   return i * W_P2 - (i * (i - 1)) / 2 + (j - i);
@@ -740,6 +744,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
   //   this round's labels, the first member from pair i and the second from
   //   pair ip = (i + 1) mod 32: the diagonal 2 x 2 blocks of both pairs and
   //   the block between them, rows from the lower-numbered pair.
+  // (offsets in bytes, from the start of either copy of G)
   int fo[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) fo[k] = 0;
@@ -750,32 +755,34 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
       const int i = tid, ip = (tid + 1) & (W_NPAIR - 1);
       aswap = ip < i;
       const int ro = aswap ? ip : i, co = aswap ? i : ip;
-      fo[0] = wtri(i, i);
-      fo[1] = wtri(i, W_NPAIR + i);
-      fo[2] = wtri(W_NPAIR + i, W_NPAIR + i);
-      fo[3] = wtri(ip, ip);
-      fo[4] = wtri(ip, W_NPAIR + ip);
-      fo[5] = wtri(W_NPAIR + ip, W_NPAIR + ip);
-      fo[6] = gso(ro, co);
-      fo[7] = gso(ro, W_NPAIR + co);
-      fo[8] = gso(W_NPAIR + ro, co);
-      fo[9] = gso(W_NPAIR + ro, W_NPAIR + co);
+      fo[0] = 8 * wtri(i, i);
+      fo[1] = 8 * wtri(i, W_NPAIR + i);
+      fo[2] = 8 * wtri(W_NPAIR + i, W_NPAIR + i);
+      fo[3] = 8 * wtri(ip, ip);
+      fo[4] = 8 * wtri(ip, W_NPAIR + ip);
+      fo[5] = 8 * wtri(W_NPAIR + ip, W_NPAIR + ip);
+      fo[6] = 8 * gso(ro, co);
+      fo[7] = 8 * gso(ro, W_NPAIR + co);
+      fo[8] = 8 * gso(W_NPAIR + ro, co);
+      fo[9] = 8 * gso(W_NPAIR + ro, W_NPAIR + co);
     }
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
       if (own[o]) {
         const int rp = brp[o], cp = bcp[o];
         const int rpm = (rp - 1) & (W_NPAIR - 1), cpm = (cp - 1) & (W_NPAIR - 1);
-        fo[8 * o + 0] = wtri(rp, cp);
-        fo[8 * o + 1] = wtri(rp, W_NPAIR + cp);
-        fo[8 * o + 2] = wtri(cp, W_NPAIR + rp);
-        fo[8 * o + 3] = wtri(W_NPAIR + rp, W_NPAIR + cp);
-        fo[8 * o + 4] = wtri(rp, W_NPAIR + cpm);
-        fo[8 * o + 5] = wtri(cp, W_NPAIR + rpm);
-        fo[8 * o + 6] = gso(W_NPAIR + rpm, W_NPAIR + cpm);
+        fo[8 * o + 0] = 8 * wtri(rp, cp);
+        fo[8 * o + 1] = 8 * wtri(rp, W_NPAIR + cp);
+        fo[8 * o + 2] = 8 * wtri(cp, W_NPAIR + rp);
+        fo[8 * o + 3] = 8 * wtri(W_NPAIR + rp, W_NPAIR + cp);
+        fo[8 * o + 4] = 8 * wtri(rp, W_NPAIR + cpm);
+        fo[8 * o + 5] = 8 * wtri(cp, W_NPAIR + rpm);
+        fo[8 * o + 6] = 8 * gso(W_NPAIR + rpm, W_NPAIR + cpm);
       }
     }
   }
+  // cross rounds: thread (row, i) holds Q[row][i] and Q[row][32 + (i + rr)
+  // % 32] for rows (tid >> 5) + 16 m
   const int qi = tid & 31, qrow = tid >> 5;
   double qa[4], qb[4];
 #pragma unroll
@@ -784,146 +791,171 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     qa[mm] = row == qi ? 1.0 : 0.0;
     qb[mm] = row == W_NPAIR + qi ? 1.0 : 0.0;
   }
-  int gr = 0;
-  for (int isw = 0; isw < u.inner_sweeps; ++isw) {
-    for (int rr = 0; rr < nrounds; ++rr, ++gr) {
-      const int cur = gr & 1, nxt = cur ^ 1;
-      const int rn = rr + 1 < nrounds ? rr + 1 : 0;
-      double *Gc = G[cur];
-      double *Gn = G[nxt];
-      if (cross) {
+  // one cross round; the copy of G it reads is a constant of each
+  // instantiation, so every LDS access is a fixed offset from a constant
+  // address (the rounds alternate between the copies, 32 to a sweep)
+  auto cross_round = [&](auto cur_c, int rr, int isw) {
+    constexpr int cur = decltype(cur_c)::value, nxt = cur ^ 1;
+    const int rn = rr + 1 < W_NPAIR ? rr + 1 : 0;
+    const char *Gc = reinterpret_cast<const char *>(G[cur]);
+    char *Gn = reinterpret_cast<char *>(G[nxt]);
+    auto gc = [&](int o) -> double {
+      return *reinterpret_cast<const double *>(Gc + o);
+    };
+    auto gn = [&](int o) -> double & {
+      return *reinterpret_cast<double *>(Gn + o);
+    };
+    if (tid < W_NPAIR) {
+      const double2 ji = csn[cur][tid];
+      const double2 jp = csn[cur][(tid + 1) & (W_NPAIR - 1)];
+      double g[4], nv[4];
+      g[0] = gc(fo[0]);
+      g[1] = gc(fo[1]);
+      g[2] = g[1];
+      g[3] = gc(fo[2]);
+      rot_block(ji.x, ji.y, ji.x, ji.y, g, nv);
+      const double app = nv[0];
+      g[0] = gc(fo[3]);
+      g[1] = gc(fo[4]);
+      g[2] = g[1];
+      g[3] = gc(fo[5]);
+      rot_block(jp.x, jp.y, jp.x, jp.y, g, nv);
+      const double aqq = nv[3];
+      g[0] = gc(fo[6]);
+      g[1] = gc(fo[7]);
+      g[2] = gc(fo[8]);
+      g[3] = gc(fo[9]);
+      const double2 jr = aswap ? jp : ji, jc = aswap ? ji : jp;
+      rot_block(jr.x, jr.y, jc.x, jc.y, g, nv);
+      const double apq = aswap ? nv[2] : nv[1];
+      double cr = 1.0, sr = 0.0;
+      const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
+      if (rot) flag[(isw + (rn == 0)) & 1] = 1;
+      csn[nxt][tid] = make_double2(cr, sr);
+    }
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      if (own[o]) {
+        const double2 j1 = csn[cur][brp[o]], j2 = csn[cur][bcp[o]];
+        double g[4], nv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) g[k] = gc(fo[8 * o + k]);
+        rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
+        gn(fo[8 * o + 0]) = nv[0];
+        gn(fo[8 * o + 4]) = nv[1];
+        if (brp[o] != bcp[o]) gn(fo[8 * o + 5]) = nv[2];
+        gn(fo[8 * o + 6]) = nv[3];
+      }
+    }
+    const double2 jq = csn[cur][qi];
+    const int src = (lane & 32) | ((lane + 1) & 31);
+#pragma unroll
+    for (int mm = 0; mm < 4; ++mm) {
+      const double na = jq.x * qa[mm] - jq.y * qb[mm];
+      const double nb = jq.y * qa[mm] + jq.x * qb[mm];
+      qa[mm] = na;
+      qb[mm] = __shfl(nb, src);
+    }
+    __syncthreads();
+    if (rr == 0 && tid == 0) flag[(isw + 1) & 1] = 0;
+  };
+  if (cross) {
+    for (int isw = 0; isw < u.inner_sweeps; ++isw) {
+      for (int rr = 0; rr < W_NPAIR; rr += 2) {
+        cross_round(IntC<0>(), rr, isw);
+        cross_round(IntC<1>(), rr + 1, isw);
+      }
+      if (!flag[isw & 1]) break;
+    }
+  } else {
+    int gr = 0;
+    for (int isw = 0; isw < u.inner_sweeps; ++isw) {
+      for (int rr = 0; rr < nrounds; ++rr, ++gr) {
+        const int cur = gr & 1, nxt = cur ^ 1;
+        const int rn = rr + 1 < nrounds ? rr + 1 : 0;
+        double *Gc = G[cur];
+        double *Gn = G[nxt];
         if (tid < W_NPAIR) {
-          const double2 ji = csn[cur][tid];
-          const double2 jp = csn[cur][(tid + 1) & (W_NPAIR - 1)];
+          // angles of pair tid of the next round: its members are row ra of
+          // pair ia = (a0, a1) and row rb of pair ib = (b0, b1) of this round
+          int pn, qn, ia, pa, ib, pb;
+          inner_pair(cross, rn, tid, W_P2, pn, qn);
+          inner_slot(cross, rr, pn, W_P2, ia, pa);
+          inner_slot(cross, rr, qn, W_P2, ib, pb);
+          const int ra = pn < pa ? 0 : 1, rb = qn < pb ? 0 : 1;
+          const int a0 = ra ? pa : pn, a1 = ra ? pn : pa;
+          const int b0 = rb ? pb : qn, b1 = rb ? qn : pb;
+          const double2 ja = csn[cur][ia], jb = csn[cur][ib];
           double g[4], nv[4];
-          g[0] = Gc[fo[0]];
-          g[1] = Gc[fo[1]];
+          g[0] = Gc[wtri(a0, a0)];
+          g[1] = Gc[wtri(a0, a1)];
           g[2] = g[1];
-          g[3] = Gc[fo[2]];
-          rot_block(ji.x, ji.y, ji.x, ji.y, g, nv);
-          const double app = nv[0];
-          g[0] = Gc[fo[3]];
-          g[1] = Gc[fo[4]];
+          g[3] = Gc[wtri(a1, a1)];
+          rot_block(ja.x, ja.y, ja.x, ja.y, g, nv);
+          const double app = ra ? nv[3] : nv[0];
+          g[0] = Gc[wtri(b0, b0)];
+          g[1] = Gc[wtri(b0, b1)];
           g[2] = g[1];
-          g[3] = Gc[fo[5]];
-          rot_block(jp.x, jp.y, jp.x, jp.y, g, nv);
-          const double aqq = nv[3];
-          g[0] = Gc[fo[6]];
-          g[1] = Gc[fo[7]];
-          g[2] = Gc[fo[8]];
-          g[3] = Gc[fo[9]];
-          const double2 jr = aswap ? jp : ji, jc = aswap ? ji : jp;
-          rot_block(jr.x, jr.y, jc.x, jc.y, g, nv);
-          const double apq = aswap ? nv[2] : nv[1];
+          g[3] = Gc[wtri(b1, b1)];
+          rot_block(jb.x, jb.y, jb.x, jb.y, g, nv);
+          const double aqq = rb ? nv[3] : nv[0];
+          double apq;
+          if (ia < ib) {
+            g[0] = gs(Gc, a0, b0);
+            g[1] = gs(Gc, a0, b1);
+            g[2] = gs(Gc, a1, b0);
+            g[3] = gs(Gc, a1, b1);
+            rot_block(ja.x, ja.y, jb.x, jb.y, g, nv);
+            apq = ra ? (rb ? nv[3] : nv[2]) : (rb ? nv[1] : nv[0]);
+          } else {
+            g[0] = gs(Gc, b0, a0);
+            g[1] = gs(Gc, b0, a1);
+            g[2] = gs(Gc, b1, a0);
+            g[3] = gs(Gc, b1, a1);
+            rot_block(jb.x, jb.y, ja.x, ja.y, g, nv);
+            apq = rb ? (ra ? nv[3] : nv[2]) : (ra ? nv[1] : nv[0]);
+          }
           double cr = 1.0, sr = 0.0;
           const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
           if (rot) flag[(isw + (rn == 0)) & 1] = 1;
           csn[nxt][tid] = make_double2(cr, sr);
         }
-#pragma unroll
+  #pragma unroll
         for (int o = 0; o < 2; ++o) {
-          if (own[o]) {
+          if (!cross && own[o]) {
+            int p1, q1, p2, q2;
+            inner_pair(cross, rr, brp[o], W_P2, p1, q1);
+            inner_pair(cross, rr, bcp[o], W_P2, p2, q2);
             const double2 j1 = csn[cur][brp[o]], j2 = csn[cur][bcp[o]];
             double g[4], nv[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) g[k] = Gc[fo[8 * o + k]];
+            g[0] = gs(Gc, p1, p2);
+            g[1] = gs(Gc, p1, q2);
+            g[2] = gs(Gc, q1, p2);
+            g[3] = gs(Gc, q1, q2);
             rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
-            Gn[fo[8 * o + 0]] = nv[0];
-            Gn[fo[8 * o + 4]] = nv[1];
-            if (brp[o] != bcp[o]) Gn[fo[8 * o + 5]] = nv[2];
-            Gn[fo[8 * o + 6]] = nv[3];
+            gs(Gn, p1, p2) = nv[0];
+            gs(Gn, p1, q2) = nv[1];
+            if (brp[o] != bcp[o]) gs(Gn, q1, p2) = nv[2];
+            gs(Gn, q1, q2) = nv[3];
           }
         }
-      } else if (tid < W_NPAIR) {
-        // angles of pair tid of the next round: its members are row ra of
-        // pair ia = (a0, a1) and row rb of pair ib = (b0, b1) of this round
-        int pn, qn, ia, pa, ib, pb;
-        inner_pair(cross, rn, tid, W_P2, pn, qn);
-        inner_slot(cross, rr, pn, W_P2, ia, pa);
-        inner_slot(cross, rr, qn, W_P2, ib, pb);
-        const int ra = pn < pa ? 0 : 1, rb = qn < pb ? 0 : 1;
-        const int a0 = ra ? pa : pn, a1 = ra ? pn : pa;
-        const int b0 = rb ? pb : qn, b1 = rb ? qn : pb;
-        const double2 ja = csn[cur][ia], jb = csn[cur][ib];
-        double g[4], nv[4];
-        g[0] = Gc[wtri(a0, a0)];
-        g[1] = Gc[wtri(a0, a1)];
-        g[2] = g[1];
-        g[3] = Gc[wtri(a1, a1)];
-        rot_block(ja.x, ja.y, ja.x, ja.y, g, nv);
-        const double app = ra ? nv[3] : nv[0];
-        g[0] = Gc[wtri(b0, b0)];
-        g[1] = Gc[wtri(b0, b1)];
-        g[2] = g[1];
-        g[3] = Gc[wtri(b1, b1)];
-        rot_block(jb.x, jb.y, jb.x, jb.y, g, nv);
-        const double aqq = rb ? nv[3] : nv[0];
-        double apq;
-        if (ia < ib) {
-          g[0] = gs(Gc, a0, b0);
-          g[1] = gs(Gc, a0, b1);
-          g[2] = gs(Gc, a1, b0);
-          g[3] = gs(Gc, a1, b1);
-          rot_block(ja.x, ja.y, jb.x, jb.y, g, nv);
-          apq = ra ? (rb ? nv[3] : nv[2]) : (rb ? nv[1] : nv[0]);
-        } else {
-          g[0] = gs(Gc, b0, a0);
-          g[1] = gs(Gc, b0, a1);
-          g[2] = gs(Gc, b1, a0);
-          g[3] = gs(Gc, b1, a1);
-          rot_block(jb.x, jb.y, ja.x, ja.y, g, nv);
-          apq = rb ? (ra ? nv[3] : nv[2]) : (ra ? nv[1] : nv[0]);
+        {
+          for (int item = tid - 64; item >= 0 && item < W_P2 * W_NPAIR;
+               item += RT - 64) {
+            const int row = item / W_NPAIR, cp = item % W_NPAIR;
+            int p, q;
+            inner_pair(false, rr, cp, W_P2, p, q);
+            const double2 jq = csn[cur][cp];
+            const double x = Q[row][p], y = Q[row][q];
+            Q[row][p] = jq.x * x - jq.y * y;
+            Q[row][q] = jq.y * x + jq.x * y;
+          }
         }
-        double cr = 1.0, sr = 0.0;
-        const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
-        if (rot) flag[(isw + (rn == 0)) & 1] = 1;
-        csn[nxt][tid] = make_double2(cr, sr);
+        __syncthreads();
+        if (rr == 0 && tid == 0) flag[(isw + 1) & 1] = 0;
       }
-#pragma unroll
-      for (int o = 0; o < 2; ++o) {
-        if (!cross && own[o]) {
-          int p1, q1, p2, q2;
-          inner_pair(cross, rr, brp[o], W_P2, p1, q1);
-          inner_pair(cross, rr, bcp[o], W_P2, p2, q2);
-          const double2 j1 = csn[cur][brp[o]], j2 = csn[cur][bcp[o]];
-          double g[4], nv[4];
-          g[0] = gs(Gc, p1, p2);
-          g[1] = gs(Gc, p1, q2);
-          g[2] = gs(Gc, q1, p2);
-          g[3] = gs(Gc, q1, q2);
-          rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
-          gs(Gn, p1, p2) = nv[0];
-          gs(Gn, p1, q2) = nv[1];
-          if (brp[o] != bcp[o]) gs(Gn, q1, p2) = nv[2];
-          gs(Gn, q1, q2) = nv[3];
-        }
-      }
-      if (cross) {
-        const double2 jq = csn[cur][qi];
-        const int src = (lane & 32) | ((lane + 1) & 31);
-#pragma unroll
-        for (int mm = 0; mm < 4; ++mm) {
-          const double na = jq.x * qa[mm] - jq.y * qb[mm];
-          const double nb = jq.y * qa[mm] + jq.x * qb[mm];
-          qa[mm] = na;
-          qb[mm] = __shfl(nb, src);
-        }
-      } else {
-        for (int item = tid - 64; item >= 0 && item < W_P2 * W_NPAIR;
-             item += RT - 64) {
-          const int row = item / W_NPAIR, cp = item % W_NPAIR;
-          int p, q;
-          inner_pair(false, rr, cp, W_P2, p, q);
-          const double2 jq = csn[cur][cp];
-          const double x = Q[row][p], y = Q[row][q];
-          Q[row][p] = jq.x * x - jq.y * y;
-          Q[row][q] = jq.y * x + jq.x * y;
-        }
-      }
-      __syncthreads();
-      if (rr == 0 && tid == 0) flag[(isw + 1) & 1] = 0;
+        if (!flag[isw & 1]) break;
     }
-    if (!flag[isw & 1]) break;
   }
   if (cross) {
     // an inner sweep is W_NPAIR shifts: the second column is 32 + i again

@@ -129,11 +129,14 @@ def test_wide_blocks_by_the_width_rule():
     # theta' 540 x 540 in 16 chains.  Under a rule {512 vectors: 16 chains}
     # the rounds take 32-vector blocks (18 of them, the last ragged), each
     # block pair one workgroup, and every chain matches the oracle to the
-    # bars of the 16-wide rounds; the default rule (measured: 540 vectors
-    # take wide blocks from 64 chains on) keeps them 16-wide
+    # bars of the 16-wide rounds; a rule {512 vectors: 32 chains} keeps
+    # them 16-wide, and so does the default (measured: 540 vectors take
+    # wide blocks from 16 chains on) for a batch of 8
     run_case(180, 180, 180, 16, 180, 1e-10, 2, seed=13, wide=True,
              width_rule=[(512, 16)])
-    run_case(180, 180, 180, 16, 180, 1e-10, 1, seed=13, wide=False)
+    run_case(180, 180, 180, 16, 180, 1e-10, 1, seed=13, wide=False,
+             width_rule=[(512, 32)])
+    run_case(180, 180, 180, 8, 180, 1e-10, 1, seed=13, wide=False)
 
 
 def test_width_rule_is_checked():
@@ -152,7 +155,7 @@ def test_width_rule_is_checked():
 
 def test_wide_blocks_follow_the_batch_size(monkeypatch):
     # HMPS_WIDE (read when a context is created): unset, the width rule (by
-    # default 540 vectors take wide blocks from 64 chains on); 1 always (on
+    # default 540 vectors take wide blocks from 16 chains on); 1 always (on
     # the FP64 paths from 512 vectors); 0 never
     run_case(180, 180, 180, 2, 180, 1e-10, 1, seed=13, wide=False)
     monkeypatch.setenv("HMPS_WIDE", "1")
