@@ -138,6 +138,11 @@ __device__ __forceinline__ void rot_block(double c1, double s1, double c2,
   n[3] = s2 * h21 + c2 * h22;
 }
 
+// a compile-time int as a value (the copy of G a cross round reads)
+template <int V> struct IntC {
+  static constexpr int value = V;
+};
+
 constexpr int P2 = 2 * JB;             // vectors in a block pair
 constexpr int NPAIR = JB;              // disjoint pairs per rotation round
 constexpr int NTILE = 3;               // upper Gram tiles: II, IJ, JJ
@@ -237,7 +242,7 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     flag[0] = 0;
     flag[1] = 0;
   }
-  for (int e = tid; e < nrounds * NPAIR; e += RT) {
+  for (int e = tid; !cross && e < nrounds * NPAIR; e += RT) {
     const int rr = e / NPAIR, t = e % NPAIR;
     const int rn = rr + 1 < nrounds ? rr + 1 : 0;
     int pn, qn, ia, pa, ib, pb;
@@ -377,86 +382,213 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
     }
     bcp = brp + k;
   }
-  int gr = 0;                   // rotation rounds done
-  // pairing entry of the current round (angle lanes), read one round ahead
-  uint2 lk2 = tid < NPAIR ? look[0][tid] : make_uint2(0u, 0u);
-  for (int isw = 0; isw < u.inner_sweeps; ++isw) {
-    for (int rr = 0; rr < nrounds; ++rr, ++gr) {
-      const int cur = gr & 1, nxt = cur ^ 1;
-      const int rn = rr + 1 < nrounds ? rr + 1 : 0;
-      double (*Gc)[P2 + 1] = G[cur];
-      double (*Gn)[P2 + 1] = G[nxt];
-      if (tid < NPAIR) {
-        // angles of pair tid of the next round from this round's G: its
-        // members are row ra of pair ia = (a0, a1) and row rb of pair
-        // ib = (b0, b1) of this round
-        const int a0 = lk2.x & 255, a1 = (lk2.x >> 8) & 255;
-        const int b0 = (lk2.x >> 16) & 255, b1 = lk2.x >> 24;
-        const int ia = lk2.y & 255, ib = (lk2.y >> 8) & 255;
-        const int ra = (lk2.y >> 16) & 255, rb = lk2.y >> 24;
-        const double2 ja = csn[cur][ia], jb = csn[cur][ib];
-        double g[4], nv[4];
-        g[0] = Gc[a0][a0]; g[1] = Gc[a0][a1]; g[2] = g[1]; g[3] = Gc[a1][a1];
-        rot_block(ja.x, ja.y, ja.x, ja.y, g, nv);
-        // selects, not indexing: a runtime index would put nv in scratch
-        const double app = ra ? nv[3] : nv[0];
-        g[0] = Gc[b0][b0]; g[1] = Gc[b0][b1]; g[2] = g[1]; g[3] = Gc[b1][b1];
-        rot_block(jb.x, jb.y, jb.x, jb.y, g, nv);
-        const double aqq = rb ? nv[3] : nv[0];
-        // the cross entry as its owner, block (min(ia,ib), max(ia,ib)),
-        // computes it: rows of the smaller pair index first
-        double apq;
-        if (ia < ib) {
-          g[0] = gs(Gc, a0, b0); g[1] = gs(Gc, a0, b1);
-          g[2] = gs(Gc, a1, b0); g[3] = gs(Gc, a1, b1);
-          rot_block(ja.x, ja.y, jb.x, jb.y, g, nv);
-          apq = ra ? (rb ? nv[3] : nv[2]) : (rb ? nv[1] : nv[0]);
-        } else {
-          g[0] = gs(Gc, b0, a0); g[1] = gs(Gc, b0, a1);
-          g[2] = gs(Gc, b1, a0); g[3] = gs(Gc, b1, a1);
-          rot_block(jb.x, jb.y, ja.x, ja.y, g, nv);
-          apq = rb ? (ra ? nv[3] : nv[2]) : (ra ? nv[1] : nv[0]);
-        }
-        double cr = 1.0, sr = 0.0;
-        const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
-        // the angle belongs to the next sweep when rn wraps to 0
-        if (rot) flag[(isw + (rn == 0)) & 1] = 1;
-        csn[nxt][tid] = make_double2(cr, sr);
-        lk2 = look[rn][tid];
-      }
-      if (owner) {
-        int p1, q1, p2, q2;
-        inner_pair(cross, rr, brp, P2, p1, q1);
-        inner_pair(cross, rr, bcp, P2, p2, q2);
-        const double2 j1 = csn[cur][brp], j2 = csn[cur][bcp];
-        double g[4], nv[4];
-        g[0] = gs(Gc, p1, p2); g[1] = gs(Gc, p1, q2);
-        g[2] = gs(Gc, q1, p2); g[3] = gs(Gc, q1, q2);
-        rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
-        gs(Gn, p1, p2) = nv[0];
-        gs(Gn, p1, q2) = nv[1];
-        // a diagonal block holds (p, q) once: its (q, p) element is skipped
-        if (brp != bcp) gs(Gn, q1, p2) = nv[2];
-        gs(Gn, q1, q2) = nv[3];
-      }
-      // Q items go to waves 1-7 (wave 0 carries the angle lanes)
-      for (int item = tid - 64; item >= 0 && item < P2 * NPAIR;
-           item += RT - 64) {
-        const int row = item / NPAIR, cp = item % NPAIR;
-        int p, q;
-        inner_pair(cross, rr, cp, P2, p, q);
-        const double2 jq = csn[cur][cp];
-        const double cq = jq.x, sq = jq.y;
-        const double x = Q[row][p], y = Q[row][q];
-        Q[row][p] = cq * x - sq * y;
-        Q[row][q] = sq * x + cq * y;
-      }
-      __syncthreads();
-      // the flag of sweep isw + 1 is cleared once every thread has read it
-      // as the flag of sweep isw - 1
-      if (rr == 0 && tid == 0) flag[(isw + 1) & 1] = 0;
+  // Cross rounds relabel the second block after every round: the vector
+  // at label 16 + a moves to label 16 + (a - 1) mod 16 in the next round's
+  // copy of G.  Pair i is then (i, 16 + i) in every round, so every G
+  // offset of the angle lanes and the owners is fixed (bytes from the
+  // start of a copy, computed here once).  The values, and the order of
+  // the operations on them, are those of the pairing (i, 16 + (i + rr)
+  // mod 16) on fixed labels; after a full inner sweep (16 rounds) the
+  // labels are the original ones again.  Q keeps the original labels.
+  //   owners: the four entries read (rows (rp, 16 + rp), columns (cp,
+  //   16 + cp)) and the three written at new places;
+  //   angle lane i: the next round's pair i is (i, 16 + (i + 1) mod 16)
+  //   here, the first member from pair i and the second from pair ip =
+  //   (i + 1) mod 16: both diagonal 2 x 2 blocks and the block between
+  //   them, rows from the lower-numbered pair.
+  int fo[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) fo[k] = 0;
+  bool aswap = false;
+  if (cross) {
+    constexpr int GROW = (P2 + 1) * (int)sizeof(double);
+    auto go = [](int x, int y) {
+      return x <= y ? x * GROW + 8 * y : y * GROW + 8 * x;
+    };
+    if (tid < NPAIR) {
+      const int i = tid, ip = (tid + 1) & (NPAIR - 1);
+      aswap = ip < i;
+      const int ro = aswap ? ip : i, co = aswap ? i : ip;
+      fo[0] = go(i, i);
+      fo[1] = go(i, NPAIR + i);
+      fo[2] = go(NPAIR + i, NPAIR + i);
+      fo[3] = go(ip, ip);
+      fo[4] = go(ip, NPAIR + ip);
+      fo[5] = go(NPAIR + ip, NPAIR + ip);
+      fo[6] = go(ro, co);
+      fo[7] = go(ro, NPAIR + co);
+      fo[8] = go(NPAIR + ro, co);
+      fo[9] = go(NPAIR + ro, NPAIR + co);
     }
-    if (!flag[isw & 1]) break;
+    if (owner) {
+      const int rp = brp, cp = bcp;
+      const int rpm = (rp - 1) & (NPAIR - 1), cpm = (cp - 1) & (NPAIR - 1);
+      fo[0] = go(rp, cp);
+      fo[1] = go(rp, NPAIR + cp);
+      fo[2] = go(cp, NPAIR + rp);
+      fo[3] = go(NPAIR + rp, NPAIR + cp);
+      fo[4] = go(rp, NPAIR + cpm);
+      fo[5] = go(cp, NPAIR + rpm);
+      fo[6] = go(NPAIR + rpm, NPAIR + cpm);
+    }
+  }
+  // one cross round; the copy of G it reads is a constant of each
+  // instantiation, so every G access is a fixed offset from a constant
+  // address (the rounds alternate between the copies, 16 to a sweep)
+  auto cross_round = [&](auto cur_c, int rr, int isw) {
+    constexpr int cur = decltype(cur_c)::value, nxt = cur ^ 1;
+    const int rn = rr + 1 < NPAIR ? rr + 1 : 0;
+    const char *Gc = reinterpret_cast<const char *>(&G[cur][0][0]);
+    char *Gn = reinterpret_cast<char *>(&G[nxt][0][0]);
+    auto gc = [&](int o) -> double {
+      return *reinterpret_cast<const double *>(Gc + o);
+    };
+    auto gn = [&](int o) -> double & {
+      return *reinterpret_cast<double *>(Gn + o);
+    };
+    if (tid < NPAIR) {
+      const double2 ji = csn[cur][tid];
+      const double2 jp = csn[cur][(tid + 1) & (NPAIR - 1)];
+      double g[4], nv[4];
+      g[0] = gc(fo[0]);
+      g[1] = gc(fo[1]);
+      g[2] = g[1];
+      g[3] = gc(fo[2]);
+      rot_block(ji.x, ji.y, ji.x, ji.y, g, nv);
+      const double app = nv[0];
+      g[0] = gc(fo[3]);
+      g[1] = gc(fo[4]);
+      g[2] = g[1];
+      g[3] = gc(fo[5]);
+      rot_block(jp.x, jp.y, jp.x, jp.y, g, nv);
+      const double aqq = nv[3];
+      g[0] = gc(fo[6]);
+      g[1] = gc(fo[7]);
+      g[2] = gc(fo[8]);
+      g[3] = gc(fo[9]);
+      const double2 jr = aswap ? jp : ji, jc = aswap ? ji : jp;
+      rot_block(jr.x, jr.y, jc.x, jc.y, g, nv);
+      const double apq = aswap ? nv[2] : nv[1];
+      double cr = 1.0, sr = 0.0;
+      const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
+      if (rot) flag[(isw + (rn == 0)) & 1] = 1;
+      csn[nxt][tid] = make_double2(cr, sr);
+    }
+    if (owner) {
+      const double2 j1 = csn[cur][brp], j2 = csn[cur][bcp];
+      double g[4], nv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) g[k] = gc(fo[k]);
+      rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
+      gn(fo[0]) = nv[0];
+      gn(fo[4]) = nv[1];
+      // a diagonal block holds (p, q) once: its (q, p) element is skipped
+      if (brp != bcp) gn(fo[5]) = nv[2];
+      gn(fo[6]) = nv[3];
+    }
+    // Q items go to waves 1-7 (wave 0 carries the angle lanes)
+    for (int item = tid - 64; item >= 0 && item < P2 * NPAIR;
+         item += RT - 64) {
+      const int row = item / NPAIR, cp = item % NPAIR;
+      const int p = cp, q = NPAIR + ((cp + rr) & (NPAIR - 1));
+      const double2 jq = csn[cur][cp];
+      const double x = Q[row][p], y = Q[row][q];
+      Q[row][p] = jq.x * x - jq.y * y;
+      Q[row][q] = jq.y * x + jq.x * y;
+    }
+    __syncthreads();
+    if (rr == 0 && tid == 0) flag[(isw + 1) & 1] = 0;
+  };
+  if (cross) {
+    for (int isw = 0; isw < u.inner_sweeps; ++isw) {
+      for (int rr = 0; rr < NPAIR; rr += 2) {
+        cross_round(IntC<0>(), rr, isw);
+        cross_round(IntC<1>(), rr + 1, isw);
+      }
+      if (!flag[isw & 1]) break;
+    }
+  } else {
+    int gr = 0;                   // rotation rounds done
+    // pairing entry of the current round (angle lanes), read one round ahead
+    uint2 lk2 = tid < NPAIR ? look[0][tid] : make_uint2(0u, 0u);
+    for (int isw = 0; isw < u.inner_sweeps; ++isw) {
+      for (int rr = 0; rr < nrounds; ++rr, ++gr) {
+        const int cur = gr & 1, nxt = cur ^ 1;
+        const int rn = rr + 1 < nrounds ? rr + 1 : 0;
+        double (*Gc)[P2 + 1] = G[cur];
+        double (*Gn)[P2 + 1] = G[nxt];
+        if (tid < NPAIR) {
+          // angles of pair tid of the next round from this round's G: its
+          // members are row ra of pair ia = (a0, a1) and row rb of pair
+          // ib = (b0, b1) of this round
+          const int a0 = lk2.x & 255, a1 = (lk2.x >> 8) & 255;
+          const int b0 = (lk2.x >> 16) & 255, b1 = lk2.x >> 24;
+          const int ia = lk2.y & 255, ib = (lk2.y >> 8) & 255;
+          const int ra = (lk2.y >> 16) & 255, rb = lk2.y >> 24;
+          const double2 ja = csn[cur][ia], jb = csn[cur][ib];
+          double g[4], nv[4];
+          g[0] = Gc[a0][a0]; g[1] = Gc[a0][a1]; g[2] = g[1]; g[3] = Gc[a1][a1];
+          rot_block(ja.x, ja.y, ja.x, ja.y, g, nv);
+          // selects, not indexing: a runtime index would put nv in scratch
+          const double app = ra ? nv[3] : nv[0];
+          g[0] = Gc[b0][b0]; g[1] = Gc[b0][b1]; g[2] = g[1]; g[3] = Gc[b1][b1];
+          rot_block(jb.x, jb.y, jb.x, jb.y, g, nv);
+          const double aqq = rb ? nv[3] : nv[0];
+          // the cross entry as its owner, block (min(ia,ib), max(ia,ib)),
+          // computes it: rows of the smaller pair index first
+          double apq;
+          if (ia < ib) {
+            g[0] = gs(Gc, a0, b0); g[1] = gs(Gc, a0, b1);
+            g[2] = gs(Gc, a1, b0); g[3] = gs(Gc, a1, b1);
+            rot_block(ja.x, ja.y, jb.x, jb.y, g, nv);
+            apq = ra ? (rb ? nv[3] : nv[2]) : (rb ? nv[1] : nv[0]);
+          } else {
+            g[0] = gs(Gc, b0, a0); g[1] = gs(Gc, b0, a1);
+            g[2] = gs(Gc, b1, a0); g[3] = gs(Gc, b1, a1);
+            rot_block(jb.x, jb.y, ja.x, ja.y, g, nv);
+            apq = rb ? (ra ? nv[3] : nv[2]) : (ra ? nv[1] : nv[0]);
+          }
+          double cr = 1.0, sr = 0.0;
+          const bool rot = pair_rotation(app, aqq, apq, tol_in, skip, cr, sr);
+          // the angle belongs to the next sweep when rn wraps to 0
+          if (rot) flag[(isw + (rn == 0)) & 1] = 1;
+          csn[nxt][tid] = make_double2(cr, sr);
+          lk2 = look[rn][tid];
+        }
+        if (owner) {
+          int p1, q1, p2, q2;
+          inner_pair(cross, rr, brp, P2, p1, q1);
+          inner_pair(cross, rr, bcp, P2, p2, q2);
+          const double2 j1 = csn[cur][brp], j2 = csn[cur][bcp];
+          double g[4], nv[4];
+          g[0] = gs(Gc, p1, p2); g[1] = gs(Gc, p1, q2);
+          g[2] = gs(Gc, q1, p2); g[3] = gs(Gc, q1, q2);
+          rot_block(j1.x, j1.y, j2.x, j2.y, g, nv);
+          gs(Gn, p1, p2) = nv[0];
+          gs(Gn, p1, q2) = nv[1];
+          // a diagonal block holds (p, q) once: its (q, p) element is skipped
+          if (brp != bcp) gs(Gn, q1, p2) = nv[2];
+          gs(Gn, q1, q2) = nv[3];
+        }
+        // Q items go to waves 1-7 (wave 0 carries the angle lanes)
+        for (int item = tid - 64; item >= 0 && item < P2 * NPAIR;
+             item += RT - 64) {
+          const int row = item / NPAIR, cp = item % NPAIR;
+          int p, q;
+          inner_pair(cross, rr, cp, P2, p, q);
+          const double2 jq = csn[cur][cp];
+          const double cq = jq.x, sq = jq.y;
+          const double x = Q[row][p], y = Q[row][q];
+          Q[row][p] = cq * x - sq * y;
+          Q[row][q] = sq * x + cq * y;
+        }
+        __syncthreads();
+        // the flag of sweep isw + 1 is cleared once every thread has read it
+        // as the flag of sweep isw - 1
+        if (rr == 0 && tid == 0) flag[(isw + 1) & 1] = 0;
+      }
+      if (!flag[isw & 1]) break;
+    }
   }
 
   // ---- 4. Xp <- Xp Q, as D = Q^T Xp^T per 16-row chunk --------------------
@@ -551,10 +683,6 @@ constexpr int W_NBLK = W_NPAIR * (W_NPAIR + 1) / 2;
 constexpr int W_OWN0 = 64;
 constexpr int W_OWNERS = RT - W_OWN0;
 static_assert(W_NBLK <= 2 * W_OWNERS, "two blocks per owner at most");
-
-template <int V> struct IntC {
-  static constexpr int value = V;
-};
 
 // packed upper triangle, i <= j
 __device__ __forceinline__ int wtri(int i, int j) {
