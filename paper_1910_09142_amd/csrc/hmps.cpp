@@ -616,7 +616,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   // that width), max_nb32: the FP32 rounds of the mixed path (16-wide)
   int max_nb = 0, max_nbw = 0, max_nb32 = 2, max_vlen = 1, max_nvec = 1,
       max_qr_n = 0;
-  int max_rr_n = 0, max_rr_l = 0, max_qr2_n = 0;
+  int max_rr_n = 0, max_rr_l = 0, max_qr2_n = 0, max_qr_l = 0;
   double flops = 0.0, svd_flops = 0.0;
   const bool is_move = (op == OP_IDENT);
   // centre moves are exact gauge changes, and hmps_svd_probe (theta' placed
@@ -662,6 +662,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       if (path_has_qr(path)) {
         ++n_qr;
         max_qr_n = std::max(max_qr_n, nvec);
+        max_qr_l = std::max(max_qr_l, vlen);
       }
       if (path_has_qr2(path)) ++n_qr2;
       if (path == PATH_QR2) max_qr2_n = std::max(max_qr2_n, nvec);
@@ -689,8 +690,10 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       // the two-QR path R^T = Q2 R2 the same way, and R2^T into Z
       const int panels = (max_qr_n + QB - 1) / QB;
       for (int stage = 0; stage < (n_qr2 > 0 ? 2 : 1); ++stage) {
+        // rows of the longest matrix this stage factors (R^T: N x N)
+        const int qrows = stage == 0 ? max_qr_l : max_qr_n;
         for (int p = 0; p < panels; ++p) {
-          launch_qr_panel(b, s, u, stage, p, st);
+          launch_qr_panel(b, s, u, stage, p, qrows - QB * p, st);
           launch_qr_update(b, s, u, stage, p, panels - 1 - p, st);
         }
         launch_qr_to_vectors(b, s, u, stage, max_qr_n, st);

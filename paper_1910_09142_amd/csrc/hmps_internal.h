@@ -233,7 +233,7 @@ void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
 // p, the update of its trailing columns (max_tiles 16-column tiles), and
 // the transposed factor into the vector buffer.
 void launch_qr_panel(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                     int stage, int p, hipStream_t st);
+                     int stage, int p, int max_rows, hipStream_t st);
 void launch_qr_update(const Batch &b, const UpdScratch &s, const UpdParams &u,
                       int stage, int p, int max_tiles, hipStream_t st);
 void launch_qr_to_vectors(const Batch &b, const UpdScratch &s,

@@ -194,7 +194,8 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
       const int panels = (N + QB - 1) / QB;
       for (int stage = 0; stage < (path == PATH_QR2 ? 2 : 1); ++stage) {
         for (int p = 0; p < panels; ++p) {
-          launch_qr_panel(b, s, u, stage, p, st);
+          launch_qr_panel(b, s, u, stage, p, (stage == 0 ? L : N) - QB * p,
+                          st);
           launch_qr_update(b, s, u, stage, p, panels - 1 - p, st);
         }
         launch_qr_to_vectors(b, s, u, stage, N, st);

@@ -32,7 +32,8 @@ using namespace dev;
 
 constexpr int PT = 256;   // threads of the update and transpose kernels
 constexpr int QPT = 512;  // threads of the panel kernel (8 wavefronts)
-// panel rows per thread of the panel kernel
+// panel rows per thread of the panel kernel, at most (a launch takes the
+// fewest that hold its longest panel)
 constexpr int RPT = (QR_MAX_L + QPT - 1) / QPT;
 
 // The matrix a stage factors (column-major, stride ld, L x N) and where
@@ -104,16 +105,18 @@ __device__ __forceinline__ double wave_sum16(double (&v)[16]) {
 // alpha = x_0, beta = -sign(alpha) ||x||, v = (x - beta e_0) / (alpha -
 // beta) (so v_0 = 1), tau = (beta - alpha) / beta, and (I - tau v v^T) x =
 // beta e_0.  R_jj = beta; v_1.. are stored below the diagonal.
-// Thread i holds panel rows i, i + 512, i + 1024 of all 16 columns in
-// registers.  One reduction per column gives every product the column
+// Thread i holds panel rows i, i + 512, .. (R of them, the fewest that
+// hold the launch's longest panel) of all 16 columns in registers.  One reduction per column gives every product the column
 // needs: d_q = x^T y_q over rows t.. with y_q the later panel columns
 // (q > t), the earlier reflectors (q < t) and x itself (q = t, ||x||^2).
 // Since v = (x - beta e_0) / (alpha - beta), v^T y_q = (d_q - beta y_q[t])
 // / (alpha - beta); sign(-beta) = sign(alpha), so nothing cancels.  These
-// reflect the later columns, a_q -= tau v (v^T a_q), and build T column by
-// column: T[0:t, t] = -tau T[0:t, 0:t] (V[:, 0:t]^T v_t), T[t][t] = tau.
-// The eight wavefront partials are summed in a fixed order.
+// reflect the later columns, a_q -= tau v (v^T a_q), and, kept for the
+// earlier reflectors, give T once the panel is done: T[0:t, t] = -tau
+// T[0:t, 0:t] (V[:, 0:t]^T v_t), T[t][t] = tau.  The eight wavefront
+// partials are summed in a fixed order.
 // =====================================================================
+template <int R>
 __global__ void __launch_bounds__(QPT) k_qr_panel(Batch b, UpdScratch s,
                                                   UpdParams u, int stage,
                                                   int p) {
@@ -127,12 +130,20 @@ __global__ void __launch_bounds__(QPT) k_qr_panel(Batch b, UpdScratch s,
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   __shared__ double red[(QPT / 64) * QB];
   __shared__ double dots[QB];
-  __shared__ double yt[QB];  // row t of the panel (the y_q[t])
-  __shared__ double T[QB][QB + 1];
-  double a[RPT][QB];
+  __shared__ double yt[QB];        // row t of the panel (the y_q[t])
+  __shared__ double VV[QB][QB + 1];  // VV[t][q] = v_t^T y_q, panel order
+  __shared__ double taus[QB];
+  // The columns are taken in four groups of four.  The registers hold the
+  // groups in a rotating order: in quarter k, register group g holds panel
+  // columns 4 ((k + g) mod 4) .. + 3, so the current group is always
+  // group 0 and every register index is a constant, while the loop over
+  // the quarters stays a loop (a fully unrolled panel is too long for the
+  // instruction cache).  After the fourth rotation the order is the
+  // panel's again.
+  double a[R][QB];
   // loads with clamped addresses and a select (no branch around a load)
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
+  for (int i = 0; i < R; ++i) {
     const int r = tid + QPT * i;
     const int rr = r < rows ? r : rows - 1;
 #pragma unroll
@@ -142,71 +153,92 @@ __global__ void __launch_bounds__(QPT) k_qr_panel(Batch b, UpdScratch s,
       a[i][q] = (r < rows && q < w) ? x : 0.0;
     }
   }
-  if (tid < QB * QB) T[tid / QB][tid % QB] = 0.0;
-  // fully unrolled: every register index is a constant (w is uniform, so
-  // every thread takes the same branches and reaches the same barriers)
+  static_assert(QB == 16, "four groups of four columns");
+#pragma unroll 1
+  for (int k = 0; k < 4; ++k) {
 #pragma unroll
-  for (int t = 0; t < QB; ++t) {
-    if (t < w) {
-      // row t is row 0 of thread t
-      if (tid == t) {
+    for (int tl = 0; tl < 4; ++tl) {
+      const int t = 4 * k + tl;  // panel column, in register slot tl
+      if (t < w) {               // uniform: every thread takes it
+        if (tid == t) {
 #pragma unroll
-        for (int q = 0; q < QB; ++q) yt[q] = a[0][q];
+          for (int q = 0; q < QB; ++q) yt[q] = a[0][q];
+        }
+        double acc[QB];
+#pragma unroll
+        for (int q = 0; q < QB; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int r = tid + QPT * i;
+          const double x = r >= t ? a[i][tl] : 0.0;
+#pragma unroll
+          for (int q = 0; q < QB; ++q) acc[q] = fma(x, a[i][q], acc[q]);
+        }
+        const double part = wave_sum16(acc);  // value lane >> 2
+        if ((lane & 3) == 0) red[wv * QB + (lane >> 2)] = part;
+        __syncthreads();
+        if (tid < QB) {
+          const double *rq = red + tid;
+          dots[tid] = ((rq[0] + rq[QB]) + (rq[2 * QB] + rq[3 * QB])) +
+                      ((rq[4 * QB] + rq[5 * QB]) + (rq[6 * QB] + rq[7 * QB]));
+        }
+        __syncthreads();
+        const double s2 = dots[tl];
+        const double alpha = yt[tl];
+        double tau = 0.0, scale = 0.0, beta = alpha;
+        if (s2 > 0.0) {
+          beta = -copysign(sqrt(s2), alpha);
+          tau = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        // v^T y_q; with x = 0 the reflector is the identity and v = e_0
+        double vy[QB];
+#pragma unroll
+        for (int q = 0; q < QB; ++q)
+          vy[q] = s2 > 0.0 ? scale * (dots[q] - beta * yt[q]) : yt[q];
+        // the later columns: the rest of this group, and the groups that
+        // hold columns after this quarter's (v_r = 0 above row t leaves
+        // those rows unchanged)
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int r = tid + QPT * i;
+          const double vr = r == t ? 1.0 : (r > t ? a[i][tl] * scale : 0.0);
+          const double f = -tau * vr;
+#pragma unroll
+          for (int q = tl + 1; q < 4; ++q) a[i][q] = fma(f, vy[q], a[i][q]);
+#pragma unroll
+          for (int g = 1; g < 4; ++g) {
+            if (k + g < 4) {
+#pragma unroll
+              for (int q = 4 * g; q < 4 * g + 4; ++q)
+                a[i][q] = fma(f, vy[q], a[i][q]);
+            }
+          }
+          a[i][tl] = r == t ? beta : (r > t ? vr : a[i][tl]);
+        }
+        if (tid == 0) {
+          taus[t] = tau;
+#pragma unroll
+          for (int q = 0; q < QB; ++q)
+            VV[t][4 * ((k + (q >> 2)) & 3) + (q & 3)] = vy[q];
+        }
+        __syncthreads();
       }
-      double acc[QB];
+    }
+    // rotate the register groups: group g <- group g + 1
 #pragma unroll
-      for (int q = 0; q < QB; ++q) acc[q] = 0.0;
+    for (int i = 0; i < R; ++i) {
+      double h[4];
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int r = tid + QPT * i;
-        const double x = r >= t ? a[i][t] : 0.0;
+      for (int q = 0; q < 4; ++q) h[q] = a[i][q];
 #pragma unroll
-        for (int q = 0; q < QB; ++q) acc[q] = fma(x, a[i][q], acc[q]);
-      }
-      const double part = wave_sum16(acc);  // value lane >> 2
-      if ((lane & 3) == 0) red[wv * QB + (lane >> 2)] = part;
-      __syncthreads();
-      if (tid < QB) {
-        const double *rq = red + tid;
-        dots[tid] = ((rq[0] + rq[QB]) + (rq[2 * QB] + rq[3 * QB])) +
-                    ((rq[4 * QB] + rq[5 * QB]) + (rq[6 * QB] + rq[7 * QB]));
-      }
-      __syncthreads();
-      const double s2 = dots[t];
-      const double alpha = yt[t];
-      double tau = 0.0, scale = 0.0, beta = alpha;
-      if (s2 > 0.0) {
-        beta = -copysign(sqrt(s2), alpha);
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      // v^T y_q; with x = 0 the reflector is the identity and v = e_0
-      double vy[QB];
+      for (int q = 0; q < QB - 4; ++q) a[i][q] = a[i][q + 4];
 #pragma unroll
-      for (int q = 0; q < QB; ++q)
-        vy[q] = s2 > 0.0 ? scale * (dots[q] - beta * yt[q]) : yt[q];
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) {
-        const int r = tid + QPT * i;
-        const double vr = r == t ? 1.0 : (r > t ? a[i][t] * scale : 0.0);
-#pragma unroll
-        for (int q = t + 1; q < QB; ++q)
-          a[i][q] = r >= t ? fma(-tau * vr, vy[q], a[i][q]) : a[i][q];
-        a[i][t] = r == t ? beta : (r > t ? vr : a[i][t]);
-      }
-      // T column t, row i by thread i (T[i][q] of the earlier columns)
-      if (tid < t) {
-        double x = 0.0;
-#pragma unroll
-        for (int q = 0; q < t; ++q) x += q >= tid ? T[tid][q] * vy[q] : 0.0;
-        T[tid][t] = -tau * x;
-      }
-      if (tid == t) T[t][t] = tau;
-      __syncthreads();
+      for (int q = 0; q < 4; ++q) a[i][QB - 4 + q] = h[q];
     }
   }
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
+  for (int i = 0; i < R; ++i) {
     const int r = tid + QPT * i;
     if (r < rows) {
 #pragma unroll
@@ -214,7 +246,30 @@ __global__ void __launch_bounds__(QPT) k_qr_panel(Batch b, UpdScratch s,
         if (q < w) M[(size_t)(j0 + q) * d.ld + j0 + r] = a[i][q];
     }
   }
-  if (tid < QB * QB) qrT_slot(s, c, stage, p)[tid] = T[tid / QB][tid % QB];
+  // T (H_1 ... H_w = I - V T V^T), row i by thread i: T[i][i] = tau_i and
+  // T[i][t] = -tau_t sum_q T[i][q] (v_q^T v_t) for t > i; the sum runs
+  // over every earlier q, the entries left of the diagonal being zero
+  if (tid < QB) {
+    double Tr[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) Tr[q] = 0.0;
+#pragma unroll
+    for (int t = 0; t < QB; ++t) {
+      if (t < w) {
+        if (t == tid) {
+          Tr[t] = taus[t];
+        } else if (t > tid) {
+          double x = 0.0;
+#pragma unroll
+          for (int q = 0; q < t; ++q) x += Tr[q] * VV[t][q];
+          Tr[t] = -taus[t] * x;
+        }
+      }
+    }
+    double *Tout = qrT_slot(s, c, stage, p) + tid * QB;
+#pragma unroll
+    for (int q = 0; q < QB; ++q) Tout[q] = Tr[q];
+  }
 }
 
 // =====================================================================
@@ -354,9 +409,18 @@ __global__ void __launch_bounds__(PT) k_qr_to_vectors(Batch b, UpdScratch s,
 }  // namespace
 
 void launch_qr_panel(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                     int stage, int p, hipStream_t st) {
-  hipLaunchKernelGGL(k_qr_panel, dim3(b.B), dim3(QPT), 0, st, b, s, u, stage,
-                     p);
+                     int stage, int p, int max_rows, hipStream_t st) {
+  // every chain's panel rows fit R rows per thread
+  static_assert(RPT == 3, "panel variants for 1 .. 3 rows per thread");
+  if (max_rows <= QPT)
+    hipLaunchKernelGGL(k_qr_panel<1>, dim3(b.B), dim3(QPT), 0, st, b, s, u,
+                       stage, p);
+  else if (max_rows <= 2 * QPT)
+    hipLaunchKernelGGL(k_qr_panel<2>, dim3(b.B), dim3(QPT), 0, st, b, s, u,
+                       stage, p);
+  else
+    hipLaunchKernelGGL(k_qr_panel<3>, dim3(b.B), dim3(QPT), 0, st, b, s, u,
+                       stage, p);
 }
 
 void launch_qr_update(const Batch &b, const UpdScratch &s, const UpdParams &u,
