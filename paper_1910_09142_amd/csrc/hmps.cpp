@@ -617,6 +617,9 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
   int max_nb = 0, max_nbw = 0, max_nb32 = 2, max_vlen = 1, max_nvec = 1,
       max_qr_n = 0;
   int max_rr_n = 0, max_rr_l = 0, max_qr2_n = 0, max_qr_l = 0;
+  // longest vector of the 16-wide FP64 rounds (R^T, R2^T, the Ritz basis
+  // projection or theta' itself)
+  int max_len16 = 0;
   double flops = 0.0, svd_flops = 0.0;
   const bool is_move = (op == OP_IDENT);
   // centre moves are exact gauge changes, and hmps_svd_probe (theta' placed
@@ -654,10 +657,13 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
         max_nb32 = std::max(max_nb32, n_blocks_even(nvec, JB));
         max_nb = std::max(max_nb,
                           n_blocks_even(rr_vectors(nvec, chi_max), JB));
+        max_len16 = std::max(max_len16, path == PATH_RR2 ? nvec : vlen);
       } else if (round_width(path, nvec, wide) == JBW) {
         max_nbw = std::max(max_nbw, n_blocks_even(nvec, JBW));
       } else {
         max_nb = std::max(max_nb, n_blocks_even(nvec, JB));
+        max_len16 = std::max(max_len16,
+                             path == PATH_QR || path == PATH_QR2 ? nvec : vlen);
       }
       if (path_has_qr(path)) {
         ++n_qr;
@@ -715,7 +721,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
           if (f32)
             launch_jacobi_round32(b, s, u, r, nb_max / 2, st);
           else
-            launch_jacobi_round(b, s, u, r, nb_max / 2, st);
+            launch_jacobi_round(b, s, u, r, nb_max / 2, max_len16, st);
         }
         ctx->stats.round_launches += std::max(0, nb_max - 1);
         // the chains on wide blocks: half the rounds per sweep

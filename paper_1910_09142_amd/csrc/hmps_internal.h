@@ -211,9 +211,11 @@ void launch_jacobi_small(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, hipStream_t st);
 void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
                                hipStream_t st);
+// max_len: the longest vector over the chains on these (16-wide FP64)
+// rounds; it and the workgroup count choose the register budget
 void launch_jacobi_round(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, int round, int max_pairs,
-                         hipStream_t st);
+                         int max_len, hipStream_t st);
 void launch_jacobi_round32(const Batch &b, const UpdScratch &s,
                            const UpdParams &u, int round, int max_pairs,
                            hipStream_t st);

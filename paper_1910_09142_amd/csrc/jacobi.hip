@@ -174,8 +174,13 @@ template <> struct Prec<float> {
   static __device__ __forceinline__ int drow(int lk, int e) { return 4 * lk + e; }
 };
 
-template <typename T>
-__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
+// WPE: wavefronts per SIMD the registers are budgeted for.  Four (two
+// workgroups per CU) hold the rotation loop's offsets without spills; six
+// (three workgroups per CU, 80 registers, a few reloads per rotation
+// chunk) pay off for short vectors in launches of more than two
+// workgroups per CU (launch_jacobi_round).
+template <typename T, int WPE>
+__global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(WPE)))
     k_jacobi_round(Batch b, UpdScratch s, UpdParams u, int r) {
   typedef Prec<T> PR;
   typedef typename PR::V V;
@@ -1154,9 +1159,17 @@ void launch_jacobi_sweep_begin(const UpdScratch &s, int B, int sweep,
 
 void launch_jacobi_round(const Batch &b, const UpdScratch &s,
                          const UpdParams &u, int round, int max_pairs,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_round<double>, dim3(max_pairs, b.B), dim3(RT), 0,
-                     st, b, s, u, round);
+                         int max_len, hipStream_t st) {
+  // measured at 64 chains: three workgroups per CU win 7% on theta' of
+  // 384 vectors (768 workgroups: one wave of them instead of one and a
+  // half) and lose 5% on 768 (the rotation loop's reloads); at one chain
+  // occupancy does not matter and the reloads cost 5%
+  if (max_len <= 512 && max_pairs * b.B > 2 * 256)
+    hipLaunchKernelGGL((k_jacobi_round<double, 6>), dim3(max_pairs, b.B),
+                       dim3(RT), 0, st, b, s, u, round);
+  else
+    hipLaunchKernelGGL((k_jacobi_round<double, 4>), dim3(max_pairs, b.B),
+                       dim3(RT), 0, st, b, s, u, round);
 }
 
 void launch_jacobi_round_wide(const Batch &b, const UpdScratch &s,
@@ -1169,8 +1182,8 @@ void launch_jacobi_round_wide(const Batch &b, const UpdScratch &s,
 void launch_jacobi_round32(const Batch &b, const UpdScratch &s,
                            const UpdParams &u, int round, int max_pairs,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_round<float>, dim3(max_pairs, b.B), dim3(RT), 0,
-                     st, b, s, u, round);
+  hipLaunchKernelGGL((k_jacobi_round<float, 4>), dim3(max_pairs, b.B),
+                     dim3(RT), 0, st, b, s, u, round);
 }
 
 }  // namespace hmps

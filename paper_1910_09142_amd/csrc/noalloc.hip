@@ -206,7 +206,8 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
     const int nb = n_blocks_even(N, JB);
     for (int sw = 0; sw < u.max_sweeps; ++sw) {
       launch_jacobi_sweep_begin(s, 1, sw, st);
-      for (int r = 0; r < nb - 1; ++r) launch_jacobi_round(b, s, u, r, nb / 2, st);
+      for (int r = 0; r < nb - 1; ++r)
+        launch_jacobi_round(b, s, u, r, nb / 2, path_has_qr(path) ? N : L, st);
     }
     launch_jacobi_sweep_begin(s, 1, u.max_sweeps, st);
   }
