@@ -189,6 +189,30 @@ def test_wide_batch_is_bit_identical_to_single_chains(monkeypatch):
     ctx.hmps_destroy()
 
 
+def test_short_rounds_in_a_large_batch_are_bit_identical_to_single_chains():
+    # theta' 384 x 384 (two-QR path, R2^T of 384 rows) in 64 chains: 768
+    # workgroups per round, so the 16-wide FP64 rounds take the register
+    # budget of three workgroups per CU; alone, a chain's 12 workgroups take
+    # the two-per-CU budget.  Both run the same arithmetic: same bits
+    chi, n = 128, 64
+    center, right = workloads.bond_tensors(23, n, chi, chi, chi)
+    ctx = hmps.Context(n, 2, chi, 1)
+    ctx.hmps_load_bond(center, right)
+    ctx.hmps_apply_gate(1.0, 0.025, chi, 1e-10)
+    assert ctx.hmps_stats().wide_launches == 0
+    picks = (0, 31, 63)
+    batch = [(ctx.hmps_read_site(c, 0), ctx.hmps_read_site(c, 1))
+             for c in picks]
+    ctx.hmps_destroy()
+    ctx = hmps.Context(1, 2, chi, 1)
+    for i, c in enumerate(picks):
+        ctx.hmps_load_bond(center[c:c + 1], right[c:c + 1])
+        ctx.hmps_apply_gate(1.0, 0.025, chi, 1e-10)
+        assert np.array_equal(ctx.hmps_read_site(0, 0), batch[i][0]), c
+        assert np.array_equal(ctx.hmps_read_site(0, 1), batch[i][1]), c
+    ctx.hmps_destroy()
+
+
 def test_mixed_precision_bond():
     run_case(64, 64, 64, 2, 64, 1e-10, 2, precision=hmps.PREC_MIXED_FP32,
              tol_state=5e-6, tol_logw=1e-6)
