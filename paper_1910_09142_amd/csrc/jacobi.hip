@@ -17,7 +17,8 @@
 //   3. one cyclic two-sided Jacobi sweep on the upper triangle of G in LDS,
 //      rotations accumulated in Q, one barrier per rotation round (all
 //      pairs in the first round of a sweep, the pairs across the two blocks
-//      afterwards);
+//      afterwards, with the second block relabelled after every rotation
+//      round so that their LDS offsets stay fixed);
 //   4. Xp <- Xp Q (FP64 MFMA, 16-row chunks over eight wavefronts, loads
 //      of the next chunk in flight, coalesced stores).
 #include "device_common.h"
@@ -223,7 +224,8 @@ __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(WPE)))
   __shared__ double2 csn[2][NPAIR];  // (c, s) of every pair of a round
   __shared__ int flag[2];
   // per rotation round rr and pair t of round rr + 1: where that pair's
-  // three Gram entries sit in round rr (see step 3), packed as bytes
+  // three Gram entries sit in round rr (see step 3), packed as bytes; built
+  // for the all-pairs rounds only (the cross rounds use fixed offsets)
   __shared__ uint2 look[P2 - 1][NPAIR];
   // The first round of every outer sweep diagonalises the whole block pair
   // (all pairs, so the pairs inside each block are rotated once per
