@@ -17,9 +17,11 @@
 // (stage 1) after the first QR of the vector matrix in X (stage 0).
 //
 //   k_qr_panel      Householder reflectors of one 16-column panel, the
-//                   panel rows held in registers; the compact-WY factor T
-//                   with H_1 ... H_16 = I - V T V^T (T column by column,
-//                   as in LAPACK's dlarft)
+//                   panel rows held in registers (1 to 3 per thread), the
+//                   columns in a loop over four groups of four; the
+//                   compact-WY factor T with H_1 ... H_16 = I - V T V^T
+//                   from the kept products once the panel is done (as in
+//                   LAPACK's dlarft)
 //   k_qr_update     trailing columns C <- C - V T^T (V^T C) on the FP64
 //                   matrix cores, one 16-column tile per workgroup
 //   k_qr_to_vectors R^T into the vector buffer (Y, or Z after stage 1),
