@@ -176,6 +176,10 @@ def svd_roofline(tag, s0, s1, use_traffic):
     svd_f = s1.svd_flops - s0.svd_flops
     svd_b = s1.svd_bytes - s0.svd_bytes
     achieved = (svd_f / svd_s / 1e12) if svd_s > 0 else 0.0
+    # a launch is one round over all chains; a split round is two
+    # concurrent dispatches (the two halves of the chains, two streams),
+    # and its time is the span of both
+    split = s1.split_launches - s0.split_launches
     return {
         "bound": "mfma", "achieved": achieved,
         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -183,6 +187,9 @@ def svd_roofline(tag, s0, s1, use_traffic):
         "traffic": measured_traffic(kernel, tag) if use_traffic else None,
         "kernel": kernel,
         "launches": launches,
+        "dispatches_per_launch": (2 if split == launches else
+                                  1 if split == 0 else
+                                  1 + split / launches) if launches else None,
         "avg_launch_us": 1e6 * svd_s / launches if launches else None,
         "flops_per_launch": svd_f / launches if launches else None,
         "algo_bytes_per_launch": svd_b / launches if launches else None,

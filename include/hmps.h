@@ -169,6 +169,10 @@ typedef struct {
   int64_t wide_launches;    /* of round_launches, rounds of 32-vector
                                blocks (updates with >= 512 vectors)      */
   int64_t u1_blocks;        /* HMPS_SYM_U1: charge blocks decomposed     */
+  int64_t split_launches;   /* of wide_launches, rounds issued as two
+                               concurrent dispatches (the two halves of
+                               the chains, on two streams; batches of 16
+                               chains and more)                          */
 } hmps_stats_t;
 
 /* Bytes of device workspace needed for the given capacities. */

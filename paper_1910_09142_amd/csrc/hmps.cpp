@@ -345,6 +345,12 @@ struct hmps_ctx {
   int32_t *h_stage = nullptr;  // 4 * max_chains
   hipEvent_t sweep_ev[2] = {nullptr, nullptr};
   hipEvent_t svd_ev[2] = {nullptr, nullptr};  // timed span of the rounds
+  // the wide rounds of the second half of the chains run on stream2, so
+  // that one half's launches fill the compute units the other half's
+  // last workgroups leave idle (HMPS_SPLIT=0: one stream)
+  hipStream_t stream2 = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  int split = 1;
 };
 
 namespace {
@@ -725,9 +731,24 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
         }
         ctx->stats.round_launches += std::max(0, nb_max - 1);
         // the chains on wide blocks: half the rounds per sweep
-        if (!f32 && max_nbw > 0) {
+        if (!f32 && max_nbw > 0 && ctx->split && ctx->stream2 &&
+            ctx->B >= 16) {
+          const int h = ctx->B / 2;
+          HIPCHK(hipEventRecord(ctx->fork_ev, st));
+          HIPCHK(hipStreamWaitEvent(ctx->stream2, ctx->fork_ev, 0));
+          for (int r = 0; r < max_nbw - 1; ++r) {
+            launch_jacobi_round_wide(b, s, u, r, max_nbw / 2, 0, h, st);
+            launch_jacobi_round_wide(b, s, u, r, max_nbw / 2, h,
+                                     ctx->B - h, ctx->stream2);
+          }
+          HIPCHK(hipEventRecord(ctx->join_ev, ctx->stream2));
+          HIPCHK(hipStreamWaitEvent(st, ctx->join_ev, 0));
+          ctx->stats.round_launches += max_nbw - 1;
+          ctx->stats.wide_launches += max_nbw - 1;
+          ctx->stats.split_launches += max_nbw - 1;
+        } else if (!f32 && max_nbw > 0) {
           for (int r = 0; r < max_nbw - 1; ++r)
-            launch_jacobi_round_wide(b, s, u, r, max_nbw / 2, st);
+            launch_jacobi_round_wide(b, s, u, r, max_nbw / 2, 0, ctx->B, st);
           ctx->stats.round_launches += max_nbw - 1;
           ctx->stats.wide_launches += max_nbw - 1;
         }
@@ -1279,6 +1300,7 @@ hmps_status create_ctx(hmps_ctx **out, const hmps_options *opt,
   if (const char *e = std::getenv("HMPS_INNER")) ctx->inner_sweeps = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("HMPS_SKIP")) ctx->skip = std::min(1e-26, std::atof(e));
   if (const char *e = std::getenv("HMPS_CROSS")) ctx->cross_inner = e[0] == '1';
+  if (const char *e = std::getenv("HMPS_SPLIT")) ctx->split = e[0] == '1';
   if (const char *e = std::getenv("HMPS_WIDE"))
     ctx->wide = e[0] == '0' ? 0 : (e[0] == '1' ? 1 : -1);
   if (const char *e = std::getenv("HMPS_QR"))
@@ -1295,6 +1317,12 @@ hmps_status create_ctx(hmps_ctx **out, const hmps_options *opt,
     e = hipEventCreateWithFlags(&ctx->sweep_ev[i], hipEventDisableTiming);
   for (int i = 0; i < 2 && e == hipSuccess; ++i)
     e = hipEventCreate(&ctx->svd_ev[i]);
+  if (e == hipSuccess)
+    e = hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking);
+  if (e == hipSuccess)
+    e = hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess)
+    e = hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming);
   if (e == hipSuccess)
     e = hipHostMalloc((void **)&ctx->h_stage,
                     sizeof(int32_t) * 4 * opt->max_chains);
@@ -1371,6 +1399,12 @@ void hmps_destroy(hmps_ctx *ctx) {
     if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : ctx->svd_ev)
     if (ev) (void)hipEventDestroy(ev);
+  if (ctx->stream2) {
+    (void)hipStreamSynchronize(ctx->stream2);
+    (void)hipStreamDestroy(ctx->stream2);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   delete ctx;
 }
 
@@ -1821,6 +1855,7 @@ hmps_status hmps_stats(hmps_ctx *ctx, hmps_stats_t *out) {
     s.round_launches += b.round_launches;
     s.svd_bytes += b.svd_bytes;
     s.wide_launches += b.wide_launches;
+    s.split_launches += b.split_launches;
     std::vector<int32_t> sw(ctx->max_blocks);
     if (hipMemcpy(sw.data(), ctx->sub->d_sweeps,
                   sizeof(int32_t) * ctx->max_blocks,

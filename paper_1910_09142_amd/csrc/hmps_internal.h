@@ -220,9 +220,10 @@ void launch_jacobi_round32(const Batch &b, const UpdScratch &s,
                            const UpdParams &u, int round, int max_pairs,
                            hipStream_t st);
 // Round `round` of the wide (JBW) blocks of the chains that take them.
+// chains c0 .. c0 + nc - 1 of the batch
 void launch_jacobi_round_wide(const Batch &b, const UpdScratch &s,
                               const UpdParams &u, int round, int max_pairs,
-                              hipStream_t st);
+                              int c0, int nc, hipStream_t st);
 void launch_truncate(const Batch &b, const UpdScratch &s, const UpdParams &u,
                      hipStream_t st);
 // qr2_panels: panels of the largest PATH_QR2 chain (0: none)

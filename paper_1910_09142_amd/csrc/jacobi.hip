@@ -697,8 +697,8 @@ __device__ __forceinline__ int wtri(int i, int j) {
 }
 
 __global__ void __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(4)))
-    k_jacobi_round_wide(Batch b, UpdScratch s, UpdParams u, int r) {
-  const int c = blockIdx.y, pi = blockIdx.x;
+    k_jacobi_round_wide(Batch b, UpdScratch s, UpdParams u, int r, int c0) {
+  const int c = c0 + blockIdx.y, pi = blockIdx.x;
   if (s.done[c]) return;
   const int32_t *chi = chi_row(b, c);
   const int m = 3 * chi[u.k], n = 3 * chi[u.k + 2];
@@ -1176,9 +1176,9 @@ void launch_jacobi_round(const Batch &b, const UpdScratch &s,
 
 void launch_jacobi_round_wide(const Batch &b, const UpdScratch &s,
                               const UpdParams &u, int round, int max_pairs,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_round_wide, dim3(max_pairs, b.B), dim3(RT), 0,
-                     st, b, s, u, round);
+                              int c0, int nc, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_round_wide, dim3(max_pairs, nc), dim3(RT), 0,
+                     st, b, s, u, round, c0);
 }
 
 void launch_jacobi_round32(const Batch &b, const UpdScratch &s,

@@ -80,7 +80,8 @@ class hmps_stats_t(C.Structure):
                 ("round_launches", C.c_int64), ("svd_bytes", C.c_double),
                 ("center", C.c_int64), ("evolve_pos", C.c_int64),
                 ("jacobi_sweeps_fp32", C.c_int64),
-                ("wide_launches", C.c_int64), ("u1_blocks", C.c_int64)]
+                ("wide_launches", C.c_int64), ("u1_blocks", C.c_int64),
+                ("split_launches", C.c_int64)]
 
 
 _lib = None
