@@ -213,6 +213,31 @@ def test_short_rounds_in_a_large_batch_are_bit_identical_to_single_chains():
     ctx.hmps_destroy()
 
 
+def test_wide_rounds_on_two_streams_are_bit_identical_to_one(monkeypatch):
+    # 16 chains of theta' 540 x 540 take wide blocks (default rule) and
+    # issue every round as two dispatches of 8 chains on two streams; with
+    # HMPS_SPLIT=0 one dispatch on one stream: same bits for every chain
+    chi, n = 180, 16
+    center, right = workloads.bond_tensors(29, n, chi, chi, chi)
+    out = {}
+    for split in ("1", "0"):
+        monkeypatch.setenv("HMPS_SPLIT", split)
+        ctx = hmps.Context(n, 2, chi, 1)
+        ctx.hmps_load_bond(center, right)
+        for _ in range(2):
+            ctx.hmps_apply_gate(1.0, 0.025, chi, 1e-10)
+        st = ctx.hmps_stats()
+        assert st.wide_launches > 0
+        assert (st.split_launches == st.wide_launches) == (split == "1")
+        assert (st.split_launches == 0) == (split == "0")
+        out[split] = [(ctx.hmps_read_site(c, 0), ctx.hmps_read_site(c, 1))
+                      for c in range(n)]
+        ctx.hmps_destroy()
+    for c in range(n):
+        assert np.array_equal(out["1"][c][0], out["0"][c][0]), c
+        assert np.array_equal(out["1"][c][1], out["0"][c][1]), c
+
+
 def test_mixed_precision_bond():
     run_case(64, 64, 64, 2, 64, 1e-10, 2, precision=hmps.PREC_MIXED_FP32,
              tol_state=5e-6, tol_logw=1e-6)
