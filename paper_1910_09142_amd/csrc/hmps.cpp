@@ -345,12 +345,13 @@ struct hmps_ctx {
   int32_t *h_stage = nullptr;  // 4 * max_chains
   hipEvent_t sweep_ev[2] = {nullptr, nullptr};
   hipEvent_t svd_ev[2] = {nullptr, nullptr};  // timed span of the rounds
-  // the wide rounds of the second half of the chains run on stream2, so
-  // that one half's launches fill the compute units the other half's
-  // last workgroups leave idle (HMPS_SPLIT=0: one stream)
+  // the second half of the chains runs on stream2 for the wide rounds
+  // (bit 1: one half's launches fill the compute units the other half's
+  // last workgroups leave idle) and the QRs (bit 2: one half's panels run
+  // beside the other half's trailing updates); HMPS_SPLIT=0..3
   hipStream_t stream2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  int split = 1;
+  int split = 3;
 };
 
 namespace {
@@ -701,14 +702,36 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
       // theta' = Q R panel by panel, then R^T into the vector buffer; on
       // the two-QR path R^T = Q2 R2 the same way, and R2^T into Z
       const int panels = (max_qr_n + QB - 1) / QB;
+      // the two halves of a batch of 16 chains or more on two streams: one
+      // half's latency-bound panel runs beside the other half's trailing
+      // update, which is bound by HBM
+      const bool qsplit = (ctx->split & 2) && ctx->stream2 && ctx->B >= 16;
+      const int h = qsplit ? ctx->B / 2 : ctx->B;
+      if (qsplit) {
+        HIPCHK(hipEventRecord(ctx->fork_ev, st));
+        HIPCHK(hipStreamWaitEvent(ctx->stream2, ctx->fork_ev, 0));
+      }
       for (int stage = 0; stage < (n_qr2 > 0 ? 2 : 1); ++stage) {
         // rows of the longest matrix this stage factors (R^T: N x N)
         const int qrows = stage == 0 ? max_qr_l : max_qr_n;
         for (int p = 0; p < panels; ++p) {
-          launch_qr_panel(b, s, u, stage, p, qrows - QB * p, st);
-          launch_qr_update(b, s, u, stage, p, panels - 1 - p, st);
+          launch_qr_panel(b, s, u, stage, p, qrows - QB * p, 0, h, st);
+          launch_qr_update(b, s, u, stage, p, panels - 1 - p, 0, h, st);
+          if (qsplit) {
+            launch_qr_panel(b, s, u, stage, p, qrows - QB * p, h,
+                            ctx->B - h, ctx->stream2);
+            launch_qr_update(b, s, u, stage, p, panels - 1 - p, h,
+                             ctx->B - h, ctx->stream2);
+          }
         }
-        launch_qr_to_vectors(b, s, u, stage, max_qr_n, st);
+        launch_qr_to_vectors(b, s, u, stage, max_qr_n, 0, h, st);
+        if (qsplit)
+          launch_qr_to_vectors(b, s, u, stage, max_qr_n, h, ctx->B - h,
+                               ctx->stream2);
+      }
+      if (qsplit) {
+        HIPCHK(hipEventRecord(ctx->join_ev, ctx->stream2));
+        HIPCHK(hipStreamWaitEvent(st, ctx->join_ev, 0));
       }
       LAUNCHCHK(ctx);
     }
@@ -731,7 +754,7 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
         }
         ctx->stats.round_launches += std::max(0, nb_max - 1);
         // the chains on wide blocks: half the rounds per sweep
-        if (!f32 && max_nbw > 0 && ctx->split && ctx->stream2 &&
+        if (!f32 && max_nbw > 0 && (ctx->split & 1) && ctx->stream2 &&
             ctx->B >= 16) {
           const int h = ctx->B / 2;
           HIPCHK(hipEventRecord(ctx->fork_ev, st));
@@ -1300,7 +1323,8 @@ hmps_status create_ctx(hmps_ctx **out, const hmps_options *opt,
   if (const char *e = std::getenv("HMPS_INNER")) ctx->inner_sweeps = std::max(1, std::atoi(e));
   if (const char *e = std::getenv("HMPS_SKIP")) ctx->skip = std::min(1e-26, std::atof(e));
   if (const char *e = std::getenv("HMPS_CROSS")) ctx->cross_inner = e[0] == '1';
-  if (const char *e = std::getenv("HMPS_SPLIT")) ctx->split = e[0] == '1';
+  if (const char *e = std::getenv("HMPS_SPLIT"))
+    ctx->split = std::max(0, std::min(3, std::atoi(e)));
   if (const char *e = std::getenv("HMPS_WIDE"))
     ctx->wide = e[0] == '0' ? 0 : (e[0] == '1' ? 1 : -1);
   if (const char *e = std::getenv("HMPS_QR"))

@@ -234,14 +234,17 @@ void launch_writeback(const Batch &b, const UpdScratch &s, const UpdParams &u,
 // whose path starts with a QR (the vector matrix in X), R^T into Y.
 // Stage 1: R^T = Q2 R2 on the PATH_QR2 chains (in Y), R2^T into Z.  Panel
 // p, the update of its trailing columns (max_tiles 16-column tiles), and
-// the transposed factor into the vector buffer.
+// the transposed factor into the vector buffer.  Each launch covers the
+// chains cb .. cb + nc - 1 of the batch.
 void launch_qr_panel(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                     int stage, int p, int max_rows, hipStream_t st);
+                     int stage, int p, int max_rows, int cb, int nc,
+                     hipStream_t st);
 void launch_qr_update(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                      int stage, int p, int max_tiles, hipStream_t st);
+                      int stage, int p, int max_tiles, int cb, int nc,
+                      hipStream_t st);
 void launch_qr_to_vectors(const Batch &b, const UpdScratch &s,
-                          const UpdParams &u, int stage, int max_N,
-                          hipStream_t st);
+                          const UpdParams &u, int stage, int max_N, int cb,
+                          int nc, hipStream_t st);
 // The first QR's block reflector of panel p applied to the k unit vectors
 // held in TH of every PATH_QR2 chain (max_tiles 16-column tiles): panels
 // from last to first give Q u~ (the left factor on the two-QR path).

@@ -195,10 +195,10 @@ extern "C" hmps_status hmps_svd_probe_noalloc(
       for (int stage = 0; stage < (path == PATH_QR2 ? 2 : 1); ++stage) {
         for (int p = 0; p < panels; ++p) {
           launch_qr_panel(b, s, u, stage, p, (stage == 0 ? L : N) - QB * p,
-                          st);
-          launch_qr_update(b, s, u, stage, p, panels - 1 - p, st);
+                          0, 1, st);
+          launch_qr_update(b, s, u, stage, p, panels - 1 - p, 0, 1, st);
         }
-        launch_qr_to_vectors(b, s, u, stage, N, st);
+        launch_qr_to_vectors(b, s, u, stage, N, 0, 1, st);
       }
     }
     // a fixed sequence of max_sweeps sweeps: once a sweep rotates nothing

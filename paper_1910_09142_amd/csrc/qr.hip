@@ -121,8 +121,8 @@ __device__ __forceinline__ double wave_sum16(double (&v)[16]) {
 template <int R>
 __global__ void __launch_bounds__(QPT) k_qr_panel(Batch b, UpdScratch s,
                                                   UpdParams u, int stage,
-                                                  int p) {
-  const int c = blockIdx.x;
+                                                  int p, int cb) {
+  const int c = cb + blockIdx.x;
   const QDims d = qdims(b, c, u, s, stage);
   const int j0 = QB * p;
   if (!d.qr || j0 >= d.N) return;
@@ -288,8 +288,8 @@ __global__ void __launch_bounds__(QPT) k_qr_panel(Batch b, UpdScratch s,
 template <bool APPLY>
 __global__ void __launch_bounds__(PT) k_qr_update(Batch b, UpdScratch s,
                                                   UpdParams u, int stage,
-                                                  int p) {
-  const int c = blockIdx.y;
+                                                  int p, int cb) {
+  const int c = cb + blockIdx.y;
   const QDims d = qdims(b, c, u, s, stage);
   const int j0 = QB * p;
   int ncols = d.N, c0 = j0 + QB + QB * blockIdx.x;
@@ -386,8 +386,9 @@ __global__ void __launch_bounds__(PT) k_qr_update(Batch b, UpdScratch s,
 // LDS.
 // =====================================================================
 __global__ void __launch_bounds__(PT) k_qr_to_vectors(Batch b, UpdScratch s,
-                                                      UpdParams u, int stage) {
-  const int c = blockIdx.z;
+                                                      UpdParams u, int stage,
+                                                      int cb) {
+  const int c = cb + blockIdx.z;
   const QDims d = qdims(b, c, u, s, stage);
   if (!d.qr) return;
   const int ldN = vec_ld(d.N);
@@ -411,40 +412,43 @@ __global__ void __launch_bounds__(PT) k_qr_to_vectors(Batch b, UpdScratch s,
 }  // namespace
 
 void launch_qr_panel(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                     int stage, int p, int max_rows, hipStream_t st) {
+                     int stage, int p, int max_rows, int cb, int nc,
+                     hipStream_t st) {
   // every chain's panel rows fit R rows per thread
   static_assert(RPT == 3, "panel variants for 1 .. 3 rows per thread");
   if (max_rows <= QPT)
-    hipLaunchKernelGGL(k_qr_panel<1>, dim3(b.B), dim3(QPT), 0, st, b, s, u,
-                       stage, p);
+    hipLaunchKernelGGL(k_qr_panel<1>, dim3(nc), dim3(QPT), 0, st, b, s, u,
+                       stage, p, cb);
   else if (max_rows <= 2 * QPT)
-    hipLaunchKernelGGL(k_qr_panel<2>, dim3(b.B), dim3(QPT), 0, st, b, s, u,
-                       stage, p);
+    hipLaunchKernelGGL(k_qr_panel<2>, dim3(nc), dim3(QPT), 0, st, b, s, u,
+                       stage, p, cb);
   else
-    hipLaunchKernelGGL(k_qr_panel<3>, dim3(b.B), dim3(QPT), 0, st, b, s, u,
-                       stage, p);
+    hipLaunchKernelGGL(k_qr_panel<3>, dim3(nc), dim3(QPT), 0, st, b, s, u,
+                       stage, p, cb);
 }
 
 void launch_qr_update(const Batch &b, const UpdScratch &s, const UpdParams &u,
-                      int stage, int p, int max_tiles, hipStream_t st) {
+                      int stage, int p, int max_tiles, int cb, int nc,
+                      hipStream_t st) {
   if (max_tiles <= 0) return;
-  hipLaunchKernelGGL(k_qr_update<false>, dim3(max_tiles, b.B), dim3(PT), 0, st,
-                     b, s, u, stage, p);
+  hipLaunchKernelGGL(k_qr_update<false>, dim3(max_tiles, nc), dim3(PT), 0, st,
+                     b, s, u, stage, p, cb);
 }
 
 void launch_qr_apply(const Batch &b, const UpdScratch &s, const UpdParams &u,
                      int p, int max_tiles, hipStream_t st) {
   if (max_tiles <= 0) return;
   hipLaunchKernelGGL(k_qr_update<true>, dim3(max_tiles, b.B), dim3(PT), 0, st,
-                     b, s, u, 0, p);
+                     b, s, u, 0, p, 0);
 }
 
 void launch_qr_to_vectors(const Batch &b, const UpdScratch &s,
-                          const UpdParams &u, int stage, int max_N,
-                          hipStream_t st) {
+                          const UpdParams &u, int stage, int max_N, int cb,
+                          int nc, hipStream_t st) {
   const int npad = npad_vectors(max_N);
-  dim3 grid(npad / 16, vector_stride(max_N) / 16, b.B);
-  hipLaunchKernelGGL(k_qr_to_vectors, grid, dim3(PT), 0, st, b, s, u, stage);
+  dim3 grid(npad / 16, vector_stride(max_N) / 16, nc);
+  hipLaunchKernelGGL(k_qr_to_vectors, grid, dim3(PT), 0, st, b, s, u, stage,
+                     cb);
 }
 
 }  // namespace hmps
