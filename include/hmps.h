@@ -171,8 +171,8 @@ typedef struct {
   int64_t u1_blocks;        /* HMPS_SYM_U1: charge blocks decomposed     */
   int64_t split_launches;   /* of wide_launches, rounds issued as two
                                concurrent dispatches (the two halves of
-                               the chains, on two streams; batches of 16
-                               chains and more)                          */
+                               the chains, on two streams; rounds of more
+                               than 256 workgroups)                      */
 } hmps_stats_t;
 
 /* Bytes of device workspace needed for the given capacities. */

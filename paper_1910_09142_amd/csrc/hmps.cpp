@@ -754,8 +754,12 @@ hmps_status do_update(hmps_ctx *ctx, int k, int op, bool right, int chi_max,
         }
         ctx->stats.round_launches += std::max(0, nb_max - 1);
         // the chains on wide blocks: half the rounds per sweep
+        // split only rounds of more than one workgroup per compute unit:
+        // with fewer, every workgroup has a unit to itself and a second
+        // dispatch per round only adds its launch (measured at 16 chains:
+        // 144 and 192 workgroups lose 13% split, 288 and 384 gain 9-16%)
         if (!f32 && max_nbw > 0 && (ctx->split & 1) && ctx->stream2 &&
-            ctx->B >= 16) {
+            ctx->B >= 2 && (max_nbw / 2) * ctx->B > 256) {
           const int h = ctx->B / 2;
           HIPCHK(hipEventRecord(ctx->fork_ev, st));
           HIPCHK(hipStreamWaitEvent(ctx->stream2, ctx->fork_ev, 0));

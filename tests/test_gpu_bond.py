@@ -214,10 +214,11 @@ def test_short_rounds_in_a_large_batch_are_bit_identical_to_single_chains():
 
 
 def test_wide_rounds_on_two_streams_are_bit_identical_to_one(monkeypatch):
-    # 16 chains of theta' 540 x 540 take wide blocks (default rule) and
-    # issue every round as two dispatches of 8 chains on two streams; with
-    # HMPS_SPLIT=0 one dispatch on one stream: same bits for every chain
-    chi, n = 180, 16
+    # 32 chains of theta' 540 x 540 take wide blocks (default rule) and,
+    # at 9 block pairs each (288 workgroups a round), issue every round as
+    # two dispatches of 16 chains on two streams; with HMPS_SPLIT=0 one
+    # dispatch on one stream: same bits for every chain
+    chi, n = 180, 32
     center, right = workloads.bond_tensors(29, n, chi, chi, chi)
     out = {}
     for split in ("1", "0"):
